@@ -1,0 +1,357 @@
+"""Pins of the oracle against things other than itself (no GPU needed).
+
+Each test checks the oracle against a value the paper prints, a closed form, an
+algebraic invariant, or a brute-force evaluation written independently in
+Python's unbounded integers, so that a dropped term, a wrong sign or index, a
+swapped operand or a wrong representation map fails at least one of them.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import bounds
+from tests.conftest import GOLDEN
+
+B = 1 << 32
+CONFIG_PRIMES = [251, 32749, 65521, 1048573, 67108859, 2147483647, 4294967291]
+
+
+# ----------------------------------------------------------- python brute force
+def _order(g, p):
+    k, v = 1, g % p
+    while v != 1:
+        v = v * g % p
+        k += 1
+    return k
+
+
+def _smallest_generator(p):
+    for g in range(2, p):
+        if _order(g, p) == p - 1:
+            return g
+    raise AssertionError
+
+
+def py_decode(p, rep, v, g=None):
+    v = int(v)
+    if rep == "zpz":
+        return v
+    if rep == "mont":
+        return v * pow(B, -1, p) % p
+    if rep == "fp64":
+        return int(v)
+    if rep == "zech":
+        return 0 if v == 0 else pow(g, v, p)
+    if rep == "centred":
+        return v % p
+    raise AssertionError(rep)
+
+
+def py_encode(p, rep, r, g=None):
+    if rep == "zpz":
+        return r
+    if rep == "mont":
+        return (r * B) % p
+    if rep == "fp64":
+        return float(r)
+    if rep == "zech":
+        if r == 0:
+            return 0
+        for i in range(1, p):
+            if pow(g, i, p) == r:
+                return i
+        raise AssertionError
+    if rep == "centred":
+        return r - p if r > (p - 1) // 2 else r
+    raise AssertionError(rep)
+
+
+def py_dot(p, rep, x, y, g=None):
+    s = sum(py_decode(p, rep, a, g) * py_decode(p, rep, b, g) for a, b in zip(x, y))
+    return py_encode(p, rep, s % p, g)
+
+
+def stored_range(p, rep):
+    """All stored values that are canonical in rep."""
+    if rep in ("zpz", "mont", "fp64"):
+        return list(range(p))
+    if rep == "zech":
+        return list(range(p))  # indices 0..q-1
+    if rep == "centred":
+        h = (p - 1) // 2
+        return list(range(-h, h + 1))
+    raise AssertionError
+
+
+def random_stored(p, rep, n, seed, stream):
+    if rep == "centred":
+        h = (p - 1) // 2
+        return synth.uniform_int(seed, stream, n, 2 * h + 1, lo=-h)
+    return synth.uniform_int(seed, stream, n, p)
+
+
+def reps_for(p):
+    out = ["zpz"]
+    if p % 2:
+        out.append("mont")
+    if p < (1 << 26) + (1 << 25):
+        out.append("fp64")
+    if 2 < p <= 65521:
+        out.append("zech")
+    if 2 < p < 256:
+        out.append("centred")
+    return out
+
+
+# ------------------------------------------------------------------- paper pins
+def test_paper_printed_bounds():
+    with open(os.path.join(GOLDEN, "paper_constants.json")) as f:
+        gold = json.load(f)
+    assert bounds.axpy_max_prime(32, True) == gold["axpy_signed_max_prime"]["m32"]
+    assert bounds.axpy_max_prime(64, True) == gold["axpy_signed_max_prime"]["m64"]
+    assert bounds.axpy_max_prime(32, False) == gold["axpy_unsigned_max_prime"]["m32"]
+    assert bounds.axpy_max_prime(64, False) == gold["axpy_unsigned_max_prime"]["m64"]
+    assert bounds.montgomery_axpy_max_prime(16) == gold["montgomery_axpy_max_prime"]["b16"]
+    assert bounds.montgomery_axpy_max_prime(32) == gold["montgomery_axpy_max_prime"]["b32"]
+    assert bounds.zech_max_prime(32) == gold["zech_index_max_prime_32bit"]["value"]
+    t = gold["zech_table_bytes_2pow26"]
+    assert t["entries"] * t["bytes_per_entry"] == t["megabytes"] << 20
+    e = gold["eq1_no_reduction_length"]
+    lam = bounds.eq1_lambda(e["p"], e["m"])
+    assert abs(lam - e["approx"]) / e["approx"] < 0.005
+    assert lam == 11524604743
+    # The carried residue of the blocked loop does not change this lambda.
+    assert bounds.carried_lambda_int(e["p"], e["m"]) == lam
+    h = gold["hybrid_threshold_n512"]
+    p_ok = bounds.hybrid_max_prime(h["n"], h["m"])
+    # The printed threshold 2897 is the first prime that fails the bound.
+    assert h["n"] * h["printed"] * (h["printed"] - 1) >= (1 << h["m"])
+    assert p_ok < h["printed"] and all(not bounds.is_prime(q) for q in range(p_ok + 1, h["printed"]))
+    z = gold["zech_subtraction_correction_q101"]
+    assert bounds.zech_subtraction_correction_fraction(z["q"]) == z["fraction"]
+    m = gold["zech_mean_ops"]
+    assert sum(m["adds"]) == m["adds_total"] and sum(m["tests"]) == m["tests_total"]
+
+
+def test_bound_sanity_against_definition():
+    for p in CONFIG_PRIMES:
+        lam = bounds.carried_lambda_int(p, 64)
+        assert (p - 1) + lam * (p - 1) ** 2 <= (1 << 64) - 1
+        assert (p - 1) + (lam + 1) * (p - 1) ** 2 > (1 << 64) - 1
+        if p < (1 << 27):
+            lf = bounds.carried_lambda_fp64(p)
+            assert (p - 1) + lf * (p - 1) ** 2 <= 1 << 53 < (p - 1) + (lf + 1) * (p - 1) ** 2
+    assert bounds.carried_lambda_fp64(67108859) == 2
+    assert bounds.carried_lambda_fp64(1048573) == 8192
+    assert bounds.centred_lambda(251, 32) == 137438
+    assert bounds.montgomery_redc_terms(2147483647) == 2
+
+
+# ------------------------------------------------------------ number theory
+def test_primality_and_inverse():
+    small = [n for n in range(2, 2000) if all(n % d for d in range(2, int(n ** 0.5) + 1))]
+    assert [n for n in range(2000) if oracle.is_prime(n)] == small
+    for p in CONFIG_PRIMES:
+        assert oracle.is_prime(p)
+        assert not oracle.is_prime(p + 2) or bounds.is_prime(p + 2)
+        a = 123456789 % p or 1
+        assert a * oracle.inv_mod(a, p) % p == 1
+
+
+def test_primitive_roots_have_full_order():
+    for p in [3, 5, 7, 11, 101, 251, 32749, 65521]:
+        g = oracle.primitive_root(p)
+        assert g == _smallest_generator(p)
+        assert _order(g, p) == p - 1
+    assert oracle.primitive_root(32749) == 2
+    assert oracle.primitive_root(65521) == 17
+
+
+# ---------------------------------------------------------- brute force pins
+@pytest.mark.parametrize("p", [3, 5, 7])
+def test_exhaustive_tiny_fields(p):
+    """Every pair of vectors of length <= 3 over GF(p), every representation."""
+    for rep in reps_for(p):
+        g = _smallest_generator(p) if rep == "zech" else None
+        vals = stored_range(p, rep)
+        for n in range(0, 4):
+            vecs = list(itertools.product(vals, repeat=n))
+            xs, ys, want = [], [], []
+            for x in vecs:
+                for y in vecs:
+                    xs.append(np.array(x))
+                    ys.append(np.array(y))
+                    want.append(py_dot(p, rep, x, y, g))
+            got = oracle.dot_many(p, rep, xs, ys)
+            assert [float(v) if rep == "fp64" else int(v) for v in got] == want, (p, rep, n)
+
+
+@pytest.mark.parametrize("p", CONFIG_PRIMES)
+def test_random_against_bigint(p):
+    for rep in reps_for(p):
+        g = oracle.primitive_root(p) if rep == "zech" else None
+        for k, n in enumerate([1, 2, 3, 17, 1000, 10007]):
+            x = random_stored(p, rep, n, 11, 2 * k)
+            y = random_stored(p, rep, n, 11, 2 * k + 1)
+            if rep == "zech" and n > 1000:
+                continue  # python discrete log search is slow
+            want = py_dot(p, rep, x, y, g)
+            got = oracle.dot(p, rep, x, y)
+            assert (float(got) if rep == "fp64" else int(got)) == want, (p, rep, n)
+
+
+# ---------------------------------------------------------------- closed forms
+def _lengths_around_lambda(p):
+    lam = bounds.carried_lambda_int(p, 64)
+    out = {1, 2, 3, 63, 64, 65, 1000}
+    for L in (lam, bounds.carried_lambda_fp64(p) if p < (1 << 27) else 0):
+        for n in (L - 1, L, L + 1, 2 * L + 1):
+            if 0 < n <= 300000:
+                out.add(n)
+    return sorted(out)
+
+
+@pytest.mark.parametrize("p", CONFIG_PRIMES)
+def test_closed_forms(p):
+    for rep in reps_for(p):
+        if rep == "zech" and p > 70000:
+            continue
+        for n in _lengths_around_lambda(p):
+            i = np.arange(n, dtype=np.uint64)
+            # every product is (p-1)^2 = 1 mod p: the tightest block for Eq. 1
+            full = oracle.encode(p, rep, np.full(n, p - 1, dtype=np.uint64))
+            assert int(oracle.decode(p, rep, [oracle.dot(p, rep, full, full)])[0]) == n % p
+            # sum of i, and sum of i^2 (i mod p is congruent to i)
+            xi = oracle.encode(p, rep, i % p)
+            one = oracle.encode(p, rep, np.ones(n, dtype=np.uint64))
+            s1 = oracle.decode(p, rep, [oracle.dot(p, rep, xi, one)])[0]
+            s2 = oracle.decode(p, rep, [oracle.dot(p, rep, xi, xi)])[0]
+            assert int(s1) == (n * (n - 1) // 2) % p
+            assert int(s2) == ((n - 1) * n * (2 * n - 1) // 6) % p
+
+
+# ----------------------------------------------------------- representations
+def test_montgomery_maps():
+    for p in [3, 40499, 65521]:
+        x = np.arange(p, dtype=np.uint64)
+        enc = oracle.encode(p, "mont", x)
+        assert [int(v) for v in enc] == [(int(v) << 32) % p for v in x]
+        assert np.array_equal(oracle.decode(p, "mont", enc), x)
+    p = 2147483647
+    # 2^31 = 1 mod p, so B = 2^32 = 2 and B^-1 = 2^30 (worked by hand)
+    assert int(oracle.encode(p, "mont", [1])[0]) == 2
+    assert int(oracle.decode(p, "mont", [1])[0]) == 1 << 30
+    x = synth.uniform_int(5, 0, 5000, p).astype(np.uint64)
+    assert np.array_equal(oracle.decode(p, "mont", oracle.encode(p, "mont", x)), x)
+    # dot in Montgomery form = (sum X_i Y_i) * B^-1 mod p
+    X = synth.uniform_int(5, 1, 3000, p)
+    Y = synth.uniform_int(5, 2, 3000, p)
+    closed = sum(int(a) * int(b) for a, b in zip(X, Y)) * (1 << 30) % p
+    assert int(oracle.dot(p, "mont", X, Y)) == closed
+
+
+@pytest.mark.parametrize("p", [3, 7, 101, 251, 32749])
+def test_zech_maps(p):
+    g = oracle.primitive_root(p)
+    vals = np.arange(p, dtype=np.uint64)
+    idx = oracle.encode(p, "zech", vals)
+    assert int(idx[0]) == 0 and int(idx[1]) == p - 1 and int(idx[g]) == 1
+    assert sorted(int(v) for v in idx) == list(range(p))  # a bijection
+    assert np.array_equal(oracle.decode(p, "zech", idx), vals)
+    # decode(i) = g^i by an independent power
+    for i in [1, 2, (p - 1) // 2, p - 2, p - 1]:
+        assert int(oracle.decode(p, "zech", [i])[0]) == pow(g, i, p)
+
+
+def test_cross_representation_agreement():
+    for p in [251, 32749, 65521, 1048573, 67108859, 2147483647, 4294967291]:
+        n = 4099
+        xc = synth.uniform_int(7, 0, n, p).astype(np.uint64)
+        yc = synth.uniform_int(7, 1, n, p).astype(np.uint64)
+        want = int(sum(int(a) * int(b) for a, b in zip(xc, yc)) % p)
+        for rep in reps_for(p):
+            r = oracle.dot(p, rep, oracle.encode(p, rep, xc), oracle.encode(p, rep, yc))
+            assert int(oracle.decode(p, rep, [r])[0]) == want, (p, rep)
+
+
+# --------------------------------------------------------------------- algebra
+@pytest.mark.parametrize("p", [251, 65521, 2147483647])
+def test_algebraic_invariants(p):
+    for rep in reps_for(p):
+        n = 777
+        x = random_stored(p, rep, n, 9, 0)
+        y = random_stored(p, rep, n, 9, 1)
+        z = random_stored(p, rep, n, 9, 2)
+        zero = oracle.encode(p, rep, np.zeros(n, dtype=np.uint64))
+        dec = lambda v: int(oracle.decode(p, rep, [v])[0])  # noqa: E731
+        assert dec(oracle.dot(p, rep, x, zero)) == 0
+        assert oracle.dot(p, rep, x, y) == oracle.dot(p, rep, y, x)
+        for i in [0, 5, n - 1]:
+            e = zero.copy()
+            e[i] = oracle.encode(p, rep, [1])[0]
+            assert oracle.dot(p, rep, x, e) == x[i]
+        # bilinearity: dot(a x + b y, z) = a dot(x,z) + b dot(y,z)
+        a, b = 3 % p, (p - 2)
+        xc, yc = oracle.decode(p, rep, x), oracle.decode(p, rep, y)
+        comb = oracle.encode(p, rep, (xc * a + yc * b) % p if p < (1 << 31) else
+                             np.array([(int(u) * a + int(v) * b) % p for u, v in zip(xc, yc)], dtype=np.uint64))
+        lhs = dec(oracle.dot(p, rep, comb, z))
+        rhs = (a * dec(oracle.dot(p, rep, x, z)) + b * dec(oracle.dot(p, rep, y, z))) % p
+        assert lhs == rhs
+        # concatenation: dot(x||x', y||y') = dot(x,y) + dot(x',y')
+        whole = dec(oracle.dot(p, rep, np.concatenate([x, z]), np.concatenate([y, x])))
+        assert whole == (dec(oracle.dot(p, rep, x, y)) + dec(oracle.dot(p, rep, z, x))) % p
+
+
+def test_noncanonical_inputs_are_rejected():
+    with pytest.raises(ValueError):
+        oracle.dot(65521, "zpz", [65521], [1])
+    with pytest.raises(ValueError):
+        oracle.dot(67108859, "fp64", [0.5], [1.0])
+    with pytest.raises(ValueError):
+        oracle.dot(251, "centred", [126], [1])
+    with pytest.raises(ValueError):
+        oracle.dot(32749, "zech", [32749], [1])
+
+
+# ------------------------------------------------------------- matrix forms
+def _bigint_matmul(p, A, Bm):
+    A = [[int(v) for v in row] for row in A]
+    Bm = [[int(v) for v in row] for row in Bm]
+    K, N = len(Bm), len(Bm[0])
+    return [[sum(r[k] * Bm[k][j] for k in range(K)) % p for j in range(N)] for r in A]
+
+
+@pytest.mark.parametrize("p,rep", [(251, "centred"), (1048573, "fp64"), (65521, "zpz"),
+                                   (2147483647, "mont"), (32749, "zech")])
+def test_gemm_special_cases(p, rep):
+    M, N, K = 7, 5, 9
+    A = random_stored(p, rep, M * K, 4, 0).reshape(M, K)
+    Bm = random_stored(p, rep, K * N, 4, 1).reshape(K, N)
+    C = oracle.gemm(p, rep, A, Bm)
+    Ac, Bc, Cc = (oracle.decode(p, rep, v.ravel()).reshape(v.shape) for v in (A, Bm, C))
+    assert (Cc == np.array(_bigint_matmul(p, Ac, Bc), dtype=np.uint64)).all()
+    # identity
+    I = oracle.encode(p, rep, np.eye(K, dtype=np.uint64).ravel()).reshape(K, K)
+    assert np.array_equal(oracle.gemm(p, rep, A, I), A)
+    # K = 1: outer product
+    col, row = A[:, :1], Bm[:1, :]
+    outer = oracle.gemm(p, rep, col, row)
+    oc = (oracle.decode(p, rep, col.ravel())[:, None].astype(object) *
+          oracle.decode(p, rep, row.ravel())[None, :].astype(object)) % p
+    assert (oracle.decode(p, rep, outer.ravel()).reshape(M, N) == oc.astype(np.uint64)).all()
+    # N = 1 equals gemv, 1x1xK equals dot, entries equal the full product
+    assert np.array_equal(oracle.gemm(p, rep, A, Bm[:, :1]).ravel(), oracle.gemv(p, rep, A, Bm[:, 0]))
+    assert oracle.gemm(p, rep, A[:1], Bm[:, 1:2])[0, 0] == oracle.dot(p, rep, A[0], Bm[:, 1])
+    rows, cols = np.array([0, 3, 6, 6]), np.array([0, 4, 2, 4])
+    assert np.array_equal(oracle.gemm_entries(p, rep, A, Bm, rows, cols), C[rows, cols])
+    # Freivalds with random r: A (B r) = C r mod p
+    for t in range(4):
+        r = synth.uniform_int(40, t, N, p).astype(object)
+        Br = (Bc.astype(object) @ r) % p
+        assert np.array_equal((Ac.astype(object) @ Br) % p, (Cc.astype(object) @ r) % p)
