@@ -1,0 +1,245 @@
+/*
+ * fdot.h -- exact linear algebra over a word-size prime field GF(p) on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operation is the one studied in J.-G. Dumas, "Efficient dot product over
+ * word-size finite fields": the exact dot product of two vectors over GF(p)
+ * (Sec. 1), computed in one of the element representations of Sec. 2, with the
+ * modular reduction delayed as long as the accumulator cannot overflow
+ * (Sec. 3.1 Eq. 1 and the blocked loop of Sec. 3.2), or performed on demand
+ * (Sec. 3.3).  Matrix-vector and matrix-matrix products are the same
+ * contraction per output entry (Sec. 1 names them as the dot product's
+ * users).
+ *
+ * Conventions for every call:
+ *  - All functions are plain C, return fdot_status_t (0 = success, < 0 = error)
+ *    and never throw.
+ *  - "device" pointers are HIP device allocations owned by the caller; the
+ *    library never frees them.  "host" pointers are ordinary host memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Compute calls only enqueue work on it and return; argument errors are
+ *    reported synchronously, launch errors as FDOT_E_DEVICE.
+ *  - Vectors and matrices are dense; matrices are row-major with a leading
+ *    dimension counted in elements.
+ *  - Inputs must be canonical in their representation (below).  The hot path
+ *    does not check this; a non-canonical input gives an unspecified result.
+ *  - Results are written in the input representation and in its canonical
+ *    form, so exactly one bit pattern is correct (the conversions themselves
+ *    are not part of a dot product, Sec. 3).
+ */
+#ifndef FDOT_H
+#define FDOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FDOT_OK = 0,
+  FDOT_E_INVALID_ARG = -1, /* null pointer, bad size, bad enum, misaligned ld */
+  FDOT_E_NOT_PRIME = -2,   /* p is not prime */
+  FDOT_E_BOUND = -3,       /* p outside the representation's bound */
+  FDOT_E_UNSUPPORTED = -4, /* no such form for this representation/algorithm */
+  FDOT_E_DEVICE = -5,      /* a HIP call failed */
+  FDOT_E_NOMEM = -6,       /* device or host allocation failed */
+  FDOT_E_BUSY = -7,        /* queue full / workspace cannot grow now */
+  FDOT_E_NOT_FOUND = -8    /* unknown ticket or key */
+} fdot_status_t;
+
+/* Element representations (Sec. 2).  Storage type and canonical range:
+ *  ZPZ_U32     uint32  a in [0, p), p < 2^32                    (Sec. 2.1)
+ *  MONT_U32    uint32  a*B mod p, B = 2^32, odd p < 2^32         (Sec. 2.2)
+ *  FP64        double  integral a in [0, p), (p-1)^2 <= 2^53    (Sec. 2.3)
+ *  ZECH_U16    uint16  0 -> 0, 1 -> p-1, g^i -> i (1 <= i < p-1)
+ *                      with g the smallest primitive root, p <= 65521
+ *                                                                (Sec. 2.4)
+ *  CENTRED_I8  int8    a in [-(p-1)/2, (p-1)/2], odd p < 256    (Sec. 3.2.2)
+ */
+typedef enum {
+  FDOT_REP_ZPZ_U32 = 0,
+  FDOT_REP_MONT_U32 = 1,
+  FDOT_REP_FP64 = 2,
+  FDOT_REP_ZECH_U16 = 3,
+  FDOT_REP_CENTRED_I8 = 4
+} fdot_rep_t;
+
+/* Accumulation schedules of Sec. 3 (every one returns the same result). */
+typedef enum {
+  FDOT_ALGO_AUTO = 0,        /* the library's (tuned) choice */
+  FDOT_ALGO_DELAYED = 1,     /* Sec. 3.1-3.2: reduce once per block of at most
+                                lambda products (lambda from Eq. 1 with the
+                                carried residue); for MONT_U32 one Montgomery
+                                reduction per block (Sec. 3.2.1) */
+  FDOT_ALGO_PERTERM = 2,     /* Sec. 2.1 AXPY: reduce after every product */
+  FDOT_ALGO_OVERFLOW = 3,    /* Sec. 3.3: let the 64-bit sum wrap, detect the
+                                wrap by t+ab < ab and add CORR = 2^64 mod p;
+                                for MONT_U32 one extra reduction at the end */
+  FDOT_ALGO_ZECH_TPLUS1 = 4, /* Sec. 2.4: products by index addition, sums by
+                                Zech addition through the plus-one table */
+  FDOT_ALGO_ZECH_EXP = 5     /* Sec. 2.4 + 3.1: products by index addition,
+                                then the value table and a delayed integer sum */
+} fdot_algo_t;
+
+/* Accumulator kinds for the bound calculator. */
+typedef enum {
+  FDOT_ACC_U64 = 0,         /* unsigned 64-bit, carried residue  (Eq. 1)       */
+  FDOT_ACC_U32 = 1,         /* unsigned 32-bit, carried residue  (Eq. 1)       */
+  FDOT_ACC_F64 = 2,         /* double: exact integers up to 2^53 (Eq. 1, m=53) */
+  FDOT_ACC_I32_CENTRED = 3, /* signed 32-bit, centred operands   (Sec. 3.2.2)  */
+  FDOT_ACC_F64_CENTRED = 4, /* double, centred operands: |sum| <= 2^53        */
+  FDOT_ACC_MONT_REDC = 5,   /* products summed before one Montgomery reduction
+                               with B = 2^32: sum < p*B          (Sec. 2.2)   */
+  FDOT_ACC_U64_HYBRID = 6   /* Eq. 2 strict: lambda*p*(p-1) < 2^64 (Sec. 3.4) */
+} fdot_acc_t;
+
+/* Prime bounds printed by the paper, for the bound calculator. */
+typedef enum {
+  FDOT_BOUND_AXPY_SIGNED = 0,   /* p(p-1) <= 2^(m-1)-1            (Sec. 2.1) */
+  FDOT_BOUND_AXPY_UNSIGNED = 1, /* p(p-1) <= 2^m-1                (Sec. 2.1) */
+  FDOT_BOUND_MONTGOMERY = 2,    /* (p-1)^2 + p(B-1) < B^2, B=2^m  (Sec. 2.2) */
+  FDOT_BOUND_ZECH_INDEX = 3     /* 2(p-1) <= 2^(m-1)-1            (Sec. 2.4) */
+} fdot_bound_t;
+
+/* Fold primitives (the reductions of Sec. 2), for host-side checks. */
+typedef enum {
+  FDOT_FOLD_REMAINDER = 0, /* T mod p by a precomputed reciprocal (2-by-1
+                              division by an invariant divisor), any T < 2^64 */
+  FDOT_FOLD_REDC = 1,      /* Montgomery: T * 2^-32 mod p, T < p*2^32 (Sec. 2.2) */
+  FDOT_FOLD_FP64 = 2       /* T - floor(T*invP)*P with one +-P correction,
+                              T <= 2^53 (Sec. 2.3) */
+} fdot_fold_t;
+
+/* Constants of a field (all host values). */
+typedef struct {
+  uint64_t p;
+  int32_t rep;               /* fdot_rep_t */
+  uint32_t elem_bytes;       /* storage size of one element */
+  uint64_t lambda_u64;       /* FDOT_ACC_U64 block length */
+  uint64_t lambda_f64;       /* FDOT_ACC_F64 block length (0 if p too large) */
+  uint64_t lambda_i32c;      /* FDOT_ACC_I32_CENTRED block length */
+  uint64_t lambda_redc;      /* FDOT_ACC_MONT_REDC block length (odd p) */
+  uint64_t corr;             /* 2^64 mod p (Sec. 3.3) */
+  uint32_t norm_shift;       /* s with 2^31 <= p*2^s < 2^32 */
+  uint32_t recip;            /* floor((2^64-1)/(p*2^s)) - 2^32 */
+  uint32_t n_im;             /* -p^-1 mod 2^32 (odd p; Sec. 2.2) */
+  uint32_t b_mod_p;          /* 2^32 mod p: Montgomery form of 1 */
+  uint32_t binv_mod_p;       /* 2^-32 mod p (odd p) */
+  uint32_t b2_mod_p;         /* 2^64 mod p */
+  uint32_t g;                /* smallest primitive root (Zech; 0 otherwise) */
+  uint32_t reserved;
+  double inv_p;              /* 1.0/p rounded to nearest */
+  uint64_t table_bytes;      /* device bytes held by the field's tables */
+} fdot_field_info_t;
+
+/* One instance of a batched dot product (device-resident array). */
+typedef struct {
+  const void* x; /* device, n elements of the field's storage type */
+  const void* y; /* device, n elements */
+  uint64_t n;
+} fdot_desc_t;
+
+typedef struct fdot_field_s* fdot_field_t;
+
+/* ------------------------------------------------------------------ host only
+ * These touch no GPU. */
+
+const char* fdot_status_string(int status);
+int fdot_version(void);
+
+/* Validate p for `rep` (prime; within the representation bound of Sec. 2)
+ * and fill every constant of the field; no device tables are built. */
+fdot_status_t fdot_field_params(uint64_t p, fdot_rep_t rep, fdot_field_info_t* out);
+
+/* Largest block length lambda for accumulator `acc` (Sec. 3.1 Eq. 1 with the
+ * residue carried between blocks, Sec. 3.2.2, Sec. 3.4 Eq. 2, Sec. 2.2).
+ * 0 means not even one product fits. */
+fdot_status_t fdot_lambda(uint64_t p, fdot_acc_t acc, uint64_t* lambda);
+
+/* Largest prime below the bound `kind` for word size `bits` (Sec. 2.1, 2.2,
+ * 2.4); bits in [8, 64]. */
+fdot_status_t fdot_max_prime(fdot_bound_t kind, uint32_t bits, uint64_t* p);
+
+/* Evaluate one fold primitive on the host with the field's constants, with
+ * the same code the kernels run.  Returns FDOT_E_INVALID_ARG when T is
+ * outside the primitive's input range. */
+fdot_status_t fdot_host_fold(const fdot_field_info_t* info, fdot_fold_t kind,
+                             uint64_t T, uint64_t* out);
+
+/* The Zech tables for a prime p <= 65521 with the smallest primitive root g
+ * (Sec. 2.4).  Each host array has p entries:
+ *   value[i] = g^i mod p for 1 <= i <= p-1, value[0] = 0 (index 0 codes 0);
+ *   index[v] = Zech code of v (index[0] = 0, index[1] = p-1);
+ *   plus1[k] = h with g^h = 1 + g^k for 1 <= k <= p-1, 0 when 1 + g^k = 0;
+ *              plus1[0] = p-1 (1 + 0 = 1).
+ * Any pointer may be NULL. */
+fdot_status_t fdot_zech_tables(uint64_t p, uint16_t* value, uint16_t* index,
+                               uint16_t* plus1);
+
+/* ----------------------------------------------------------------- fields */
+
+/* Create a field: validates like fdot_field_params, then uploads its device
+ * tables (Zech) to the current device.  The handle is immutable and may be
+ * shared by threads and streams; destroy it once no enqueued work uses it. */
+fdot_status_t fdot_field_create(uint64_t p, fdot_rep_t rep, fdot_field_t* out);
+fdot_status_t fdot_field_destroy(fdot_field_t f);
+fdot_status_t fdot_field_info(fdot_field_t f, fdot_field_info_t* out);
+
+/* Conversions (Sec. 2; untimed by the paper's convention, Sec. 3).
+ * canon: device uint32 residues in [0, p); rep: device storage array. */
+fdot_status_t fdot_encode(fdot_field_t f, const uint32_t* canon, void* rep,
+                          size_t n, void* stream);
+fdot_status_t fdot_decode(fdot_field_t f, const void* rep, uint32_t* canon,
+                          size_t n, void* stream);
+
+/* ------------------------------------------------------------ dot products */
+
+/* result[0] = sum_{i<n} x_i*y_i over GF(p) (Sec. 1, Sec. 3), x, y, result on
+ * the device in the field's representation.  n = 0 gives the encoded zero;
+ * x == y is allowed.  Pointers must be aligned to the element size. */
+fdot_status_t fdot_modp(fdot_field_t f, const void* x, const void* y, size_t n,
+                        void* result, void* stream);
+fdot_status_t fdot_modp_algo(fdot_field_t f, fdot_algo_t algo, const void* x,
+                             const void* y, size_t n, void* result, void* stream);
+
+/* results[k] = dot of desc[k] for k < count, one launch sequence for the whole
+ * batch (uneven lengths allowed).  desc and results are device arrays. */
+fdot_status_t fdot_modp_many(fdot_field_t f, size_t count, const fdot_desc_t* desc,
+                             void* results, void* stream);
+fdot_status_t fdot_modp_many_algo(fdot_field_t f, fdot_algo_t algo, size_t count,
+                                  const fdot_desc_t* desc, void* results, void* stream);
+
+/* ----------------------------------------------------------- matrix forms */
+
+/* y = A x over GF(p): A is m x n row-major (lda >= n), x has n entries, y has
+ * m entries; all on the device in the field's representation. */
+fdot_status_t fgemv_modp(fdot_field_t f, size_t m, size_t n, const void* A,
+                         size_t lda, const void* x, void* y, void* stream);
+
+/* C = A B over GF(p): A M x K (lda >= K), B K x N (ldb >= N), C M x N
+ * (ldc >= N), row-major device arrays in the field's representation.  The
+ * contraction runs on matrix cores when exactness allows it (FP64 when the
+ * field's residues fit an exact double block, int8 for CENTRED_I8), cut into
+ * K-blocks that never exceed the exact range before a mod-p fold. */
+fdot_status_t fgemm_modp(fdot_field_t f, size_t M, size_t N, size_t K, const void* A,
+                         size_t lda, const void* B, size_t ldb, void* C, size_t ldc,
+                         void* stream);
+
+/* ------------------------------------------------------ runtime / tuning */
+
+/* Pre-size the per-stream workspace for batches of up to `count` instances.
+ * Call before capturing a stream into a HIP graph: a capture cannot allocate. */
+fdot_status_t fdot_workspace_reserve(void* stream, size_t count);
+
+/* Tuned launch parameters, keyed by name (e.g. "chunk.zpz", "wg_per_cu.zpz").
+ * Unknown keys give FDOT_E_NOT_FOUND. */
+fdot_status_t fdot_tune_set(const char* key, int64_t value);
+fdot_status_t fdot_tune_get(const char* key, int64_t* value);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDOT_H */

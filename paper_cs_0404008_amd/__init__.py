@@ -1,0 +1,274 @@
+"""Exact dot products and matrix products over GF(p) on MI355X (gfx950).
+
+A thin binding over the C ABI of libfdot.so (include/fdot.h): it passes device
+pointers of torch tensors and the current HIP stream, nothing else.  Every
+step of the computation runs in the library's HIP kernels; there is no host
+fallback, and importing this package fails loudly when the library is
+missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfdot.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it first (python paper_cs_0404008_amd/build.py)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+REPS = {"zpz": 0, "mont": 1, "fp64": 2, "zech": 3, "centred": 4}
+ALGOS = {"auto": 0, "delayed": 1, "perterm": 2, "overflow": 3, "zech_tplus1": 4, "zech_exp": 5}
+ACCS = {"u64": 0, "u32": 1, "f64": 2, "i32_centred": 3, "f64_centred": 4, "mont_redc": 5,
+        "u64_hybrid": 6}
+BOUNDS = {"axpy_signed": 0, "axpy_unsigned": 1, "montgomery": 2, "zech_index": 3}
+FOLDS = {"remainder": 0, "redc": 1, "fp64": 2}
+TORCH_DTYPES = {"zpz": torch.uint32, "mont": torch.uint32, "fp64": torch.float64,
+                "zech": torch.uint16, "centred": torch.int8}
+
+
+class FieldInfo(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_uint64), ("rep", ctypes.c_int32), ("elem_bytes", ctypes.c_uint32),
+                ("lambda_u64", ctypes.c_uint64), ("lambda_f64", ctypes.c_uint64),
+                ("lambda_i32c", ctypes.c_uint64), ("lambda_redc", ctypes.c_uint64),
+                ("corr", ctypes.c_uint64), ("norm_shift", ctypes.c_uint32),
+                ("recip", ctypes.c_uint32), ("n_im", ctypes.c_uint32), ("b_mod_p", ctypes.c_uint32),
+                ("binv_mod_p", ctypes.c_uint32), ("b2_mod_p", ctypes.c_uint32),
+                ("g", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("inv_p", ctypes.c_double),
+                ("table_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+_u64, _sz, _vp, _i32, _i64 = (ctypes.c_uint64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int,
+                             ctypes.c_int64)
+
+
+def _sig(name, args, res=ctypes.c_int):
+    fn = getattr(_lib, name)
+    fn.argtypes = args
+    fn.restype = res
+    return fn
+
+
+_sig("fdot_status_string", [_i32], ctypes.c_char_p)
+_sig("fdot_version", [])
+_sig("fdot_field_params", [_u64, _i32, ctypes.POINTER(FieldInfo)])
+_sig("fdot_lambda", [_u64, _i32, ctypes.POINTER(_u64)])
+_sig("fdot_max_prime", [_i32, ctypes.c_uint32, ctypes.POINTER(_u64)])
+_sig("fdot_host_fold", [ctypes.POINTER(FieldInfo), _i32, _u64, ctypes.POINTER(_u64)])
+_sig("fdot_zech_tables", [_u64, _vp, _vp, _vp])
+_sig("fdot_field_create", [_u64, _i32, ctypes.POINTER(_vp)])
+_sig("fdot_field_destroy", [_vp])
+_sig("fdot_field_info", [_vp, ctypes.POINTER(FieldInfo)])
+_sig("fdot_encode", [_vp, _vp, _vp, _sz, _vp])
+_sig("fdot_decode", [_vp, _vp, _vp, _sz, _vp])
+_sig("fdot_modp", [_vp, _vp, _vp, _sz, _vp, _vp])
+_sig("fdot_modp_algo", [_vp, _i32, _vp, _vp, _sz, _vp, _vp])
+_sig("fdot_modp_many", [_vp, _sz, _vp, _vp, _vp])
+_sig("fdot_modp_many_algo", [_vp, _i32, _sz, _vp, _vp, _vp])
+_sig("fgemv_modp", [_vp, _sz, _sz, _vp, _sz, _vp, _vp, _vp])
+_sig("fgemm_modp", [_vp, _sz, _sz, _sz, _vp, _sz, _vp, _sz, _vp, _sz, _vp])
+_sig("fdot_workspace_reserve", [_vp, _sz])
+_sig("fdot_tune_set", [ctypes.c_char_p, _i64])
+_sig("fdot_tune_get", [ctypes.c_char_p, ctypes.POINTER(_i64)])
+
+
+class FdotError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {_lib.fdot_status_string(status).decode()} ({status})")
+
+
+def _check(status: int, what: str) -> None:
+    if status != 0:
+        raise FdotError(status, what)
+
+
+def lib():
+    return _lib
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ host only
+def status_string(status: int) -> str:
+    return _lib.fdot_status_string(status).decode()
+
+
+def field_params(p: int, rep: str) -> dict:
+    info = FieldInfo()
+    _check(_lib.fdot_field_params(p, REPS[rep], ctypes.byref(info)), "fdot_field_params")
+    return info.as_dict()
+
+
+def field_params_status(p: int, rep: str) -> int:
+    info = FieldInfo()
+    return _lib.fdot_field_params(p, REPS[rep], ctypes.byref(info))
+
+
+def lambda_for(p: int, acc: str) -> int:
+    out = _u64()
+    _check(_lib.fdot_lambda(p, ACCS[acc], ctypes.byref(out)), "fdot_lambda")
+    return out.value
+
+
+def max_prime(kind: str, bits: int) -> int:
+    out = _u64()
+    _check(_lib.fdot_max_prime(BOUNDS[kind], bits, ctypes.byref(out)), "fdot_max_prime")
+    return out.value
+
+
+def host_fold(p: int, rep: str, kind: str, T: int) -> int:
+    info = FieldInfo()
+    _check(_lib.fdot_field_params(p, REPS[rep], ctypes.byref(info)), "fdot_field_params")
+    out = _u64()
+    _check(_lib.fdot_host_fold(ctypes.byref(info), FOLDS[kind], T, ctypes.byref(out)),
+           "fdot_host_fold")
+    return out.value
+
+
+def zech_tables(p: int):
+    import numpy as np
+    val = np.zeros(p, dtype=np.uint16)
+    idx = np.zeros(p, dtype=np.uint16)
+    plus1 = np.zeros(p, dtype=np.uint16)
+    _check(_lib.fdot_zech_tables(p, val.ctypes.data, idx.ctypes.data, plus1.ctypes.data),
+           "fdot_zech_tables")
+    return val, idx, plus1
+
+
+def tune_set(key: str, value: int) -> None:
+    _check(_lib.fdot_tune_set(key.encode(), int(value)), "fdot_tune_set")
+
+
+def tune_get(key: str):
+    out = _i64()
+    st = _lib.fdot_tune_get(key.encode(), ctypes.byref(out))
+    return None if st != 0 else out.value
+
+
+def workspace_reserve(count: int, stream=None) -> None:
+    _check(_lib.fdot_workspace_reserve(_stream(stream), count), "fdot_workspace_reserve")
+
+
+# ---------------------------------------------------------------------- field
+class Field:
+    """GF(p) in one representation; the handle owns the device tables."""
+
+    def __init__(self, p: int, rep: str = "zpz"):
+        self.p = int(p)
+        self.rep = rep
+        h = _vp()
+        _check(_lib.fdot_field_create(self.p, REPS[rep], ctypes.byref(h)), "fdot_field_create")
+        self._h = h
+        info = FieldInfo()
+        _check(_lib.fdot_field_info(h, ctypes.byref(info)), "fdot_field_info")
+        self.info = info.as_dict()
+        self.dtype = TORCH_DTYPES[rep]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.fdot_field_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _need(self, t: torch.Tensor, name: str):
+        if t.dtype != self.dtype or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA tensor of dtype {self.dtype}")
+
+    def encode(self, canon: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        if canon.dtype != torch.uint32 or not canon.is_cuda or not canon.is_contiguous():
+            raise TypeError("canon must be a contiguous CUDA uint32 tensor")
+        if out is None:
+            out = torch.empty(canon.shape, dtype=self.dtype, device=canon.device)
+        _check(_lib.fdot_encode(self._h, _ptr(canon), _ptr(out), canon.numel(), _stream(stream)),
+               "fdot_encode")
+        return out
+
+    def decode(self, rep: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        self._need(rep, "rep")
+        if out is None:
+            out = torch.empty(rep.shape, dtype=torch.uint32, device=rep.device)
+        _check(_lib.fdot_decode(self._h, _ptr(rep), _ptr(out), rep.numel(), _stream(stream)),
+               "fdot_decode")
+        return out
+
+    def dot(self, x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None,
+            algo: str = "auto", stream=None) -> torch.Tensor:
+        self._need(x, "x")
+        self._need(y, "y")
+        if x.numel() != y.numel() or not x.is_contiguous() or not y.is_contiguous():
+            raise ValueError("x and y must be contiguous and of equal length")
+        if out is None:
+            out = torch.empty(1, dtype=self.dtype, device=x.device)
+        _check(_lib.fdot_modp_algo(self._h, ALGOS[algo], _ptr(x), _ptr(y), x.numel(), _ptr(out),
+                                   _stream(stream)), "fdot_modp")
+        return out
+
+    @staticmethod
+    def make_desc(xs, ys, device=None) -> torch.Tensor:
+        """Device descriptor array {x, y, n} for a batch of tensor pairs."""
+        rows = []
+        for x, y in zip(xs, ys):
+            if x.numel() != y.numel():
+                raise ValueError("length mismatch")
+            rows.append([x.data_ptr(), y.data_ptr(), x.numel()])
+        dev = device or (xs[0].device if len(xs) else "cuda")
+        return torch.tensor(rows, dtype=torch.int64).reshape(-1, 3).to(dev)
+
+    def dot_many(self, desc: torch.Tensor, out: torch.Tensor | None = None, algo: str = "auto",
+                 stream=None) -> torch.Tensor:
+        if desc.dtype != torch.int64 or desc.dim() != 2 or desc.shape[1] != 3 or not desc.is_cuda:
+            raise TypeError("desc must be a CUDA int64 tensor of shape [count, 3]")
+        count = desc.shape[0]
+        if out is None:
+            out = torch.empty(count, dtype=self.dtype, device=desc.device)
+        _check(_lib.fdot_modp_many_algo(self._h, ALGOS[algo], count, _ptr(desc), _ptr(out),
+                                        _stream(stream)), "fdot_modp_many")
+        return out
+
+    def gemv(self, A: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None = None,
+             stream=None) -> torch.Tensor:
+        self._need(A, "A")
+        self._need(x, "x")
+        m, n = A.shape
+        if A.stride(1) != 1 or x.numel() != n or not x.is_contiguous():
+            raise ValueError("A must be row-major and x of length A.shape[1]")
+        if out is None:
+            out = torch.empty(m, dtype=self.dtype, device=A.device)
+        _check(_lib.fgemv_modp(self._h, m, n, _ptr(A), A.stride(0), _ptr(x), _ptr(out),
+                               _stream(stream)), "fgemv_modp")
+        return out
+
+    def gemm(self, A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None,
+             stream=None) -> torch.Tensor:
+        self._need(A, "A")
+        self._need(B, "B")
+        M, K = A.shape
+        K2, N = B.shape
+        if K != K2 or A.stride(1) != 1 or B.stride(1) != 1:
+            raise ValueError("A and B must be row-major with matching inner dimension")
+        if out is None:
+            out = torch.empty((M, N), dtype=self.dtype, device=A.device)
+        _check(_lib.fgemm_modp(self._h, M, N, K, _ptr(A), A.stride(0), _ptr(B), B.stride(0),
+                               _ptr(out), out.stride(0), _stream(stream)), "fgemm_modp")
+        return out

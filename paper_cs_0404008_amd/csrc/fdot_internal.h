@@ -1,0 +1,65 @@
+// Internal declarations of libfdot: the field object, the per-stream
+// workspace, the tuning table and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "fdot.h"
+#include "fdot_arith.h"
+
+struct fdot_field_s {
+  fdot_field_info_t info;
+  FieldK k;             // device-ready constants (table pointers on device)
+  int device;
+  uint16_t* d_zval;     // Zech tables on the device (owned)
+  uint16_t* d_zplus1;
+  uint16_t* d_zidx;
+};
+
+// Device scratch owned per stream: per-instance accumulators and tickets for
+// the cross-workgroup combination, and the chunk plan of a batch.  Tickets and
+// accumulators are returned to zero by the workgroup that finishes an
+// instance, so no clearing happens between calls.
+struct Workspace {
+  int device = -1;
+  size_t cap = 0;          // instances
+  void* base = nullptr;
+  unsigned long long* acc = nullptr;  // cap
+  unsigned int* done = nullptr;       // cap
+  uint64_t* offsets = nullptr;        // cap + 1 (chunk prefix sums)
+  uint64_t* total = nullptr;          // 1
+};
+
+// Host-side helpers (host_field.cpp).
+int fd_is_prime_u64(uint64_t n);
+uint32_t fd_primitive_root(uint64_t p);
+fdot_status_t fd_fill_params(uint64_t p, fdot_rep_t rep, fdot_field_info_t* out);
+void fd_fieldk_from_info(const fdot_field_info_t* info, FieldK* k);
+int fd_zech_build(uint64_t p, uint32_t g, uint16_t* value, uint16_t* index, uint16_t* plus1);
+
+// Runtime (runtime.cpp).
+fdot_status_t fd_workspace_get(hipStream_t s, size_t count, Workspace** out);
+int64_t fd_tune(const char* key, int64_t fallback);
+int fd_cu_count();
+
+// Launchers (dot_kernels.hip, gemm_kernels.hip).  All validate nothing: the
+// C-ABI layer has checked arguments.
+fdot_status_t fd_launch_dot(const fdot_field_s* f, fdot_algo_t algo, const void* x,
+                            const void* y, uint64_t n, void* result, Workspace* ws,
+                            hipStream_t s);
+fdot_status_t fd_launch_many(const fdot_field_s* f, fdot_algo_t algo, size_t count,
+                             const fdot_desc_t* desc, void* results, Workspace* ws,
+                             hipStream_t s);
+fdot_status_t fd_launch_encode(const fdot_field_s* f, const uint32_t* canon, void* rep,
+                               size_t n, hipStream_t s);
+fdot_status_t fd_launch_decode(const fdot_field_s* f, const void* rep, uint32_t* canon,
+                               size_t n, hipStream_t s);
+fdot_status_t fd_launch_gemv(const fdot_field_s* f, size_t m, size_t n, const void* A,
+                             size_t lda, const void* x, void* y, hipStream_t s);
+fdot_status_t fd_launch_gemm(const fdot_field_s* f, size_t M, size_t N, size_t K,
+                             const void* A, size_t lda, const void* B, size_t ldb,
+                             void* C, size_t ldc, hipStream_t s);
+fdot_status_t fd_launch_zero(void* ptr, size_t bytes, hipStream_t s);
+fdot_algo_t fd_default_algo(const fdot_field_s* f, uint64_t n);

@@ -1,0 +1,225 @@
+// C-ABI layer of libfdot: argument checks, per-stream workspace, the tuned
+// parameter table and the public compute calls.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "fdot_internal.h"
+
+namespace {
+
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
+
+std::mutex g_tune_mu;
+std::map<std::string, int64_t> g_tune;
+bool g_tune_loaded = false;
+
+// Optional "key=value" lines from the file named by FDOT_TUNE_FILE (the table
+// an install-time tuning run writes), read once.
+void load_tune_file_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = getenv("FDOT_TUNE_FILE");
+  if (!path || !*path) return;
+  FILE* fp = fopen(path, "r");
+  if (!fp) return;
+  char line[256];
+  while (fgets(line, sizeof line, fp)) {
+    char* eq = strchr(line, '=');
+    if (!eq || line[0] == '#') continue;
+    *eq = 0;
+    char* k = line;
+    while (*k == ' ' || *k == '\t') ++k;
+    char* end = eq - 1;
+    while (end >= k && (*end == ' ' || *end == '\t')) *end-- = 0;
+    g_tune[k] = strtoll(eq + 1, nullptr, 10);
+  }
+  fclose(fp);
+}
+
+bool aligned_to(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+}  // namespace
+
+int64_t fd_tune(const char* key, int64_t fallback) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  load_tune_file_locked();
+  auto it = g_tune.find(key);
+  return it == g_tune.end() ? fallback : it->second;
+}
+
+int fd_cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+fdot_status_t fd_workspace_get(hipStream_t s, size_t count, Workspace** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return FDOT_E_DEVICE;
+  std::lock_guard<std::mutex> g(g_ws_mu);
+  Workspace*& w = g_ws[std::make_pair(dev, s)];
+  if (w && w->cap >= count) {
+    *out = w;
+    return FDOT_OK;
+  }
+  // Growing allocates, which a stream under graph capture cannot do.
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return FDOT_E_BUSY;
+  size_t cap = count < 4096 ? 4096 : count;
+  const size_t bytes_acc = cap * 8, bytes_done = (cap * 4 + 7) / 8 * 8, bytes_off = (cap + 1) * 8;
+  const size_t bytes = bytes_acc + bytes_done + bytes_off + 8;
+  void* base = nullptr;
+  if (hipMalloc(&base, bytes) != hipSuccess) return FDOT_E_NOMEM;
+  if (fd_launch_zero(base, bytes, s) != FDOT_OK) {
+    hipFree(base);
+    return FDOT_E_DEVICE;
+  }
+  if (w) {  // the old buffer may still be in use by work queued on s
+    hipStreamSynchronize(s);
+    hipFree(w->base);
+  } else {
+    w = new Workspace;
+  }
+  w->device = dev;
+  w->cap = cap;
+  w->base = base;
+  char* b = (char*)base;
+  w->acc = (unsigned long long*)b;
+  w->done = (unsigned int*)(b + bytes_acc);
+  w->offsets = (uint64_t*)(b + bytes_acc + bytes_done);
+  w->total = (uint64_t*)(b + bytes_acc + bytes_done + bytes_off);
+  *out = w;
+  return FDOT_OK;
+}
+
+extern "C" {
+
+const char* fdot_status_string(int status) {
+  switch (status) {
+    case FDOT_OK: return "ok";
+    case FDOT_E_INVALID_ARG: return "invalid argument";
+    case FDOT_E_NOT_PRIME: return "modulus is not prime";
+    case FDOT_E_BOUND: return "prime outside the representation bound";
+    case FDOT_E_UNSUPPORTED: return "unsupported for this representation or algorithm";
+    case FDOT_E_DEVICE: return "device (HIP) error";
+    case FDOT_E_NOMEM: return "out of memory";
+    case FDOT_E_BUSY: return "busy";
+    case FDOT_E_NOT_FOUND: return "not found";
+  }
+  return "unknown status";
+}
+
+int fdot_version(void) { return 1; }
+
+fdot_status_t fdot_tune_set(const char* key, int64_t value) {
+  if (!key || !*key) return FDOT_E_INVALID_ARG;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  load_tune_file_locked();
+  g_tune[key] = value;
+  return FDOT_OK;
+}
+
+fdot_status_t fdot_tune_get(const char* key, int64_t* value) {
+  if (!key || !value) return FDOT_E_INVALID_ARG;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  load_tune_file_locked();
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return FDOT_E_NOT_FOUND;
+  *value = it->second;
+  return FDOT_OK;
+}
+
+fdot_status_t fdot_workspace_reserve(void* stream, size_t count) {
+  Workspace* w = nullptr;
+  return fd_workspace_get((hipStream_t)stream, count ? count : 1, &w);
+}
+
+fdot_status_t fdot_encode(fdot_field_t f, const uint32_t* canon, void* rep, size_t n, void* stream) {
+  if (!f) return FDOT_E_INVALID_ARG;
+  if (n && (!canon || !rep || !aligned_to(rep, f->info.elem_bytes) || !aligned_to(canon, 4)))
+    return FDOT_E_INVALID_ARG;
+  return fd_launch_encode(f, canon, rep, n, (hipStream_t)stream);
+}
+
+fdot_status_t fdot_decode(fdot_field_t f, const void* rep, uint32_t* canon, size_t n, void* stream) {
+  if (!f) return FDOT_E_INVALID_ARG;
+  if (n && (!canon || !rep || !aligned_to(rep, f->info.elem_bytes) || !aligned_to(canon, 4)))
+    return FDOT_E_INVALID_ARG;
+  return fd_launch_decode(f, rep, canon, n, (hipStream_t)stream);
+}
+
+fdot_status_t fdot_modp_algo(fdot_field_t f, fdot_algo_t algo, const void* x, const void* y,
+                             size_t n, void* result, void* stream) {
+  if (!f || !result) return FDOT_E_INVALID_ARG;
+  if ((int)algo < FDOT_ALGO_AUTO || (int)algo > FDOT_ALGO_ZECH_EXP) return FDOT_E_INVALID_ARG;
+  const size_t es = f->info.elem_bytes;
+  if (!aligned_to(result, es)) return FDOT_E_INVALID_ARG;
+  if (n && (!x || !y || !aligned_to(x, es) || !aligned_to(y, es))) return FDOT_E_INVALID_ARG;
+  Workspace* w = nullptr;
+  fdot_status_t st = fd_workspace_get((hipStream_t)stream, 1, &w);
+  if (st != FDOT_OK) return st;
+  return fd_launch_dot(f, algo, x, y, n, result, w, (hipStream_t)stream);
+}
+
+fdot_status_t fdot_modp(fdot_field_t f, const void* x, const void* y, size_t n, void* result,
+                        void* stream) {
+  return fdot_modp_algo(f, FDOT_ALGO_AUTO, x, y, n, result, stream);
+}
+
+fdot_status_t fdot_modp_many_algo(fdot_field_t f, fdot_algo_t algo, size_t count,
+                                  const fdot_desc_t* desc, void* results, void* stream) {
+  if (!f) return FDOT_E_INVALID_ARG;
+  if ((int)algo < FDOT_ALGO_AUTO || (int)algo > FDOT_ALGO_ZECH_EXP) return FDOT_E_INVALID_ARG;
+  if (count == 0) return FDOT_OK;
+  if (!desc || !results || !aligned_to(desc, 8) || !aligned_to(results, f->info.elem_bytes))
+    return FDOT_E_INVALID_ARG;
+  if (count > (1ull << 31)) return FDOT_E_INVALID_ARG;
+  Workspace* w = nullptr;
+  fdot_status_t st = fd_workspace_get((hipStream_t)stream, count, &w);
+  if (st != FDOT_OK) return st;
+  return fd_launch_many(f, algo, count, desc, results, w, (hipStream_t)stream);
+}
+
+fdot_status_t fdot_modp_many(fdot_field_t f, size_t count, const fdot_desc_t* desc, void* results,
+                             void* stream) {
+  return fdot_modp_many_algo(f, FDOT_ALGO_AUTO, count, desc, results, stream);
+}
+
+fdot_status_t fgemv_modp(fdot_field_t f, size_t m, size_t n, const void* A, size_t lda,
+                         const void* x, void* y, void* stream) {
+  if (!f) return FDOT_E_INVALID_ARG;
+  if (m == 0) return FDOT_OK;
+  const size_t es = f->info.elem_bytes;
+  if (!A || !y || (n && !x) || lda < n) return FDOT_E_INVALID_ARG;
+  if (!aligned_to(A, es) || !aligned_to(y, es) || (x && !aligned_to(x, es)))
+    return FDOT_E_INVALID_ARG;
+  return fd_launch_gemv(f, m, n, A, lda, x, y, (hipStream_t)stream);
+}
+
+fdot_status_t fgemm_modp(fdot_field_t f, size_t M, size_t N, size_t K, const void* A, size_t lda,
+                         const void* B, size_t ldb, void* C, size_t ldc, void* stream) {
+  if (!f) return FDOT_E_INVALID_ARG;
+  if (M == 0 || N == 0) return FDOT_OK;
+  const size_t es = f->info.elem_bytes;
+  if (!C || ldc < N || (K && (!A || !B || lda < K || ldb < N))) return FDOT_E_INVALID_ARG;
+  if (!aligned_to(C, es) || (A && !aligned_to(A, es)) || (B && !aligned_to(B, es)))
+    return FDOT_E_INVALID_ARG;
+  return fd_launch_gemm(f, M, N, K, A, lda, B, ldb, C, ldc, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -87,3 +87,44 @@ def log_uniform_lengths(seed: int, stream: int, count: int, lo_exp: float,
     u = uniform_float(seed, stream, count)
     n = np.floor(10.0 ** (lo_exp + (hi_exp - lo_exp) * u)).astype(np.int64)
     return np.maximum(n, 1)
+
+
+# ------------------------------------------------------------- device twin
+_DTYPE_CODES = {"uint32": 0, "uint16": 1, "float64": 2, "int8": 3, "int64": 4}
+_dev_lib = None
+
+
+def _device_lib():
+    global _dev_lib
+    if _dev_lib is None:
+        import ctypes
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsynth.so")
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it first")
+        L = ctypes.CDLL(path)
+        L.synth_fill.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int,
+                                 ctypes.c_void_p, ctypes.c_void_p]
+        L.synth_fill.restype = ctypes.c_int
+        _dev_lib = L
+    return _dev_lib
+
+
+def fill_device(t, seed: int, stream: int, m: int, lo: int = 0, offset: int = 0,
+                hip_stream=None) -> None:
+    """Write uniform_int(seed, stream, t.numel(), m, lo, offset) into the
+    contiguous CUDA tensor t (uint32, uint16, float64, int8 or int64) on the
+    GPU: the same values the host generator produces."""
+    import ctypes
+    import torch
+    if not t.is_cuda or not t.is_contiguous():
+        raise TypeError("t must be a contiguous CUDA tensor")
+    name = str(t.dtype).replace("torch.", "")
+    if name not in _DTYPE_CODES:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    s = hip_stream if hip_stream is not None else torch.cuda.current_stream().cuda_stream
+    rc = _device_lib().synth_fill(seed, stream, offset, t.numel(), m, lo, _DTYPE_CODES[name],
+                                  ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(s))
+    if rc != 0:
+        raise RuntimeError(f"synth_fill failed ({rc})")

@@ -1,0 +1,155 @@
+"""GPU parity of the dot-product path against the oracle, bit for bit.
+
+Sizes span several chunks and ragged tails; every representation and every
+accumulation schedule; edge cases: empty, one element, misaligned and
+aliased operands, the maximal-product pattern that fills each block to its
+bound, and batches mixing empty, tiny and multi-chunk instances.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_helpers import ELEM_BYTES, TORCH_DTYPES, same, stored, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+fd = pytest.importorskip("paper_cs_0404008_amd")
+
+P_LAMBDA100 = 429496709   # lambda_u64 = 100: folds inside a chunk
+P_FP_LAMBDA3 = 54794149   # lambda_f64 = 3
+P_FP_MAX = 94906249       # largest prime with lambda_f64 >= 1
+
+CASES = (
+    [(p, "zpz", a) for p in (251, 32749, 65521, P_LAMBDA100, 2147483647, 4294967291)
+     for a in ("auto", "delayed", "perterm", "overflow")]
+    + [(p, "mont", a) for p in (3, 32749, 65521, 2147483647, 2654435761, 4294967291)
+       for a in ("auto", "delayed", "perterm", "overflow")]
+    + [(p, "fp64", a) for p in (251, 1048573, 67108859, P_FP_LAMBDA3, P_FP_MAX)
+       for a in ("auto", "delayed", "perterm")]
+    + [(p, "zech", a) for p in (3, 251, 32749, 65521) for a in ("auto", "zech_exp", "zech_tplus1")]
+    + [(p, "centred", a) for p in (3, 251) for a in ("auto", "delayed")]
+)
+
+
+def default_chunk(rep):
+    return 262144 // ELEM_BYTES[rep]
+
+
+def lengths(rep):
+    C = default_chunk(rep)
+    return [0, 1, 3, 63, 64, 65, 1000, C - 1, C, C + 1, 3 * C + 17]
+
+
+_fields = {}
+
+
+def field(p, rep):
+    if (p, rep) not in _fields:
+        _fields[(p, rep)] = fd.Field(p, rep)
+    return _fields[(p, rep)]
+
+
+@pytest.mark.parametrize("p,rep,algo", CASES, ids=lambda v: str(v))
+def test_dot_matches_oracle(p, rep, algo):
+    F = field(p, rep)
+    for k, n in enumerate(lengths(rep)):
+        for pattern in ("random", "maxprod"):
+            x = stored(p, rep, n, 100 + k, 0, pattern)
+            y = stored(p, rep, n, 100 + k, 1, pattern)
+            want = oracle.dot(p, rep, x, y)
+            got = to_host(F.dot(to_dev(x), to_dev(y), algo=algo))[0]
+            assert same(got, want), (p, rep, algo, n, pattern, got, want)
+
+
+@pytest.mark.parametrize("p,rep", [(32749, "zpz"), (2147483647, "mont"), (67108859, "fp64"),
+                                   (32749, "zech"), (251, "centred"), (4294967291, "zpz")])
+def test_misaligned_and_aliased(p, rep):
+    F = field(p, rep)
+    n = 3 * default_chunk(rep) + 5
+    xb = to_dev(stored(p, rep, n + 8, 7, 0))
+    yb = to_dev(stored(p, rep, n + 8, 7, 1))
+    xh, yh = to_host(xb), to_host(yb)
+    for ox, oy in [(1, 1), (1, 2), (3, 0), (0, 5)]:
+        got = to_host(F.dot(xb[ox:ox + n], yb[oy:oy + n]))[0]
+        want = oracle.dot(p, rep, xh[ox:ox + n], yh[oy:oy + n])
+        assert same(got, want), (ox, oy)
+    got = to_host(F.dot(xb[:n], xb[:n]))[0]
+    assert same(got, oracle.dot(p, rep, xh[:n], xh[:n]))
+
+
+@pytest.mark.parametrize("p,rep,algo", [(65521, "zpz", "auto"), (2147483647, "mont", "delayed"),
+                                        (4294967291, "zpz", "perterm"),
+                                        (4294967291, "zpz", "overflow"),
+                                        (67108859, "fp64", "auto"), (32749, "zech", "zech_exp"),
+                                        (32749, "zech", "zech_tplus1"), (251, "centred", "auto")])
+def test_batched_matches_oracle_and_single(p, rep, algo):
+    F = field(p, rep)
+    C = default_chunk(rep)
+    ns = [0, 1, 5, 64, 1000, C - 3, C, C + 1, 2 * C + 7, 0, 17, 5 * C + 3, 333, 12345]
+    xs = [to_dev(stored(p, rep, n, 31, 2 * k)) for k, n in enumerate(ns)]
+    ys = [to_dev(stored(p, rep, n, 31, 2 * k + 1)) for k, n in enumerate(ns)]
+    # misaligned views in the middle of the batch
+    big = to_dev(stored(p, rep, 9000, 32, 0))
+    xs.append(big[1:4001]); ys.append(big[3:4003])
+    xs.append(big[2:8002]); ys.append(big[2:8002])
+    desc = fd.Field.make_desc(xs, ys)
+    got = to_host(F.dot_many(desc, algo=algo))
+    want = oracle.dot_many(p, rep, [to_host(x) for x in xs], [to_host(y) for y in ys])
+    assert same(got, want)
+    single = np.array([to_host(F.dot(x, y, algo=algo))[0] for x, y in zip(xs, ys)])
+    assert same(got, single)
+    again = to_host(F.dot_many(desc, algo=algo))
+    assert same(got, again)
+
+
+def test_many_chunks_per_workgroup():
+    """Force few workgroups and small chunks so each workgroup loops over many
+    chunks of many instances."""
+    p, rep = 65521, "zpz"
+    F = field(p, rep)
+    fd.tune_set("chunk.zpz", 1024)
+    fd.tune_set("wg_per_cu.zpz", 1)
+    try:
+        ns = [int(v) for v in synth.log_uniform_lengths(9, 0, 300, 2.0, 5.0)]
+        xs = [to_dev(stored(p, rep, n, 33, 2 * k)) for k, n in enumerate(ns)]
+        ys = [to_dev(stored(p, rep, n, 33, 2 * k + 1)) for k, n in enumerate(ns)]
+        got = to_host(F.dot_many(fd.Field.make_desc(xs, ys)))
+        want = oracle.dot_many(p, rep, [to_host(x) for x in xs], [to_host(y) for y in ys])
+        assert same(got, want)
+        n = 1_000_003
+        x, y = stored(p, rep, n, 34, 0), stored(p, rep, n, 34, 1)
+        assert same(to_host(F.dot(to_dev(x), to_dev(y)))[0], oracle.dot(p, rep, x, y))
+    finally:
+        fd.tune_set("chunk.zpz", 65536)
+        fd.tune_set("wg_per_cu.zpz", 8)
+
+
+def test_centred_fold_path():
+    """A chunk long enough that the int32 accumulator must be flushed."""
+    p, rep = 251, "centred"
+    F = field(p, rep)
+    fd.tune_set("chunk.centred", 1 << 24)
+    try:
+        n = (1 << 24) + 77
+        for pattern in ("random", "maxprod"):
+            x, y = stored(p, rep, n, 35, 0, pattern), stored(p, rep, n, 35, 1, pattern)
+            assert same(to_host(F.dot(to_dev(x), to_dev(y)))[0], oracle.dot(p, rep, x, y))
+    finally:
+        fd.tune_set("chunk.centred", 262144)
+
+
+@pytest.mark.parametrize("p,rep", [(32749, "zpz"), (2147483647, "mont"), (4294967291, "mont"),
+                                   (67108859, "fp64"), (32749, "zech"), (65521, "zech"),
+                                   (251, "centred")])
+def test_encode_decode(p, rep):
+    F = field(p, rep)
+    n = 100003
+    canon = synth.uniform_int(41, 0, n, p).astype(np.uint32)
+    canon[:4] = [0, 1, p - 1, min(2, p - 1)]
+    enc = F.encode(to_dev(canon))
+    assert enc.dtype == TORCH_DTYPES[rep]
+    assert same(to_host(enc), oracle.encode(p, rep, canon.astype(np.uint64)))
+    dec = F.decode(enc)
+    assert same(to_host(dec), canon)
