@@ -234,7 +234,10 @@ fdot_status_t fgemm_modp(fdot_field_t f, size_t M, size_t N, size_t K, const voi
 fdot_status_t fdot_workspace_reserve(void* stream, size_t count);
 
 /* Tuned launch parameters, keyed by name (e.g. "chunk.zpz", "wg_per_cu.zpz").
- * Unknown keys give FDOT_E_NOT_FOUND. */
+ * fdot_tune_set with value INT64_MIN removes the key (back to the built-in
+ * default); fdot_tune_get of a key that is not set gives FDOT_E_NOT_FOUND.
+ * The file named by the environment variable FDOT_TUNE_FILE ("key=value"
+ * lines) is read at the first tuning lookup. */
 fdot_status_t fdot_tune_set(const char* key, int64_t value);
 fdot_status_t fdot_tune_get(const char* key, int64_t* value);
 

@@ -152,8 +152,10 @@ def zech_tables(p: int):
     return val, idx, plus1
 
 
-def tune_set(key: str, value: int) -> None:
-    _check(_lib.fdot_tune_set(key.encode(), int(value)), "fdot_tune_set")
+def tune_set(key: str, value) -> None:
+    """Set a tuned launch parameter; value None removes the key."""
+    v = -(1 << 63) if value is None else int(value)
+    _check(_lib.fdot_tune_set(key.encode(), v), "fdot_tune_set")
 
 
 def tune_get(key: str):
@@ -181,10 +183,10 @@ class Field:
         self.info = info.as_dict()
         self.dtype = TORCH_DTYPES[rep]
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.fdot_field_destroy):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            _lib.fdot_field_destroy(h)
+            _destroy(h)
             self._h = None
 
     @property

@@ -2,27 +2,60 @@
 // batched form (many pairs of uneven length in one launch), plus the
 // representation conversions and the matrix-vector product.
 //
-// Work decomposition.  A vector pair is cut into chunks of `chunk` elements;
-// a workgroup streams one chunk with 16-byte loads, every lane accumulating
-// its share in registers (the delayed reduction of Sec. 3.1-3.2, the on-demand
-// correction of Sec. 3.3, or a per-term reduction), then folds its
-// accumulators to a residue below p.  The workgroup sums its lanes' residues,
-// folds once more and adds the result (< p) to the pair's 64-bit accumulator
-// with one atomic; the workgroup that completes a pair's last chunk reads the
-// accumulator, reduces it, encodes the result in the pair's representation and
-// puts the accumulator and its ticket back to zero for the next call.  Integer
-// sums are exact and associative, so the result is the same bit pattern
-// whatever the order in which chunks finish.
+// Work decomposition.  A vector pair is cut into chunks, and each chunk into
+// four interleaved slices; the unit of work is one wavefront streaming one
+// slice with 16-byte loads, each lane accumulating its share in registers (the
+// delayed reduction of Sec. 3.1-3.2, the on-demand correction of Sec. 3.3, or
+// a per-term reduction) and folding to a residue below p at the end.  The
+// wavefront sums its lanes' residues with cross-lane shuffles, folds once
+// more, and adds the result r < p to the pair's combination word with one
+// 64-bit atomic: the low 48 bits collect the residues, the high 16 bits count
+// finished units.  A pair has at most 65535 units, so the low field cannot
+// overflow into the count, and the wavefront whose atomic returns
+// count = units-1 holds the complete sum: it reduces it, encodes the result
+// in the pair's representation and puts the word back to zero for the next
+// call.  No workgroup barrier, no memory fence: waves never wait for one
+// another.  Integer sums are exact and associative, so the result is the same
+// bit pattern whatever order the units finish in.
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 
 #include "fdot_internal.h"
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// 16-byte loads issued per operand before they are consumed (per lane).
+#ifndef FDOT_UNROLL
+#define FDOT_UNROLL 4
+#endif
+
+// Operand pointers reach the kernels through descriptors, so the compiler
+// cannot tell they address global memory and would emit flat loads, which
+// it must wait for all at once.  These casts make every streaming load a
+// global load, so a wavefront keeps all of its loads in flight.
+typedef __attribute__((address_space(1))) const u32x4 gvec_t;
+template <typename T>
+using gptr_t = __attribute__((address_space(1))) const T*;
+
+__device__ __forceinline__ u32x4 load_nt(const u32x4* p) {
+  return __builtin_nontemporal_load((gvec_t*)p);
+}
+__device__ __forceinline__ u32x4 load_v(const u32x4* p) { return *(gvec_t*)p; }
+template <typename T>
+__device__ __forceinline__ T load_s(const T* p) {
+  return *(gptr_t<T>)p;
+}
+
 namespace {
+
+constexpr uint64_t kCountOne = 1ull << 48;
+constexpr uint64_t kSumMask = kCountOne - 1;
+constexpr uint64_t kMaxUnits = 65535;  // per pair: the 16-bit count field
 
 struct Job {
   const void* x;             // single form
@@ -32,13 +65,28 @@ struct Job {
   uint64_t count;
   const uint64_t* offsets;   // chunk prefix sums (count + 1)
   const uint64_t* total;     // number of chunks of the batch
-  uint64_t chunk;            // elements per chunk
-  unsigned long long* acc;
-  unsigned int* done;
+  unsigned long long* next;  // next unclaimed chunk (reset by the plan kernel)
+  const uint32_t* owner;     // chunk -> pair, when the batch has <= owner_cap chunks
+  uint64_t owner_cap;
+  uint64_t chunk;            // elements per chunk (at least; see chunk_of)
+  unsigned long long* acc;   // combination words, one per pair
   void* results;
-  uint32_t fold_vecs;        // vectors between two folds (folding policies)
+  uint32_t fold_vecs;        // vectors between two folds
+  uint32_t slice_shift;      // log2 of the wavefronts sharing one chunk
+  uint32_t dynamic;          // batched form: units claimed from a counter
   uint32_t pad;
 };
+
+// Chunk length used for a pair of length n: the configured chunk, or longer
+// when the pair would otherwise need more than 65535 work units (chunks x
+// slices), the most the 16-bit count of its combination word can hold.
+__host__ __device__ __forceinline__ uint64_t chunk_of(uint64_t n, uint64_t chunk,
+                                                      uint32_t slice_shift) {
+  const uint64_t max_chunks = kMaxUnits >> slice_shift;
+  const uint64_t need = (n + max_chunks - 1) / max_chunks;
+  const uint64_t c = (need + 15) / 16 * 16;
+  return c > chunk ? c : chunk;
+}
 
 __device__ __forceinline__ uint32_t lo16(uint32_t w) { return w & 0xFFFFu; }
 __device__ __forceinline__ uint32_t hi16(uint32_t w) { return w >> 16; }
@@ -53,35 +101,35 @@ __device__ __forceinline__ D2 as_d2(const u32x4& v) {
 }
 
 // ------------------------------------------------------------------ policies
-// Each lane policy keeps a lane's accumulators and knows how to consume one
+// A lane policy keeps one lane's accumulators and knows how to consume one
 // 16-byte vector pair, one scalar pair, how to fold its state to a residue in
-// [0, p) and how to encode a final residue in its representation.
+// [0, p) and how to encode a final residue in its representation.  Policies
+// with a block bound count vectors and fold every J.fold_vecs of them; the
+// host sets fold_vecs from lambda so that no accumulator can overflow, and to
+// 2^32-1 (never reached) when lambda is out of reach.
 
 // Classical residues, 64-bit accumulators, one reduction per block of at most
-// lambda products (Sec. 3.1 Eq. 1, Sec. 3.2).  With FOLD = false the host has
-// checked that a lane never receives more than lambda products per chunk.
-template <bool FOLD>
+// lambda products (Sec. 3.1 Eq. 1 with the carried residue, Sec. 3.2).  Two
+// accumulators, each taking two products per vector.
 struct PZpzDelayed {
   using E = uint32_t;
   static constexpr int VW = 4;
-  static constexpr int U = 4;
+  static constexpr int U = FDOT_UNROLL;
+  static constexpr bool kFolds = true;
   uint64_t s0, s1;
-  uint32_t cnt;
-  __device__ void init(const FieldK&) { s0 = s1 = 0; cnt = 0; }
-  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK& F, const Job& J) {
+  __device__ void init(const FieldK&) { s0 = s1 = 0; }
+  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK&) {
     s0 += (uint64_t)a.x * b.x;
     s1 += (uint64_t)a.y * b.y;
     s0 += (uint64_t)a.z * b.z;
     s1 += (uint64_t)a.w * b.w;
-    if (FOLD && ++cnt == J.fold_vecs) {
-      s0 = mod_u64(s0, F);
-      s1 = mod_u64(s1, F);
-      cnt = 0;
-    }
+  }
+  __device__ void fold(const FieldK& F) {
+    s0 = mod_u64(s0, F);
+    s1 = mod_u64(s1, F);
   }
   __device__ void one(E a, E b, const FieldK& F, const Job&) {
-    s0 += (uint64_t)a * b;
-    if (FOLD) s0 = mod_u64(s0, F);
+    s0 = mod_u64(s0 + (uint64_t)a * b, F);
   }
   __device__ uint32_t finish(const FieldK& F) {
     return mod_u64((uint64_t)mod_u64(s0, F) + mod_u64(s1, F), F);
@@ -97,10 +145,10 @@ struct PZpzDelayed {
 struct PZpzPerTerm {
   using E = uint32_t;
   static constexpr int VW = 4;
-  static constexpr int U = 4;
+  static constexpr int U = FDOT_UNROLL;
   uint32_t a0, a1, a2, a3;
   __device__ void init(const FieldK&) { a0 = a1 = a2 = a3 = 0; }
-  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK& F, const Job&) {
+  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK& F) {
     a0 = mod_small((uint64_t)a.x * b.x + a0, F);
     a1 = mod_small((uint64_t)a.y * b.y + a1, F);
     a2 = mod_small((uint64_t)a.z * b.z + a2, F);
@@ -134,10 +182,10 @@ template <bool MONT>
 struct POverflow {
   using E = uint32_t;
   static constexpr int VW = 4;
-  static constexpr int U = 4;
+  static constexpr int U = FDOT_UNROLL;
   uint64_t s0, s1;
   __device__ void init(const FieldK&) { s0 = s1 = 0; }
-  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK& F, const Job&) {
+  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK& F) {
     ovf_add(s0, (uint64_t)a.x * b.x, F.corr);
     ovf_add(s1, (uint64_t)a.y * b.y, F.corr);
     ovf_add(s0, (uint64_t)a.z * b.z, F.corr);
@@ -159,31 +207,25 @@ struct POverflow {
 // below p*B, so REDC returns (block sum)*B^-1 mod p, which is already in
 // Montgomery form.  The REDC outputs of the blocks are added as plain
 // residues and reduced once at the end.
-template <bool FOLD>
 struct PMontDelayed {
   using E = uint32_t;
   static constexpr int VW = 4;
-  static constexpr int U = 4;
+  static constexpr int U = FDOT_UNROLL;
+  static constexpr bool kFolds = true;
   uint64_t t0, t1, tot;
-  uint32_t cnt;
-  __device__ void init(const FieldK&) { t0 = t1 = tot = 0; cnt = 0; }
-  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK& F, const Job& J) {
+  __device__ void init(const FieldK&) { t0 = t1 = tot = 0; }
+  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK&) {
     t0 += (uint64_t)a.x * b.x;
     t1 += (uint64_t)a.y * b.y;
     t0 += (uint64_t)a.z * b.z;
     t1 += (uint64_t)a.w * b.w;
-    if (FOLD && ++cnt == J.fold_vecs) {
-      tot += (uint64_t)redc(t0, F) + redc(t1, F);
-      t0 = t1 = 0;
-      cnt = 0;
-    }
+  }
+  __device__ void fold(const FieldK& F) {
+    tot += (uint64_t)redc(t0, F) + redc(t1, F);
+    t0 = t1 = 0;
   }
   __device__ void one(E a, E b, const FieldK& F, const Job&) {
-    t0 += (uint64_t)a * b;
-    if (FOLD) {
-      tot += redc(t0, F);
-      t0 = 0;
-    }
+    tot += redc((uint64_t)a * b, F);
   }
   __device__ uint32_t finish(const FieldK& F) {
     return mod_u64(tot + redc(t0, F) + redc(t1, F), F);
@@ -199,10 +241,10 @@ struct PMontDelayed {
 struct PMontPerTerm {
   using E = uint32_t;
   static constexpr int VW = 4;
-  static constexpr int U = 4;
+  static constexpr int U = FDOT_UNROLL;
   uint64_t t0, t1;
   __device__ void init(const FieldK&) { t0 = t1 = 0; }
-  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK& F, const Job&) {
+  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK& F) {
     t0 += redc((uint64_t)a.x * b.x, F);
     t1 += redc((uint64_t)a.y * b.y, F);
     t0 += redc((uint64_t)a.z * b.z, F);
@@ -220,28 +262,23 @@ struct PMontPerTerm {
 // Residues held in doubles (Sec. 2.3 with the delayed division of Sec. 3.1,
 // m = 53): fused multiply-adds are exact while the integral sum stays at or
 // below 2^53; the floating-point remainder folds every lambda_f64 products.
-template <bool FOLD>
 struct PF64 {
   using E = double;
   static constexpr int VW = 2;
-  static constexpr int U = 4;
+  static constexpr int U = FDOT_UNROLL;
+  static constexpr bool kFolds = true;
   double a0, a1;
-  uint32_t cnt;
-  __device__ void init(const FieldK&) { a0 = a1 = 0.0; cnt = 0; }
-  __device__ void vec(const u32x4& av, const u32x4& bv, const FieldK& F, const Job& J) {
+  __device__ void init(const FieldK&) { a0 = a1 = 0.0; }
+  __device__ void vec(const u32x4& av, const u32x4& bv, const FieldK&) {
     const D2 a = as_d2(av), b = as_d2(bv);
     a0 = fma(a.x, b.x, a0);
     a1 = fma(a.y, b.y, a1);
-    if (FOLD && ++cnt == J.fold_vecs) {
-      a0 = fold_f64(a0, F);
-      a1 = fold_f64(a1, F);
-      cnt = 0;
-    }
   }
-  __device__ void one(E a, E b, const FieldK& F, const Job&) {
-    a0 = fma(a, b, a0);
-    if (FOLD) a0 = fold_f64(a0, F);
+  __device__ void fold(const FieldK& F) {
+    a0 = fold_f64(a0, F);
+    a1 = fold_f64(a1, F);
   }
+  __device__ void one(E a, E b, const FieldK& F, const Job&) { a0 = fold_f64(fma(a, b, a0), F); }
   __device__ uint32_t finish(const FieldK& F) {
     const uint64_t r = (uint64_t)fold_f64(a0, F) + (uint64_t)fold_f64(a1, F);
     return (uint32_t)(r >= F.p ? r - F.p : r);
@@ -251,7 +288,7 @@ struct PF64 {
   }
 };
 
-// Zech product: index addition modulo q-1 (Sec. 2.4), code 0 is the zero
+// Zech product: index addition modulo q-1 (Sec. 2.4); code 0 is the zero
 // element and absorbs.
 __device__ __forceinline__ uint32_t zech_mul(uint32_t a, uint32_t b, uint32_t qbar) {
   uint32_t t = a + b;
@@ -261,29 +298,40 @@ __device__ __forceinline__ uint32_t zech_mul(uint32_t a, uint32_t b, uint32_t qb
 
 // Zech codes; products by index addition, then the value table (in LDS) turns
 // each product into a classical residue that is summed with delayed
-// reduction (the host checks that a lane's 32-bit sum cannot overflow).
+// reduction: two 32-bit sums, each taking four values per vector, flushed to
+// 64 bits every fold_vecs vectors.
 struct PZechExp {
   using E = uint16_t;
   static constexpr int VW = 8;
   static constexpr int U = 2;
   static constexpr bool kTable = true;
+  static constexpr bool kFolds = true;
   uint32_t s0, s1;
+  uint64_t tot;
   const uint16_t* tab;  // value table in LDS
-  __device__ void init(const FieldK&) { s0 = s1 = 0; }
+  __device__ void init(const FieldK&) { s0 = s1 = 0; tot = 0; }
   __device__ void term(uint32_t& s, uint32_t a, uint32_t b, const FieldK& F) {
     uint32_t t = a + b;
     t = t > F.qbar ? t - F.qbar : t;
     const uint32_t v = tab[t];
     s += (a == 0u || b == 0u) ? 0u : v;
   }
-  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK& F, const Job&) {
+  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK& F) {
     term(s0, lo16(a.x), lo16(b.x), F); term(s1, hi16(a.x), hi16(b.x), F);
     term(s0, lo16(a.y), lo16(b.y), F); term(s1, hi16(a.y), hi16(b.y), F);
     term(s0, lo16(a.z), lo16(b.z), F); term(s1, hi16(a.z), hi16(b.z), F);
     term(s0, lo16(a.w), lo16(b.w), F); term(s1, hi16(a.w), hi16(b.w), F);
   }
-  __device__ void one(E a, E b, const FieldK& F, const Job&) { term(s0, a, b, F); }
-  __device__ uint32_t finish(const FieldK& F) { return mod_u64((uint64_t)s0 + s1, F); }
+  __device__ void fold(const FieldK&) {
+    tot += (uint64_t)s0 + s1;
+    s0 = s1 = 0;
+  }
+  __device__ void one(E a, E b, const FieldK& F, const Job&) {
+    uint32_t s = 0;
+    term(s, a, b, F);
+    tot += s;
+  }
+  __device__ uint32_t finish(const FieldK& F) { return mod_u64(tot + s0 + s1, F); }
   __device__ static void store(void* out, uint64_t k, uint32_t r, const FieldK& F) {
     ((uint16_t*)out)[k] = F.zidx[r];
   }
@@ -306,7 +354,7 @@ struct PZechTplus1 {
   }
   __device__ uint32_t zadd(uint32_t u, uint32_t t, const FieldK& F) {
     int k = (int)t - (int)u;
-    k += (k <= 0) ? (int)F.qbar : 0;  // k in [1, q-1]
+    k += (k <= 0) ? (int)F.qbar : 0;  // in [0, q-1] always; [1, q-1] when u, t != 0
     const uint32_t h = tab[k];
     uint32_t w = u + h;
     w = w > F.qbar ? w - F.qbar : w;
@@ -317,7 +365,7 @@ struct PZechTplus1 {
   __device__ void term(int j, uint32_t a, uint32_t b, const FieldK& F) {
     z[j] = zadd(z[j], zech_mul(a, b, F.qbar), F);
   }
-  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK& F, const Job&) {
+  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK& F) {
     term(0, lo16(a.x), lo16(b.x), F); term(1, hi16(a.x), hi16(b.x), F);
     term(2, lo16(a.y), lo16(b.y), F); term(3, hi16(a.y), hi16(b.y), F);
     term(4, lo16(a.z), lo16(b.z), F); term(5, hi16(a.z), hi16(b.z), F);
@@ -337,33 +385,25 @@ struct PZechTplus1 {
 
 // Centred residues in int8 (Sec. 3.2.2): four-way int8 dot products into a
 // 32-bit accumulator, flushed to 64 bits every lambda_i32c products.
-template <bool FOLD>
 struct PCentred {
   using E = int8_t;
   static constexpr int VW = 16;
-  static constexpr int U = 4;
+  static constexpr int U = FDOT_UNROLL;
+  static constexpr bool kFolds = true;
   int32_t a;
   int64_t acc;
-  uint32_t cnt;
-  __device__ void init(const FieldK&) { a = 0; acc = 0; cnt = 0; }
-  __device__ void vec(const u32x4& x, const u32x4& y, const FieldK&, const Job& J) {
+  __device__ void init(const FieldK&) { a = 0; acc = 0; }
+  __device__ void vec(const u32x4& x, const u32x4& y, const FieldK&) {
     a = __builtin_amdgcn_sdot4((int)x.x, (int)y.x, a, false);
     a = __builtin_amdgcn_sdot4((int)x.y, (int)y.y, a, false);
     a = __builtin_amdgcn_sdot4((int)x.z, (int)y.z, a, false);
     a = __builtin_amdgcn_sdot4((int)x.w, (int)y.w, a, false);
-    if (FOLD && ++cnt == J.fold_vecs) {
-      acc += a;
-      a = 0;
-      cnt = 0;
-    }
   }
-  __device__ void one(E x, E y, const FieldK&, const Job&) {
-    a += (int32_t)x * (int32_t)y;
-    if (FOLD) {
-      acc += a;
-      a = 0;
-    }
+  __device__ void fold(const FieldK&) {
+    acc += a;
+    a = 0;
   }
+  __device__ void one(E x, E y, const FieldK&, const Job&) { acc += (int32_t)x * (int32_t)y; }
   __device__ uint32_t finish(const FieldK& F) { return mod_i64(acc + a, F); }
   __device__ static void store(void* out, uint64_t k, uint32_t r, const FieldK& F) {
     const int32_t c = (int32_t)r > F.half ? (int32_t)r - (int32_t)F.p32 : (int32_t)r;
@@ -376,59 +416,106 @@ struct HasTable { static constexpr bool value = false; };
 template <class P>
 struct HasTable<P, decltype((void)P::kTable)> { static constexpr bool value = P::kTable; };
 
+template <class P, class = void>
+struct Folds { static constexpr bool value = false; };
+template <class P>
+struct Folds<P, decltype((void)P::kFolds)> { static constexpr bool value = P::kFolds; };
+
 // --------------------------------------------------------------- the driver
 
-// Stream [x, x+len) against [y, y+len) through one lane policy.  16-byte
-// vector loads when both pointers share the same offset modulo 16 (a short
-// scalar head aligns them); scalar loads otherwise.
-template <class Pol, int NTH>
-__device__ __forceinline__ void run_range(Pol& L, const typename Pol::E* x,
-                                          const typename Pol::E* y, uint64_t len,
-                                          const FieldK& F, const Job& J) {
+// One wavefront streams its slice of [x, x+len) against [y, y+len) through a
+// lane policy.  The range is read as 1 KiB blocks (64 lanes x 16 bytes); slice
+// s of S takes blocks s, s+S, s+2S, ..., so the S wavefronts working on one
+// chunk sweep it together as one contiguous stream (far fewer DRAM row
+// switches than S independent streams).  Slice 0 also takes a short scalar
+// head that aligns both pointers to 16 bytes when they share the same offset,
+// and the scalar tail; pointers with different offsets are read with scalar
+// loads.  A folding policy folds before any accumulator can have taken more
+// than fold_vecs vectors: once per unrolled step when fold_vecs >= U, after
+// every vector otherwise.
+template <class Pol>
+__device__ __forceinline__ void wave_range(Pol& L, const typename Pol::E* x,
+                                           const typename Pol::E* y, uint64_t len,
+                                           uint32_t lane, uint32_t slice, uint32_t S,
+                                           const FieldK& F, const Job& J) {
   using E = typename Pol::E;
-  constexpr int VW = Pol::VW, U = Pol::U;
-  const uint32_t tid = threadIdx.x;
+  constexpr int VW = Pol::VW, U = Pol::U, W = 64;
+  constexpr bool kF = Folds<Pol>::value;
+  const uint32_t fv = J.fold_vecs;
   const uintptr_t ax = (uintptr_t)x & 15u, ay = (uintptr_t)y & 15u;
   if (ax != ay) {
-    for (uint64_t i = tid; i < len; i += NTH) L.one(x[i], y[i], F, J);
+    for (uint64_t i = (uint64_t)slice * W + lane; i < len; i += (uint64_t)S * W)
+      L.one(load_s(x + i), load_s(y + i), F, J);
     return;
   }
   uint64_t head = ax ? (16u - ax) / sizeof(E) : 0;
   if (head > len) head = len;
-  if (tid < head) L.one(x[tid], y[tid], F, J);
+  if (slice == 0 && lane < head) L.one(load_s(x + lane), load_s(y + lane), F, J);
   const u32x4* xv = (const u32x4*)(x + head);
   const u32x4* yv = (const u32x4*)(y + head);
   const uint64_t nv = (len - head) / VW;
-  uint64_t i = tid;
-  for (; i + (uint64_t)(U - 1) * NTH < nv; i += (uint64_t)U * NTH) {
-    u32x4 a[U], b[U];
+  const uint64_t step = (uint64_t)S * W;  // vectors from one block of this slice to the next
+  uint64_t i = (uint64_t)slice * W + lane;
+  uint32_t pending = 0;                   // vectors taken since the last fold
+  if (!kF || fv >= (uint32_t)U) {
+    for (; i + (uint64_t)(U - 1) * step < nv; i += (uint64_t)U * step) {
+      u32x4 a[U], b[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      a[u] = __builtin_nontemporal_load(xv + i + (uint64_t)u * NTH);
-      b[u] = __builtin_nontemporal_load(yv + i + (uint64_t)u * NTH);
+      for (int u = 0; u < U; ++u) {
+        a[u] = load_nt(xv + i + (uint64_t)u * step);
+        b[u] = load_nt(yv + i + (uint64_t)u * step);
+      }
+      // issue every load of the step before consuming any of them
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u) L.vec(a[u], b[u], F);
+      if constexpr (kF) {
+        pending += U;
+        if (pending > fv - U) {
+          L.fold(F);
+          pending = 0;
+        }
+      }
     }
+  } else {
+    for (; i + (uint64_t)(U - 1) * step < nv; i += (uint64_t)U * step) {
+      u32x4 a[U], b[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) L.vec(a[u], b[u], F, J);
+      for (int u = 0; u < U; ++u) {
+        a[u] = load_nt(xv + i + (uint64_t)u * step);
+        b[u] = load_nt(yv + i + (uint64_t)u * step);
+      }
+      // issue every load of the step before consuming any of them
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        L.vec(a[u], b[u], F);
+        if constexpr (kF) {
+          if (++pending == fv) {
+            L.fold(F);
+            pending = 0;
+          }
+        }
+      }
+    }
   }
-  for (; i < nv; i += NTH) L.vec(xv[i], yv[i], F, J);
+  for (; i < nv; i += step) {
+    L.vec(load_v(xv + i), load_v(yv + i), F);
+    if constexpr (kF) {
+      if (++pending >= fv) {
+        L.fold(F);
+        pending = 0;
+      }
+    }
+  }
   const uint64_t t0 = head + nv * VW;
-  if (tid < len - t0) L.one(x[t0 + tid], y[t0 + tid], F, J);
+  if (slice == 0 && lane < len - t0) L.one(load_s(x + t0 + lane), load_s(y + t0 + lane), F, J);
 }
 
-// Sum of one 64-bit value per thread; the result is valid in thread 0.
-template <int NTH>
-__device__ __forceinline__ uint64_t block_sum(uint64_t v, unsigned long long* s) {
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  __syncthreads();  // the previous chunk's reader of s is done
-  if ((threadIdx.x & 63u) == 0) s[threadIdx.x >> 6] = v;
-  __syncthreads();
-  uint64_t t = 0;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int w = 0; w < NTH / 64; ++w) t += s[w];
-  }
-  return t;
+  return v;
 }
 
 // Largest k with offsets[k] <= c (skips empty instances).
@@ -446,71 +533,111 @@ template <class Pol, int NTH, bool MANY>
 __global__ __launch_bounds__(NTH) void dot_kernel(const FieldK F, const Job J) {
   using E = typename Pol::E;
   extern __shared__ uint16_t s_tab[];
-  __shared__ unsigned long long s_red[NTH / 64];
   constexpr bool kTab = HasTable<Pol>::value;
-  if (kTab) {
+  if constexpr (kTab) {
     // The policy's table (p entries of 16 bits) is copied once per workgroup.
-    const uint16_t* src = nullptr;
-    if constexpr (kTab) src = std::is_same<Pol, PZechExp>::value ? F.zval : F.zplus1;
+    const uint16_t* src = std::is_same<Pol, PZechExp>::value ? F.zval : F.zplus1;
     for (uint32_t i = threadIdx.x; i < F.p32; i += NTH) s_tab[i] = src[i];
     __syncthreads();
   }
-  const uint64_t total = MANY ? *J.total : (J.n + J.chunk - 1) / J.chunk;
-  for (uint64_t c = blockIdx.x; c < total; c += gridDim.x) {
-    uint64_t k, nck, len;
+  const uint32_t lane = threadIdx.x & 63u;
+  // Work unit u = slice (u mod S) of chunk (u / S), S = 2^slice_shift: the S
+  // wavefronts of a chunk sweep it side by side.  Units are claimed from a
+  // counter (batched form, J.dynamic) or dealt round-robin: consecutive waves
+  // of a workgroup take consecutive units.
+  const uint32_t sh = J.slice_shift;
+  const uint32_t S = 1u << sh;
+  const uint64_t cs1 = MANY ? 0 : chunk_of(J.n, J.chunk, sh);
+  const uint64_t total_chunks = MANY ? *J.total : (J.n + cs1 - 1) / cs1;
+  const uint64_t total = total_chunks << sh;
+  const bool use_owner = MANY && total_chunks <= J.owner_cap;
+  const bool dyn = MANY && J.dynamic;
+  const uint64_t wstride = (uint64_t)gridDim.x * (NTH / 64);
+  uint64_t u = (uint64_t)blockIdx.x * (NTH / 64) + (threadIdx.x >> 6);
+  if (dyn) {
+    unsigned long long c0 = 0;
+    if (lane == 0) c0 = atomicAdd(J.next, 1ull);
+    u = __shfl(c0, 0, 64);
+  }
+  // The combination atomic of a unit is checked one unit later, so that the
+  // wavefront does not wait for its return before streaming the next unit.
+  bool has_pending = false;
+  uint64_t pk = 0, pnck = 0, pr = 0;
+  unsigned long long pold = 0;
+  while (u < total) {
+    unsigned long long nxt = 0;
+    if (dyn && lane == 0) nxt = atomicAdd(J.next, 1ull);  // claim the next unit early
+    const uint64_t c = u >> sh;
+    const uint32_t slice = (uint32_t)(u & (S - 1));
+    uint64_t k, beg, len, nck;
     const E* x;
     const E* y;
     if (MANY) {
-      k = find_instance(J.offsets, J.count, c);
+      k = use_owner ? (uint64_t)J.owner[c] : find_instance(J.offsets, J.count, c);
       const uint64_t first = J.offsets[k];
-      nck = J.offsets[k + 1] - first;
+      nck = (J.offsets[k + 1] - first) << sh;
       const fdot_desc_t d = J.desc[k];
-      const uint64_t beg = (c - first) * J.chunk;
-      len = d.n - beg < J.chunk ? d.n - beg : J.chunk;
+      const uint64_t cs = chunk_of(d.n, J.chunk, sh);
+      beg = (c - first) * cs;
+      len = d.n - beg < cs ? d.n - beg : cs;
       x = (const E*)d.x + beg;
       y = (const E*)d.y + beg;
     } else {
       k = 0;
       nck = total;
-      const uint64_t beg = c * J.chunk;
-      len = J.n - beg < J.chunk ? J.n - beg : J.chunk;
+      beg = c * cs1;
+      len = J.n - beg < cs1 ? J.n - beg : cs1;
       x = (const E*)J.x + beg;
       y = (const E*)J.y + beg;
     }
     Pol L;
     L.init(F);
     if constexpr (kTab) L.tab = s_tab;
-    run_range<Pol, NTH>(L, x, y, len, F, J);
-    const uint64_t wsum = block_sum<NTH>(L.finish(F), s_red);
-    if (threadIdx.x == 0) {
-      atomicAdd(J.acc + k, (unsigned long long)mod_u64(wsum, F));
-      __threadfence();
-      const unsigned prev = atomicAdd(J.done + k, 1u);
-      if (prev + 1 == nck) {
-        __threadfence();
-        const unsigned long long tot = atomicExch(J.acc + k, 0ull);
-        atomicExch(J.done + k, 0u);
-        Pol::store(J.results, k, mod_u64(tot, F), F);
+    wave_range<Pol>(L, x, y, len, lane, slice, S, F, J);
+    const uint64_t wsum = wave_sum(L.finish(F));
+    if (lane == 0) {
+      if (has_pending && (pold >> 48) + 1 == pnck) {
+        // Every other unit of that pair has been added: the word is ours.
+        atomicExch(J.acc + pk, 0ull);
+        Pol::store(J.results, pk, mod_u64((pold & kSumMask) + pr, F), F);
       }
+      pr = mod_u64(wsum, F);
+      pold = atomicAdd(J.acc + k, (unsigned long long)(pr + kCountOne));
+      pk = k;
+      pnck = nck;
+      has_pending = true;
     }
+    u = dyn ? (uint64_t)__shfl(nxt, 0, 64) : u + wstride;
+  }
+  if (lane == 0 && has_pending && (pold >> 48) + 1 == pnck) {
+    atomicExch(J.acc + pk, 0ull);
+    Pol::store(J.results, pk, mod_u64((pold & kSumMask) + pr, F), F);
   }
 }
 
-// Chunk plan of a batch: offsets[k] = sum_{j<k} ceil(n_j / chunk),
-// offsets[count] = total.  Empty instances get the zero element (all-zero
-// bits in every representation) at once, since no chunk will finish them.
+// Chunk plan of a batch: offsets[k] = sum_{j<k} chunks(n_j),
+// offsets[count] = total; resets the claim counter.  Empty instances get the
+// zero element (all-zero bits in every representation) at once, since no
+// chunk will finish them.
 constexpr int PLAN_NT = 1024;
 __global__ __launch_bounds__(PLAN_NT) void plan_kernel(const fdot_desc_t* desc, uint64_t count,
                                                        uint64_t chunk, uint64_t* offsets,
                                                        uint64_t* total, void* results,
-                                                       uint32_t elem_bytes) {
+                                                       uint32_t elem_bytes,
+                                                       unsigned long long* next,
+                                                       uint32_t* owner, uint64_t owner_cap,
+                                                       uint32_t slice_shift) {
   __shared__ uint64_t s[PLAN_NT];
   const uint32_t t = threadIdx.x;
   const uint64_t seg = (count + PLAN_NT - 1) / PLAN_NT;
   const uint64_t b = t * seg < count ? t * seg : count;
   const uint64_t e = b + seg < count ? b + seg : count;
   uint64_t local = 0;
-  for (uint64_t k = b; k < e; ++k) local += (desc[k].n + chunk - 1) / chunk;
+  for (uint64_t k = b; k < e; ++k) {
+    const uint64_t n = desc[k].n;
+    const uint64_t cs = chunk_of(n, chunk, slice_shift);
+    local += (n + cs - 1) / cs;
+  }
   s[t] = local;
   __syncthreads();
   for (uint32_t o = 1; o < PLAN_NT; o <<= 1) {  // inclusive scan
@@ -523,7 +650,8 @@ __global__ __launch_bounds__(PLAN_NT) void plan_kernel(const fdot_desc_t* desc, 
   for (uint64_t k = b; k < e; ++k) {
     offsets[k] = run;
     const uint64_t n = desc[k].n;
-    run += (n + chunk - 1) / chunk;
+    const uint64_t cs = chunk_of(n, chunk, slice_shift);
+    run += (n + cs - 1) / cs;
     if (n == 0) {
       uint8_t* r = (uint8_t*)results + k * elem_bytes;
       for (uint32_t i = 0; i < elem_bytes; ++i) r[i] = 0;
@@ -532,7 +660,14 @@ __global__ __launch_bounds__(PLAN_NT) void plan_kernel(const fdot_desc_t* desc, 
   if (t == PLAN_NT - 1) {
     offsets[count] = s[t];
     *total = s[t];
+    *next = 0;
   }
+  // chunk -> pair table (the batch kernel falls back to a binary search over
+  // the offsets when the batch has more chunks than the table holds)
+  const uint64_t tot = s[PLAN_NT - 1];
+  __syncthreads();  // offsets written by every thread of this workgroup
+  if (tot <= owner_cap)
+    for (uint64_t c = t; c < tot; c += PLAN_NT) owner[c] = (uint32_t)find_instance(offsets, count, c);
 }
 
 __global__ void zero_kernel(uint8_t* p, size_t bytes) {
@@ -594,74 +729,43 @@ __global__ __launch_bounds__(256) void gemv_kernel(const FieldK F, const Job J, 
   using E = typename Pol::E;
   extern __shared__ uint16_t s_tab[];
   constexpr bool kTab = HasTable<Pol>::value;
-  if (kTab) {
-    const uint16_t* src = nullptr;
-    if constexpr (kTab) src = std::is_same<Pol, PZechExp>::value ? F.zval : F.zplus1;
+  if constexpr (kTab) {
+    const uint16_t* src = std::is_same<Pol, PZechExp>::value ? F.zval : F.zplus1;
     for (uint32_t i = threadIdx.x; i < F.p32; i += 256) s_tab[i] = src[i];
     __syncthreads();
   }
   const uint64_t row = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= m) return;
   const uint32_t lane = threadIdx.x & 63u;
-  const E* a = (const E*)A + row * lda;
-  const E* xv = (const E*)x;
   Pol L;
   L.init(F);
   if constexpr (kTab) L.tab = s_tab;
-  constexpr int VW = Pol::VW;
-  const uintptr_t aa = (uintptr_t)a & 15u, ax = (uintptr_t)xv & 15u;
-  if (aa != ax) {
-    for (uint64_t i = lane; i < n; i += 64) L.one(a[i], xv[i], F, J);
-  } else {
-    uint64_t head = aa ? (16u - aa) / sizeof(E) : 0;
-    if (head > n) head = n;
-    if (lane < head) L.one(a[lane], xv[lane], F, J);
-    const u32x4* av = (const u32x4*)(a + head);
-    const u32x4* bv = (const u32x4*)(xv + head);
-    const uint64_t nv = (n - head) / VW;
-    uint64_t i = lane;
-    for (; i + 64 < nv; i += 128) {
-      const u32x4 a0 = av[i], b0 = bv[i], a1 = av[i + 64], b1 = bv[i + 64];
-      L.vec(a0, b0, F, J);
-      L.vec(a1, b1, F, J);
-    }
-    for (; i < nv; i += 64) L.vec(av[i], bv[i], F, J);
-    const uint64_t t0 = head + nv * VW;
-    if (lane < n - t0) L.one(a[t0 + lane], xv[t0 + lane], F, J);
-  }
-  uint64_t v = L.finish(F);
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  wave_range<Pol>(L, (const E*)A + row * lda, (const E*)x, n, lane, 0, 1, F, J);
+  const uint64_t v = wave_sum(L.finish(F));
   if (lane == 0) Pol::store(y, row, mod_u64(v, F), F);
 }
 
 // ---------------------------------------------------------------- launching
 enum class Kind {
-  ZpzDelayed, ZpzDelayedFold, ZpzPerTerm, ZpzOverflow,
-  MontDelayed, MontDelayedFold, MontPerTerm, MontOverflow,
-  F64, F64Fold, ZechExp, ZechTplus1, Centred, CentredFold
+  ZpzDelayed, ZpzPerTerm, ZpzOverflow, MontDelayed, MontPerTerm, MontOverflow,
+  F64, ZechExp, ZechTplus1, Centred
 };
 
 struct Plan {
   Kind kind;
   uint32_t fold_vecs;
-  int nth;
   size_t lds;
 };
 
-// Products one accumulator of a lane can receive from one chunk (or row):
-// ppv per vector, plus at most one head and one tail product.
-static uint64_t lane_products(uint64_t chunk, int vw, int nth, uint64_t ppv) {
-  const uint64_t vecs = (chunk + (uint64_t)vw * nth - 1) / ((uint64_t)vw * nth);
-  return vecs * ppv + 2;
+static uint32_t clamp_vecs(uint64_t v) {
+  return v == 0 ? 1u : (v > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)v);
 }
 
-static fdot_status_t make_plan(const fdot_field_s* f, fdot_algo_t algo, uint64_t chunk,
-                               int nth, Plan* pl) {
+// Choose the lane policy and its fold period from the field's block lengths.
+static fdot_status_t make_plan(const fdot_field_s* f, fdot_algo_t algo, Plan* pl) {
   const fdot_field_info_t& I = f->info;
-  if (algo == FDOT_ALGO_AUTO) algo = fd_default_algo(f, chunk);
-  pl->fold_vecs = 0;
-  pl->nth = nth;
+  if (algo == FDOT_ALGO_AUTO) algo = fd_default_algo(f, 0);
+  pl->fold_vecs = 0xFFFFFFFFu;
   pl->lds = 0;
   switch (I.rep) {
     case FDOT_REP_ZPZ_U32:
@@ -671,12 +775,8 @@ static fdot_status_t make_plan(const fdot_field_s* f, fdot_algo_t algo, uint64_t
         return FDOT_OK;
       }
       if (algo != FDOT_ALGO_DELAYED) return FDOT_E_UNSUPPORTED;
-      if (I.lambda_u64 >= lane_products(chunk, 4, nth, 2)) {
-        pl->kind = Kind::ZpzDelayed;
-      } else {
-        pl->kind = Kind::ZpzDelayedFold;
-        pl->fold_vecs = (uint32_t)(I.lambda_u64 / 2);
-      }
+      pl->kind = Kind::ZpzDelayed;
+      pl->fold_vecs = clamp_vecs(I.lambda_u64 / 2);  // two products per vector per accumulator
       return FDOT_OK;
     case FDOT_REP_MONT_U32:
       if (algo == FDOT_ALGO_OVERFLOW) { pl->kind = Kind::MontOverflow; return FDOT_OK; }
@@ -685,81 +785,80 @@ static fdot_status_t make_plan(const fdot_field_s* f, fdot_algo_t algo, uint64_t
         return FDOT_OK;
       }
       if (algo != FDOT_ALGO_DELAYED) return FDOT_E_UNSUPPORTED;
-      if (I.lambda_redc >= lane_products(chunk, 4, nth, 2)) {
-        pl->kind = Kind::MontDelayed;
-      } else {
-        pl->kind = Kind::MontDelayedFold;
-        pl->fold_vecs = (uint32_t)(I.lambda_redc / 2);
-      }
+      pl->kind = Kind::MontDelayed;
+      pl->fold_vecs = clamp_vecs(I.lambda_redc / 2);
       return FDOT_OK;
     case FDOT_REP_FP64:
-      if (algo == FDOT_ALGO_PERTERM) {
-        pl->kind = Kind::F64Fold;
-        pl->fold_vecs = 1;
-        return FDOT_OK;
-      }
-      if (algo != FDOT_ALGO_DELAYED) return FDOT_E_UNSUPPORTED;
-      if (I.lambda_f64 >= lane_products(chunk, 2, nth, 1)) {
-        pl->kind = Kind::F64;
-      } else {
-        pl->kind = Kind::F64Fold;
-        pl->fold_vecs = (uint32_t)(I.lambda_f64 < 0xFFFFFFFFull ? I.lambda_f64 : 0xFFFFFFFFull);
-      }
+      if (algo != FDOT_ALGO_DELAYED && algo != FDOT_ALGO_PERTERM) return FDOT_E_UNSUPPORTED;
+      pl->kind = Kind::F64;
+      pl->fold_vecs = algo == FDOT_ALGO_PERTERM ? 1u : clamp_vecs(I.lambda_f64);
       return FDOT_OK;
     case FDOT_REP_ZECH_U16:
-      pl->lds = (size_t)((I.p + 1) / 2) * 4;
+      pl->lds = (size_t)I.p * 2;
       if (algo == FDOT_ALGO_ZECH_TPLUS1) { pl->kind = Kind::ZechTplus1; return FDOT_OK; }
       if (algo != FDOT_ALGO_ZECH_EXP) return FDOT_E_UNSUPPORTED;
-      // Each lane sums up to lane_products values below p in 32 bits.
-      if (lane_products(chunk, 8, nth, 4) * (I.p - 1) > 0xFFFFFFFFull) return FDOT_E_UNSUPPORTED;
       pl->kind = Kind::ZechExp;
+      // each 32-bit sum takes four values below p per vector
+      pl->fold_vecs = clamp_vecs(0xFFFFFFFFull / (4 * (I.p - 1)));
       return FDOT_OK;
     case FDOT_REP_CENTRED_I8:
       if (algo != FDOT_ALGO_DELAYED) return FDOT_E_UNSUPPORTED;
-      if (I.lambda_i32c >= lane_products(chunk, 16, nth, 16)) {
-        pl->kind = Kind::Centred;
-      } else {
-        if (I.lambda_i32c < 16) return FDOT_E_UNSUPPORTED;
-        pl->kind = Kind::CentredFold;
-        pl->fold_vecs = (uint32_t)(I.lambda_i32c / 16);
-      }
+      if (I.lambda_i32c < 16) return FDOT_E_UNSUPPORTED;
+      pl->kind = Kind::Centred;
+      pl->fold_vecs = clamp_vecs(I.lambda_i32c / 16);  // sixteen products per vector
       return FDOT_OK;
   }
   return FDOT_E_UNSUPPORTED;
 }
 
+// Workgroups of `fn` that can be resident on one CU with `lds` bytes of
+// dynamic LDS (cached).  Grids are clamped to CUs x this: a larger grid would
+// leave a second, short wave of workgroups at the end.
+static int resident_per_cu(const void* fn, int nth, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, size_t>, int> cache;
+  std::lock_guard<std::mutex> g(mu);
+  auto key = std::make_pair(fn, lds);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  if (lds > 65536) hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nth, lds) != hipSuccess || nb < 1) nb = 1;
+  cache[key] = nb;
+  return nb;
+}
+
 template <class Pol, int NTH>
-static fdot_status_t launch_dot_t(const FieldK& F, const Job& J, bool many, unsigned grid,
-                                  size_t lds, hipStream_t s) {
-  if (many) {
-    auto fn = dot_kernel<Pol, NTH, true>;
-    if (lds > 65536) hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(NTH), lds, s, F, J);
-  } else {
-    auto fn = dot_kernel<Pol, NTH, false>;
-    if (lds > 65536) hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(NTH), lds, s, F, J);
-  }
+static fdot_status_t launch_dot_t(const FieldK& F, const Job& J, bool many, uint64_t work_waves,
+                                  unsigned wg_per_cu, size_t lds, hipStream_t s) {
+  const void* fn = many ? (const void*)dot_kernel<Pol, NTH, true>
+                        : (const void*)dot_kernel<Pol, NTH, false>;
+  unsigned per_cu = (unsigned)resident_per_cu(fn, NTH, lds);
+  if (wg_per_cu < per_cu) per_cu = wg_per_cu;
+  uint64_t grid = (uint64_t)fd_cu_count() * per_cu;
+  const uint64_t need = (work_waves + NTH / 64 - 1) / (NTH / 64);
+  if (need < grid) grid = need;
+  if (grid < 1) grid = 1;
+  if (many)
+    hipLaunchKernelGGL((dot_kernel<Pol, NTH, true>), dim3((unsigned)grid), dim3(NTH), lds, s, F, J);
+  else
+    hipLaunchKernelGGL((dot_kernel<Pol, NTH, false>), dim3((unsigned)grid), dim3(NTH), lds, s, F, J);
   return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
 }
 
 static fdot_status_t dispatch(const Plan& pl, const FieldK& F, const Job& J, bool many,
-                              unsigned grid, hipStream_t s) {
+                              uint64_t work_waves, unsigned wpc, hipStream_t s) {
   switch (pl.kind) {
-    case Kind::ZpzDelayed: return launch_dot_t<PZpzDelayed<false>, 256>(F, J, many, grid, 0, s);
-    case Kind::ZpzDelayedFold: return launch_dot_t<PZpzDelayed<true>, 256>(F, J, many, grid, 0, s);
-    case Kind::ZpzPerTerm: return launch_dot_t<PZpzPerTerm, 256>(F, J, many, grid, 0, s);
-    case Kind::ZpzOverflow: return launch_dot_t<POverflow<false>, 256>(F, J, many, grid, 0, s);
-    case Kind::MontDelayed: return launch_dot_t<PMontDelayed<false>, 256>(F, J, many, grid, 0, s);
-    case Kind::MontDelayedFold: return launch_dot_t<PMontDelayed<true>, 256>(F, J, many, grid, 0, s);
-    case Kind::MontPerTerm: return launch_dot_t<PMontPerTerm, 256>(F, J, many, grid, 0, s);
-    case Kind::MontOverflow: return launch_dot_t<POverflow<true>, 256>(F, J, many, grid, 0, s);
-    case Kind::F64: return launch_dot_t<PF64<false>, 256>(F, J, many, grid, 0, s);
-    case Kind::F64Fold: return launch_dot_t<PF64<true>, 256>(F, J, many, grid, 0, s);
-    case Kind::ZechExp: return launch_dot_t<PZechExp, 1024>(F, J, many, grid, pl.lds, s);
-    case Kind::ZechTplus1: return launch_dot_t<PZechTplus1, 1024>(F, J, many, grid, pl.lds, s);
-    case Kind::Centred: return launch_dot_t<PCentred<false>, 256>(F, J, many, grid, 0, s);
-    case Kind::CentredFold: return launch_dot_t<PCentred<true>, 256>(F, J, many, grid, 0, s);
+    case Kind::ZpzDelayed: return launch_dot_t<PZpzDelayed, 256>(F, J, many, work_waves, wpc, 0, s);
+    case Kind::ZpzPerTerm: return launch_dot_t<PZpzPerTerm, 256>(F, J, many, work_waves, wpc, 0, s);
+    case Kind::ZpzOverflow: return launch_dot_t<POverflow<false>, 256>(F, J, many, work_waves, wpc, 0, s);
+    case Kind::MontDelayed: return launch_dot_t<PMontDelayed, 256>(F, J, many, work_waves, wpc, 0, s);
+    case Kind::MontPerTerm: return launch_dot_t<PMontPerTerm, 256>(F, J, many, work_waves, wpc, 0, s);
+    case Kind::MontOverflow: return launch_dot_t<POverflow<true>, 256>(F, J, many, work_waves, wpc, 0, s);
+    case Kind::F64: return launch_dot_t<PF64, 256>(F, J, many, work_waves, wpc, 0, s);
+    case Kind::ZechExp: return launch_dot_t<PZechExp, 1024>(F, J, many, work_waves, wpc, pl.lds, s);
+    case Kind::ZechTplus1: return launch_dot_t<PZechTplus1, 1024>(F, J, many, work_waves, wpc, pl.lds, s);
+    case Kind::Centred: return launch_dot_t<PCentred, 256>(F, J, many, work_waves, wpc, 0, s);
   }
   return FDOT_E_UNSUPPORTED;
 }
@@ -775,29 +874,49 @@ static const char* rep_key(int rep) {
   return "zpz";
 }
 
-struct LaunchShape {
+// Launch parameters from the tuning table.  slices.<rep>: wavefronts that
+// share one chunk (1, 2, 4 or 8); dynamic.<rep>: batched units claimed from a
+// counter (1) or dealt round-robin (0); chunk.<rep>: elements per chunk of
+// the batched form (default 128 KiB per operand);
+// min_chunk.<rep>: smallest chunk of the single form, which otherwise spreads
+// a vector over every resident wavefront; wg_per_cu.<rep>: workgroups per CU
+// (further clamped by residency).
+struct Shape {
   uint64_t chunk;
-  int nth;
-  unsigned max_grid;
+  unsigned wg_per_cu;
+  int waves_per_wg;
+  uint32_t slice_shift;
+  uint32_t dynamic;
 };
 
-static LaunchShape shape_for(const fdot_field_s* f) {
+static Shape shape_for(const fdot_field_s* f, uint64_t n_single) {
   char key[64];
   const char* r = rep_key(f->info.rep);
   const bool zech = f->info.rep == FDOT_REP_ZECH_U16;
-  // Defaults: 256 KiB per operand per chunk for 16-byte-vector policies.
-  const int64_t dflt_chunk = (int64_t)(262144 / f->info.elem_bytes);
-  snprintf(key, sizeof key, "chunk.%s", r);
-  int64_t chunk = fd_tune(key, dflt_chunk);
-  chunk = (chunk + 15) / 16 * 16;
-  if (chunk < 1024) chunk = 1024;
+  const uint64_t eb = f->info.elem_bytes;
+  Shape sh;
+  sh.waves_per_wg = zech ? 16 : 4;
+  snprintf(key, sizeof key, "slices.%s", r);
+  const int64_t sl = fd_tune(key, 1);
+  sh.slice_shift = sl >= 8 ? 3 : sl >= 4 ? 2 : sl >= 2 ? 1 : 0;
+  snprintf(key, sizeof key, "dynamic.%s", r);
+  sh.dynamic = fd_tune(key, 0) != 0;
   snprintf(key, sizeof key, "wg_per_cu.%s", r);
-  int64_t wpc = fd_tune(key, zech ? (f->info.p <= 40000 ? 2 : 1) : 8);
-  if (wpc < 1) wpc = 1;
-  LaunchShape sh;
+  int64_t wpc = fd_tune(key, zech ? 2 : 2);
+  sh.wg_per_cu = (unsigned)(wpc < 1 ? 1 : wpc);
+  snprintf(key, sizeof key, "chunk.%s", r);
+  int64_t chunk = fd_tune(key, (int64_t)(131072 / eb));
+  if (n_single) {
+    snprintf(key, sizeof key, "min_chunk.%s", r);
+    int64_t mn = fd_tune(key, (int64_t)(16384 / eb));
+    const uint64_t waves = (uint64_t)fd_cu_count() * sh.wg_per_cu * sh.waves_per_wg;
+    const int64_t spread = (int64_t)((n_single + waves - 1) / waves);
+    chunk = spread < chunk ? spread : chunk;
+    if (chunk < mn) chunk = mn;
+  }
+  chunk = (chunk + 15) / 16 * 16;
+  if (chunk < 64) chunk = 64;
   sh.chunk = (uint64_t)chunk;
-  sh.nth = zech ? 1024 : 256;
-  sh.max_grid = (unsigned)(fd_cu_count() * wpc);
   return sh;
 }
 
@@ -824,9 +943,9 @@ fdot_status_t fd_launch_dot(const fdot_field_s* f, fdot_algo_t algo, const void*
                        f->info.elem_bytes);
     return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
   }
-  const LaunchShape sh = shape_for(f);
+  const Shape sh = shape_for(f, n);
   Plan pl;
-  fdot_status_t st = make_plan(f, algo, sh.chunk, sh.nth, &pl);
+  fdot_status_t st = make_plan(f, algo, &pl);
   if (st != FDOT_OK) return st;
   Job J;
   memset(&J, 0, sizeof J);
@@ -835,24 +954,24 @@ fdot_status_t fd_launch_dot(const fdot_field_s* f, fdot_algo_t algo, const void*
   J.n = n;
   J.chunk = sh.chunk;
   J.acc = ws->acc;
-  J.done = ws->done;
   J.results = result;
   J.fold_vecs = pl.fold_vecs;
-  const uint64_t chunks = (n + sh.chunk - 1) / sh.chunk;
-  const unsigned grid = (unsigned)(chunks < sh.max_grid ? chunks : sh.max_grid);
-  return dispatch(pl, f->k, J, false, grid, s);
+  J.slice_shift = sh.slice_shift;
+  const uint64_t cs = chunk_of(n, sh.chunk, sh.slice_shift);
+  return dispatch(pl, f->k, J, false, ((n + cs - 1) / cs) << sh.slice_shift, sh.wg_per_cu, s);
 }
 
 fdot_status_t fd_launch_many(const fdot_field_s* f, fdot_algo_t algo, size_t count,
                              const fdot_desc_t* desc, void* results, Workspace* ws,
                              hipStream_t s) {
   if (count == 0) return FDOT_OK;
-  const LaunchShape sh = shape_for(f);
+  const Shape sh = shape_for(f, 0);
   Plan pl;
-  fdot_status_t st = make_plan(f, algo, sh.chunk, sh.nth, &pl);
+  fdot_status_t st = make_plan(f, algo, &pl);
   if (st != FDOT_OK) return st;
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(PLAN_NT), 0, s, desc, (uint64_t)count, sh.chunk,
-                     ws->offsets, ws->total, results, f->info.elem_bytes);
+                     ws->offsets, ws->total, results, f->info.elem_bytes, ws->next, ws->owner,
+                     (uint64_t)ws->owner_cap, sh.slice_shift);
   if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
   Job J;
   memset(&J, 0, sizeof J);
@@ -860,12 +979,16 @@ fdot_status_t fd_launch_many(const fdot_field_s* f, fdot_algo_t algo, size_t cou
   J.count = count;
   J.offsets = ws->offsets;
   J.total = ws->total;
+  J.next = ws->next;
+  J.owner = ws->owner;
+  J.owner_cap = ws->owner_cap;
+  J.slice_shift = sh.slice_shift;
+  J.dynamic = sh.dynamic;
   J.chunk = sh.chunk;
   J.acc = ws->acc;
-  J.done = ws->done;
   J.results = results;
   J.fold_vecs = pl.fold_vecs;
-  return dispatch(pl, f->k, J, true, sh.max_grid, s);
+  return dispatch(pl, f->k, J, true, ~0ull >> 8, sh.wg_per_cu, s);
 }
 
 fdot_status_t fd_launch_encode(const fdot_field_s* f, const uint32_t* canon, void* rep, size_t n,
@@ -907,31 +1030,25 @@ static fdot_status_t launch_gemv_t(const fdot_field_s* f, const Job& J, size_t m
 fdot_status_t fd_launch_gemv(const fdot_field_s* f, size_t m, size_t n, const void* A, size_t lda,
                              const void* x, void* y, hipStream_t s) {
   if (m == 0) return FDOT_OK;
-  // A row is one "chunk" streamed by one wavefront (64 lanes).
+  if ((m + 3) / 4 > 0x7FFFFFFFull) return FDOT_E_INVALID_ARG;
   Plan pl;
   fdot_algo_t algo = fd_default_algo(f, n);
-  if (f->info.rep == FDOT_REP_ZECH_U16) algo = FDOT_ALGO_ZECH_EXP;
-  fdot_status_t st = make_plan(f, algo, n ? n : 1, 64, &pl);
+  fdot_status_t st = make_plan(f, algo, &pl);
   if (st != FDOT_OK) return st;
-  if (pl.lds) pl.lds = (size_t)f->info.p * 2;
   Job J;
   memset(&J, 0, sizeof J);
   J.fold_vecs = pl.fold_vecs;
   switch (pl.kind) {
-    case Kind::ZpzDelayed: return launch_gemv_t<PZpzDelayed<false>>(f, J, m, n, A, lda, x, y, 0, s);
-    case Kind::ZpzDelayedFold: return launch_gemv_t<PZpzDelayed<true>>(f, J, m, n, A, lda, x, y, 0, s);
+    case Kind::ZpzDelayed: return launch_gemv_t<PZpzDelayed>(f, J, m, n, A, lda, x, y, 0, s);
     case Kind::ZpzPerTerm: return launch_gemv_t<PZpzPerTerm>(f, J, m, n, A, lda, x, y, 0, s);
     case Kind::ZpzOverflow: return launch_gemv_t<POverflow<false>>(f, J, m, n, A, lda, x, y, 0, s);
-    case Kind::MontDelayed: return launch_gemv_t<PMontDelayed<false>>(f, J, m, n, A, lda, x, y, 0, s);
-    case Kind::MontDelayedFold: return launch_gemv_t<PMontDelayed<true>>(f, J, m, n, A, lda, x, y, 0, s);
+    case Kind::MontDelayed: return launch_gemv_t<PMontDelayed>(f, J, m, n, A, lda, x, y, 0, s);
     case Kind::MontPerTerm: return launch_gemv_t<PMontPerTerm>(f, J, m, n, A, lda, x, y, 0, s);
     case Kind::MontOverflow: return launch_gemv_t<POverflow<true>>(f, J, m, n, A, lda, x, y, 0, s);
-    case Kind::F64: return launch_gemv_t<PF64<false>>(f, J, m, n, A, lda, x, y, 0, s);
-    case Kind::F64Fold: return launch_gemv_t<PF64<true>>(f, J, m, n, A, lda, x, y, 0, s);
+    case Kind::F64: return launch_gemv_t<PF64>(f, J, m, n, A, lda, x, y, 0, s);
     case Kind::ZechExp: return launch_gemv_t<PZechExp>(f, J, m, n, A, lda, x, y, pl.lds, s);
     case Kind::ZechTplus1: return launch_gemv_t<PZechTplus1>(f, J, m, n, A, lda, x, y, pl.lds, s);
-    case Kind::Centred: return launch_gemv_t<PCentred<false>>(f, J, m, n, A, lda, x, y, 0, s);
-    case Kind::CentredFold: return launch_gemv_t<PCentred<true>>(f, J, m, n, A, lda, x, y, 0, s);
+    case Kind::Centred: return launch_gemv_t<PCentred>(f, J, m, n, A, lda, x, y, 0, s);
   }
   return FDOT_E_UNSUPPORTED;
 }

@@ -18,18 +18,20 @@ struct fdot_field_s {
   uint16_t* d_zidx;
 };
 
-// Device scratch owned per stream: per-instance accumulators and tickets for
-// the cross-workgroup combination, and the chunk plan of a batch.  Tickets and
-// accumulators are returned to zero by the workgroup that finishes an
-// instance, so no clearing happens between calls.
+// Device scratch owned per stream: one combination word per instance (residue
+// sum and finished-chunk count, returned to zero by the wavefront that
+// finishes the instance, so no clearing happens between calls), and the chunk
+// plan of a batch (prefix offsets, chunk -> instance table, claim counter).
 struct Workspace {
   int device = -1;
   size_t cap = 0;          // instances
   void* base = nullptr;
   unsigned long long* acc = nullptr;  // cap
-  unsigned int* done = nullptr;       // cap
+  uint32_t* owner = nullptr;          // owner_cap: chunk -> instance
+  size_t owner_cap = 0;
   uint64_t* offsets = nullptr;        // cap + 1 (chunk prefix sums)
   uint64_t* total = nullptr;          // 1
+  unsigned long long* next = nullptr; // 1: chunk counter of the batched form
 };
 
 // Host-side helpers (host_field.cpp).

@@ -81,8 +81,10 @@ fdot_status_t fd_workspace_get(hipStream_t s, size_t count, Workspace** out) {
   if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
     return FDOT_E_BUSY;
   size_t cap = count < 4096 ? 4096 : count;
-  const size_t bytes_acc = cap * 8, bytes_done = (cap * 4 + 7) / 8 * 8, bytes_off = (cap + 1) * 8;
-  const size_t bytes = bytes_acc + bytes_done + bytes_off + 8;
+  const size_t owner_cap = cap * 64 < (1u << 20) ? (1u << 20) : cap * 64;
+  const size_t bytes_acc = cap * 8, bytes_owner = (owner_cap * 4 + 7) / 8 * 8,
+               bytes_off = (cap + 1) * 8;
+  const size_t bytes = bytes_acc + bytes_owner + bytes_off + 16;
   void* base = nullptr;
   if (hipMalloc(&base, bytes) != hipSuccess) return FDOT_E_NOMEM;
   if (fd_launch_zero(base, bytes, s) != FDOT_OK) {
@@ -100,9 +102,11 @@ fdot_status_t fd_workspace_get(hipStream_t s, size_t count, Workspace** out) {
   w->base = base;
   char* b = (char*)base;
   w->acc = (unsigned long long*)b;
-  w->done = (unsigned int*)(b + bytes_acc);
-  w->offsets = (uint64_t*)(b + bytes_acc + bytes_done);
-  w->total = (uint64_t*)(b + bytes_acc + bytes_done + bytes_off);
+  w->owner = (uint32_t*)(b + bytes_acc);
+  w->owner_cap = owner_cap;
+  w->offsets = (uint64_t*)(b + bytes_acc + bytes_owner);
+  w->total = (uint64_t*)(b + bytes_acc + bytes_owner + bytes_off);
+  w->next = (unsigned long long*)(b + bytes_acc + bytes_owner + bytes_off + 8);
   *out = w;
   return FDOT_OK;
 }
@@ -130,7 +134,10 @@ fdot_status_t fdot_tune_set(const char* key, int64_t value) {
   if (!key || !*key) return FDOT_E_INVALID_ARG;
   std::lock_guard<std::mutex> g(g_tune_mu);
   load_tune_file_locked();
-  g_tune[key] = value;
+  if (value == INT64_MIN)
+    g_tune.erase(key);
+  else
+    g_tune[key] = value;
   return FDOT_OK;
 }
 

@@ -34,7 +34,7 @@ CASES = (
 
 
 def default_chunk(rep):
-    return 262144 // ELEM_BYTES[rep]
+    return 65536 // ELEM_BYTES[rep]
 
 
 def lengths(rep):
@@ -61,6 +61,13 @@ def test_dot_matches_oracle(p, rep, algo):
             want = oracle.dot(p, rep, x, y)
             got = to_host(F.dot(to_dev(x), to_dev(y), algo=algo))[0]
             assert same(got, want), (p, rep, algo, n, pattern, got, want)
+    # the same pairs as one batch (long chunks: exercises the in-chunk folds)
+    for pattern in ("random", "maxprod"):
+        xs = [stored(p, rep, n, 100 + k, 0, pattern) for k, n in enumerate(lengths(rep))]
+        ys = [stored(p, rep, n, 100 + k, 1, pattern) for k, n in enumerate(lengths(rep))]
+        xd, yd = [to_dev(v) for v in xs], [to_dev(v) for v in ys]
+        got = to_host(F.dot_many(fd.Field.make_desc(xd, yd), algo=algo))
+        assert same(got, oracle.dot_many(p, rep, xs, ys)), (p, rep, algo, pattern)
 
 
 @pytest.mark.parametrize("p,rep", [(32749, "zpz"), (2147483647, "mont"), (67108859, "fp64"),
@@ -122,22 +129,25 @@ def test_many_chunks_per_workgroup():
         x, y = stored(p, rep, n, 34, 0), stored(p, rep, n, 34, 1)
         assert same(to_host(F.dot(to_dev(x), to_dev(y)))[0], oracle.dot(p, rep, x, y))
     finally:
-        fd.tune_set("chunk.zpz", 65536)
-        fd.tune_set("wg_per_cu.zpz", 8)
+        fd.tune_set("chunk.zpz", None)
+        fd.tune_set("wg_per_cu.zpz", None)
 
 
 def test_centred_fold_path():
-    """A chunk long enough that the int32 accumulator must be flushed."""
+    """One chunk long enough that a lane's int32 accumulator must be flushed
+    to 64 bits several times."""
     p, rep = 251, "centred"
     F = field(p, rep)
     fd.tune_set("chunk.centred", 1 << 24)
+    fd.tune_set("min_chunk.centred", 1 << 24)
     try:
         n = (1 << 24) + 77
         for pattern in ("random", "maxprod"):
             x, y = stored(p, rep, n, 35, 0, pattern), stored(p, rep, n, 35, 1, pattern)
             assert same(to_host(F.dot(to_dev(x), to_dev(y)))[0], oracle.dot(p, rep, x, y))
     finally:
-        fd.tune_set("chunk.centred", 262144)
+        fd.tune_set("chunk.centred", None)
+        fd.tune_set("min_chunk.centred", None)
 
 
 @pytest.mark.parametrize("p,rep", [(32749, "zpz"), (2147483647, "mont"), (4294967291, "mont"),
