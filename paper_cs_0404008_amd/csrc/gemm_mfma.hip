@@ -1,10 +1,467 @@
-// Matrix-core (MFMA) kernels for the exact matrix product: placeholder until
-// the FP64 and int8 paths land; every call falls through to the exact
-// vector-ALU kernel.
+// Matrix-core (MFMA) kernels for the exact matrix product C = A B over GF(p).
+//
+// Exactness.  Every entry of C is a dot product (Sec. 1), so the delayed
+// reduction of Sec. 3.1 applies to the K loop: products of residues are
+// accumulated on the matrix cores and the accumulator is folded back to a
+// residue every K-block, with the block chosen so that no partial sum can
+// leave the exact range of the accumulator:
+//  * FP64: integral doubles are exact up to 2^53 (Eq. 1 with m = 53), and a
+//    sum of exact integers below 2^53 is the same whatever order the matrix
+//    core adds them in.  Residues are used as stored, or centred
+//    (Sec. 3.2.2) for primes whose squares leave too little room.
+//  * int8: centred residues of p < 2^8, 32-bit integer accumulation, folded
+//    before |sum| could reach 2^31 (the centred bound of Sec. 3.2.2).
+//
+// Operand layouts of the gfx950 instructions used (one wavefront):
+//  v_mfma_f64_16x16x4_f64: lane l holds A[l%16][l/16] and B[l/16][l%16]; its
+//    four results are D[4r + l/16][l%16], r = 0..3.
+//  v_mfma_i32_32x32x32_i8: lane l holds 16 int8 of row l%32 of A and of
+//    column l%32 of B, for the k-slots 16*(l/32) .. 16*(l/32)+15 (any
+//    assignment of k-slots works as long as A and B use the same one); its 16
+//    results are D[8(r/4) + 4(l/32) + r%4][l%32].
+#include <math.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "fdot_internal.h"
 
-fdot_status_t fd_launch_gemm_mfma(const fdot_field_s*, size_t, size_t, size_t, const void*, size_t,
-                                  const void*, size_t, void*, size_t, hipStream_t, bool* handled) {
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+namespace {
+
+// Global-memory load through an address-space-1 pointer (a global load, not
+// a flat one the compiler would have to wait for together with LDS traffic).
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+
+// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
+// b mod 8).  Remap so that each XCD gets a contiguous range of output tiles,
+// then walk tiles in bands of kBand tile-rows, so the tiles sharing A and B
+// panels run on the same XCD, close in time, and hit its L2.
+constexpr int kXcds = 8;
+constexpr int kBand = 8;
+__device__ __forceinline__ void tile_of(uint32_t b, uint32_t nblocks, uint32_t tiles_m,
+                                        uint32_t tiles_n, uint32_t* tm, uint32_t* tn) {
+  uint32_t t = b;
+  if (nblocks % kXcds == 0) t = (b % kXcds) * (nblocks / kXcds) + b / kXcds;
+  const uint32_t band_tiles = kBand * tiles_n;
+  const uint32_t band = t / band_tiles;
+  const uint32_t in_band = t % band_tiles;
+  const uint32_t rows = (tiles_m - band * kBand) < kBand ? (tiles_m - band * kBand) : kBand;
+  *tm = band * kBand + in_band % rows;
+  *tn = in_band / rows;
+}
+
+// ------------------------------------------------------------------ FP64
+constexpr int FM = 128, FN = 128, FK = 16;
+
+template <typename E, bool CENTRE>
+__device__ __forceinline__ double to_term(E v, const FieldK& F) {
+  double d = (double)v;
+  if (CENTRE) d = d > (double)F.half ? d - F.P : d;
+  return d;
+}
+
+__device__ __forceinline__ double fold_keep(double acc, const FieldK& F, bool centre) {
+  double r = fold_f64(acc, F);
+  if (centre) r = r > (double)F.half ? r - F.P : r;
+  return r;
+}
+
+// Two consecutive elements of a row as terms.  VEC: one 16-byte (double) or
+// 8-byte (uint32) load, the caller having checked alignment and bounds.
+template <typename E, bool CENTRE, bool VEC>
+__device__ __forceinline__ void load_pair(const E* base, uint64_t off, bool in0, bool in1,
+                                          const FieldK& F, double& t0, double& t1) {
+  if (VEC && in1) {
+    if constexpr (sizeof(E) == 8) {
+      typedef double d2 __attribute__((ext_vector_type(2)));
+      const d2 v = gld((const d2*)(base + off));
+      t0 = to_term<E, CENTRE>((E)v.x, F);
+      t1 = to_term<E, CENTRE>((E)v.y, F);
+    } else {
+      typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+      const u2 v = gld((const u2*)(base + off));
+      t0 = to_term<E, CENTRE>((E)v.x, F);
+      t1 = to_term<E, CENTRE>((E)v.y, F);
+    }
+  } else {
+    t0 = in0 ? to_term<E, CENTRE>(gld(base + off), F) : 0.0;
+    t1 = in1 ? to_term<E, CENTRE>(gld(base + off + 1), F) : 0.0;
+  }
+}
+
+// C tile 128 x 128 per workgroup; wavefront w owns rows 64*(w/2).., columns
+// 64*(w%2).. as 4 x 4 blocks of 16 x 16.  K is staged through LDS 16 at a
+// time (A row-major with a padded pitch, B as stored), consumed in 4 steps of
+// one MFMA K (4); the next K-tile is fetched into registers while the current
+// one is multiplied.  The accumulators are folded after every fold_sub MFMA
+// steps (SUBFOLD, for block lengths below one K-tile) or K-tiles.
+constexpr int FAP = FK + 1;    // A pitch in LDS (doubles): conflict-free column reads
+constexpr int FBP = FN + 2;    // B pitch in LDS (doubles): keeps 16-byte alignment
+template <typename E, bool CENTRE, bool VEC, bool SUBFOLD>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const FieldK F, int rep, uint32_t M,
+                                                       uint32_t N, uint32_t K, const E* A,
+                                                       uint64_t lda, const E* B, uint64_t ldb,
+                                                       void* C, uint64_t ldc, uint32_t fold_sub) {
+  __shared__ double As[FM * FAP];
+  __shared__ double Bs[FK * FBP];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const uint32_t tiles_m = (M + FM - 1) / FM, tiles_n = (N + FN - 1) / FN;
+  uint32_t tm, tn;
+  tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, &tm, &tn);
+  const uint32_t m0 = tm * FM, n0 = tn * FN;
+  const uint32_t wm = (w >> 1) * 64, wn = (w & 1) * 64;
+  // This thread's share of a K-tile: 4 pairs of A (row ar + 32q, columns
+  // ak, ak+1) and 4 pairs of B (row bk + 4q, columns bc, bc+1).
+  const uint32_t ar = tid / 8, ak = 2 * (tid % 8);
+  const uint32_t bk = tid / 64, bc = 2 * (tid % 64);
+  double ra[4][2], rb[4][2];
+  auto fetch = [&](uint32_t k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t gm = m0 + ar + 32 * q, gk = k0 + ak;
+      const bool rin = gm < M;
+      load_pair<E, CENTRE, VEC>(A, (uint64_t)gm * lda + gk, rin && gk < K, rin && gk + 1 < K, F,
+                                ra[q][0], ra[q][1]);
+      const uint32_t gk2 = k0 + bk + 4 * q, gn = n0 + bc;
+      const bool kin = gk2 < K;
+      load_pair<E, CENTRE, VEC>(B, (uint64_t)gk2 * ldb + gn, kin && gn < N, kin && gn + 1 < N, F,
+                                rb[q][0], rb[q][1]);
+    }
+  };
+  v4d acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+  uint32_t sub = 0;
+  if (K > 0) fetch(0);
+  for (uint32_t k0 = 0; k0 < K; k0 += FK) {
+    __syncthreads();  // every wave is done reading the previous tile
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      As[(ar + 32 * q) * FAP + ak] = ra[q][0];
+      As[(ar + 32 * q) * FAP + ak + 1] = ra[q][1];
+      Bs[(bk + 4 * q) * FBP + bc] = rb[q][0];
+      Bs[(bk + 4 * q) * FBP + bc + 1] = rb[q][1];
+    }
+    __syncthreads();
+    if (k0 + FK < K) fetch(k0 + FK);
+#pragma unroll
+    for (int s = 0; s < FK / 4; ++s) {
+      const uint32_t kr = 4 * s + lane / 16;
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[(wm + 16 * i + lane % 16) * FAP + kr];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kr * FBP + wn + 16 * j + lane % 16];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      if (SUBFOLD && ++sub == fold_sub) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][j][r] = fold_keep(acc[i][j][r], F, CENTRE);
+        sub = 0;
+      }
+    }
+    // Without SUBFOLD, fold_sub counts whole K-tiles.
+    if (!SUBFOLD && ++sub == fold_sub) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[i][j][r] = fold_keep(acc[i][j][r], F, CENTRE);
+      sub = 0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t gm = m0 + wm + 16 * i + 4 * r + lane / 16;
+        const uint32_t gn = n0 + wn + 16 * j + lane % 16;
+        if (gm < M && gn < N) {
+          const uint32_t v = (uint32_t)fold_f64(acc[i][j][r], F);
+          const uint64_t o = (uint64_t)gm * ldc + gn;
+          if (rep == FDOT_REP_FP64) ((double*)C)[o] = (double)v;
+          else if (rep == FDOT_REP_MONT_U32) ((uint32_t*)C)[o] = redc(v, F);
+          else ((uint32_t*)C)[o] = v;
+        }
+      }
+}
+
+// ------------------------------------------------------------------ int8
+constexpr int IPAD = 16;
+
+// Signed 32-bit value to its centred residue, through a double quotient.
+__device__ __forceinline__ int32_t centred_mod(int32_t v, const FieldK& F) {
+  const double q = floor((double)v * F.invP);
+  int32_t r = v - (int32_t)q * (int32_t)F.p32;
+  r = r >= (int32_t)F.p32 ? r - (int32_t)F.p32 : r;
+  r = r < 0 ? r + (int32_t)F.p32 : r;
+  return r > F.half ? r - (int32_t)F.p32 : r;
+}
+
+// C tile (64 BI) x (64 BJ) per workgroup from A (M x K, int8 row-major) and
+// Bt = B^T (N x K, int8 row-major); wavefront w owns a (32 BI) x (32 BJ)
+// sub-tile as BI x BJ blocks of 32 x 32.  K is staged IK at a time (rows
+// padded by 16 bytes in LDS, so the 16-byte fragment reads of 16 lanes hit
+// distinct banks) and consumed in MFMA steps of 32; the next K-tile is
+// fetched into registers while the current one is multiplied.  Accumulators
+// are folded (to centred residues) after every fold_steps stagings.
+template <int BI, int BJ, int IK, bool VEC>
+__global__ __launch_bounds__(256) void gemm_i8_kernel(const FieldK F, uint32_t M, uint32_t N,
+                                                      uint32_t K, const int8_t* A, uint64_t lda,
+                                                      const int8_t* Bt, uint64_t ldbt, int8_t* C,
+                                                      uint64_t ldc, uint32_t fold_steps) {
+  constexpr int TM = 64 * BI, TN = 64 * BJ;
+  constexpr int NA = TM * IK / 16 / 256, NB = TN * IK / 16 / 256;  // 16-byte vectors per thread
+  __shared__ __attribute__((aligned(16))) int8_t As[TM][IK + IPAD];
+  __shared__ __attribute__((aligned(16))) int8_t Bs[TN][IK + IPAD];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const uint32_t tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
+  uint32_t tm, tn;
+  tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, &tm, &tn);
+  const uint32_t m0 = tm * TM, n0 = tn * TN;
+  const uint32_t wm = (w >> 1) * 32 * BI, wn = (w & 1) * 32 * BJ;
+  v4i pa[NA], pb[NB];
+  auto fetch_row = [&](const int8_t* base, uint64_t ld, uint32_t row, uint32_t rows, uint32_t gk) {
+    v4i v = {0, 0, 0, 0};
+    if (row >= rows) return v;
+    if (VEC && gk + 16 <= K) return gld((const v4i*)(base + (uint64_t)row * ld + gk));
+    int8_t t[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t[i] = gk + i < K ? gld(base + (uint64_t)row * ld + gk + i) : (int8_t)0;
+    __builtin_memcpy(&v, t, 16);
+    return v;
+  };
+  auto fetch = [&](uint32_t k0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const uint32_t e = tid + 256u * q;
+      pa[q] = fetch_row(A, lda, m0 + e / (IK / 16), M, k0 + (e % (IK / 16)) * 16);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const uint32_t e = tid + 256u * q;
+      pb[q] = fetch_row(Bt, ldbt, n0 + e / (IK / 16), N, k0 + (e % (IK / 16)) * 16);
+    }
+  };
+  v16i acc[BI][BJ];
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
+  uint32_t steps = 0;
+  if (K > 0) fetch(0);
+  for (uint32_t k0 = 0; k0 < K; k0 += IK) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const uint32_t e = tid + 256u * q;
+      *(v4i*)&As[e / (IK / 16)][(e % (IK / 16)) * 16] = pa[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const uint32_t e = tid + 256u * q;
+      *(v4i*)&Bs[e / (IK / 16)][(e % (IK / 16)) * 16] = pb[q];
+    }
+    __syncthreads();
+    if (k0 + IK < K) fetch(k0 + IK);
+#pragma unroll
+    for (int s = 0; s < IK / 32; ++s) {
+      const uint32_t kc = 32 * s + 16 * (lane / 32);
+      v4i a[BI], b[BJ];
+#pragma unroll
+      for (int i = 0; i < BI; ++i) a[i] = *(const v4i*)&As[wm + 32 * i + lane % 32][kc];
+#pragma unroll
+      for (int j = 0; j < BJ; ++j) b[j] = *(const v4i*)&Bs[wn + 32 * j + lane % 32][kc];
+#pragma unroll
+      for (int i = 0; i < BI; ++i)
+#pragma unroll
+        for (int j = 0; j < BJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (++steps == fold_steps) {
+#pragma unroll
+      for (int i = 0; i < BI; ++i)
+#pragma unroll
+        for (int j = 0; j < BJ; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[i][j][r] = centred_mod(acc[i][j][r], F);
+      steps = 0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t gm = m0 + wm + 32 * i + 8 * (r / 4) + 4 * (lane / 32) + r % 4;
+        const uint32_t gn = n0 + wn + 32 * j + lane % 32;
+        if (gm < M && gn < N) C[(uint64_t)gm * ldc + gn] = (int8_t)centred_mod(acc[i][j][r], F);
+      }
+}
+
+// Bt = B^T for int8 matrices, 64 x 64 tiles through LDS.
+__global__ __launch_bounds__(256) void transpose_i8_kernel(const int8_t* B, uint64_t ldb, uint32_t K,
+                                                           uint32_t N, int8_t* Bt, uint64_t ldbt) {
+  __shared__ int8_t t[64][65];
+  const uint32_t k0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  for (uint32_t e = threadIdx.x; e < 64 * 64; e += 256) {
+    const uint32_t r = e / 64, c = e % 64;
+    t[r][c] = (k0 + r < K && n0 + c < N) ? B[(uint64_t)(k0 + r) * ldb + n0 + c] : (int8_t)0;
+  }
+  __syncthreads();
+  for (uint32_t e = threadIdx.x; e < 64 * 64; e += 256) {
+    const uint32_t r = e / 64, c = e % 64;  // r: n, c: k
+    if (n0 + r < N && k0 + c < K) Bt[(uint64_t)(n0 + r) * ldbt + k0 + c] = t[c][r];
+  }
+}
+
+// Scratch for the transposed B, one buffer per (device, stream), grown on
+// demand (outside graph capture).
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, std::pair<void*, size_t>> g_scratch;
+
+fdot_status_t scratch_for(hipStream_t s, size_t bytes, void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return FDOT_E_DEVICE;
+  std::lock_guard<std::mutex> g(g_mu);
+  auto& e = g_scratch[std::make_pair(dev, s)];
+  if (e.second >= bytes) {
+    *out = e.first;
+    return FDOT_OK;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return FDOT_E_BUSY;
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return FDOT_E_NOMEM;
+  if (e.first) {
+    hipStreamSynchronize(s);
+    hipFree(e.first);
+  }
+  e = std::make_pair(p, bytes);
+  *out = p;
+  return FDOT_OK;
+}
+
+// Largest lambda with carry + lambda*h^2 <= limit (h = largest |term|).
+uint64_t lambda_carried(uint64_t limit, uint64_t h, uint64_t carry) {
+  if (h == 0) return ~0ull;
+  const unsigned __int128 hh = (unsigned __int128)h * h;
+  if (limit < carry) return 0;
+  const unsigned __int128 l = (limit - carry) / hh;
+  return l > 0xFFFFFFFFull ? 0xFFFFFFFFull : (uint64_t)l;
+}
+
+}  // namespace
+
+fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, size_t K,
+                                  const void* A, size_t lda, const void* B, size_t ldb, void* C,
+                                  size_t ldc, hipStream_t s, bool* handled) {
   *handled = false;
-  return FDOT_E_UNSUPPORTED;
+  const fdot_field_info_t& I = f->info;
+  if (M > 0x7FFFFFFFull || N > 0x7FFFFFFFull || K > 0x7FFFFFFFull) return FDOT_E_UNSUPPORTED;
+  const uint64_t p = I.p, h = (p - 1) / 2;
+  if (I.rep == FDOT_REP_CENTRED_I8) {
+    // |centred residue| <= h; carried residue after a fold also <= h.
+    const uint64_t lam = lambda_carried(0x7FFFFFFFull, h, h);
+    if (lam < 128 || fd_tune("gemm.i8.disable", 0)) return FDOT_E_UNSUPPORTED;
+    *handled = true;
+    void* bt = nullptr;
+    fdot_status_t st = scratch_for(s, (size_t)N * K + 16, &bt);
+    if (st != FDOT_OK) return st;
+    if (K > 0) {
+      hipLaunchKernelGGL(transpose_i8_kernel, dim3((unsigned)((N + 63) / 64), (unsigned)((K + 63) / 64)),
+                         dim3(256), 0, s, (const int8_t*)B, (uint64_t)ldb, (uint32_t)K, (uint32_t)N,
+                         (int8_t*)bt, (uint64_t)K);
+      if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
+    }
+    // Workgroup tile: 0 = 256 x 256, 1 = 256 x 128, 2 = 128 x 128; K-tile 64 or 128.
+    const int64_t shape = fd_tune("gemm.i8.tile", 2);
+    const int64_t kt = fd_tune("gemm.i8.ktile", 128) == 64 ? 64 : 128;
+    const uint32_t fold_steps = (uint32_t)(lam / (uint64_t)kt);
+    const bool vec = (lda % 16 == 0) && (((uintptr_t)A) % 16 == 0) && (K % 16 == 0);
+    const uint32_t TM = shape == 2 ? 128 : 256, TN = shape == 0 ? 256 : 128;
+    const uint64_t tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+    if (tiles > 0x7FFFFFFFull) return FDOT_E_INVALID_ARG;
+#define FD_I8_LAUNCH(BI, BJ, KT, V)                                                               \
+  hipLaunchKernelGGL((gemm_i8_kernel<BI, BJ, KT, V>), dim3((unsigned)tiles), dim3(256), 0, s,     \
+                     f->k, (uint32_t)M, (uint32_t)N, (uint32_t)K, (const int8_t*)A,                \
+                     (uint64_t)lda, (const int8_t*)bt, (uint64_t)K, (int8_t*)C, (uint64_t)ldc,    \
+                     fold_steps)
+#define FD_I8_SHAPE(KT)                                                                            \
+  if (shape == 2) { if (vec) FD_I8_LAUNCH(2, 2, KT, true); else FD_I8_LAUNCH(2, 2, KT, false); }  \
+  else if (shape == 1) { if (vec) FD_I8_LAUNCH(4, 2, KT, true); else FD_I8_LAUNCH(4, 2, KT, false); } \
+  else { if (vec) FD_I8_LAUNCH(4, 4, KT, true); else FD_I8_LAUNCH(4, 4, KT, false); }
+    if (kt == 64) { FD_I8_SHAPE(64) } else { FD_I8_SHAPE(128) }
+#undef FD_I8_SHAPE
+#undef FD_I8_LAUNCH
+    return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
+  }
+  if (I.rep != FDOT_REP_FP64 && I.rep != FDOT_REP_ZPZ_U32 && I.rep != FDOT_REP_MONT_U32)
+    return FDOT_E_UNSUPPORTED;
+  if (fd_tune("gemm.f64.disable", 0)) return FDOT_E_UNSUPPORTED;
+  // Exact double sums up to 2^53.  Residues as stored: terms <= (p-1)^2,
+  // carried residue <= p-1.  Centred: terms <= h^2, carried |residue| <= h.
+  const uint64_t lim = 1ull << 53;
+  const uint64_t lam_plain = lambda_carried(lim, p - 1, p - 1);
+  const uint64_t lam_centre = lambda_carried(lim, h, h);
+  bool centre;
+  uint64_t lam;
+  if (lam_plain >= 64 || lam_plain >= lam_centre) {
+    centre = false;
+    lam = lam_plain;
+  } else {
+    centre = true;
+    lam = lam_centre;
+  }
+  if (lam < 4) return FDOT_E_UNSUPPORTED;
+  *handled = true;
+  const uint64_t tiles = ((M + FM - 1) / FM) * ((N + FN - 1) / FN);
+  if (tiles > 0x7FFFFFFFull) return FDOT_E_INVALID_ARG;
+  const bool subfold = lam < FK;
+  const uint32_t fold_sub = (uint32_t)(subfold ? lam / 4 : lam / FK);
+  const dim3 grid((unsigned)tiles), block(256);
+#define FD_F64_LAUNCH(E, CEN, V, SF)                                                              \
+  hipLaunchKernelGGL((gemm_f64_kernel<E, CEN, V, SF>), grid, block, 0, s, f->k, I.rep,            \
+                     (uint32_t)M, (uint32_t)N, (uint32_t)K, (const E*)A, (uint64_t)lda,           \
+                     (const E*)B, (uint64_t)ldb, C, (uint64_t)ldc, fold_sub)
+#define FD_F64_PICK(E, CEN)                                                                        \
+  if (vec) { if (subfold) FD_F64_LAUNCH(E, CEN, true, true); else FD_F64_LAUNCH(E, CEN, true, false); } \
+  else { if (subfold) FD_F64_LAUNCH(E, CEN, false, true); else FD_F64_LAUNCH(E, CEN, false, false); }
+  // Pair loads need both rows of A and B to start on a pair boundary.
+  const size_t esz = I.elem_bytes, pair = 2 * esz;
+  const bool vec = lda % 2 == 0 && ldb % 2 == 0 && ((uintptr_t)A) % pair == 0 &&
+                   ((uintptr_t)B) % pair == 0;
+  if (I.rep == FDOT_REP_FP64) {
+    if (centre) { FD_F64_PICK(double, true) } else { FD_F64_PICK(double, false) }
+  } else {
+    if (centre) { FD_F64_PICK(uint32_t, true) } else { FD_F64_PICK(uint32_t, false) }
+  }
+#undef FD_F64_PICK
+#undef FD_F64_LAUNCH
+  return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
 }

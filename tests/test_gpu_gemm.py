@@ -1,0 +1,131 @@
+"""GPU parity of the matrix forms (fgemv_modp, fgemm_modp) against the oracle.
+
+Covers every kernel path: FP64 matrix cores with residues as stored and
+centred, classical and Montgomery residues converted on load, int8 matrix
+cores on centred residues, and the exact vector-ALU kernel; ragged shapes,
+K beyond the fold bound (so the in-loop folds run), unaligned leading
+dimensions, and the full 8192 x 8192 x 4096 products on sampled entries.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_helpers import same, stored, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+fd = pytest.importorskip("paper_cs_0404008_amd")
+
+FIELDS = [
+    (1048573, "fp64"),       # FP64 MFMA, residues as stored
+    (67108859, "fp64"),      # FP64 MFMA, centred, fold every 8 products
+    (65521, "zpz"),          # FP64 MFMA from uint32 residues
+    (32749, "mont"),         # FP64 MFMA on Montgomery residues, one REDC at the end
+    (251, "centred"),        # int8 MFMA
+    (2147483647, "zpz"),     # vector-ALU kernel
+    (4294967291, "mont"),    # vector-ALU kernel
+    (32749, "zech"),         # vector-ALU kernel
+]
+SHAPES = [(1, 1, 1), (7, 5, 9), (130, 129, 33), (257, 300, 100), (128, 128, 64), (64, 48, 1000),
+          (3, 200, 17)]
+
+_fields = {}
+
+
+def field(p, rep):
+    if (p, rep) not in _fields:
+        _fields[(p, rep)] = fd.Field(p, rep)
+    return _fields[(p, rep)]
+
+
+def mat(p, rep, rows, cols, seed, stream, pattern="random"):
+    return stored(p, rep, rows * cols, seed, stream, pattern).reshape(rows, cols)
+
+
+@pytest.mark.parametrize("p,rep", FIELDS, ids=lambda v: str(v))
+def test_gemm_matches_oracle(p, rep):
+    F = field(p, rep)
+    for t, (M, N, K) in enumerate(SHAPES):
+        for pattern in ("random", "maxprod"):
+            A = mat(p, rep, M, K, 50 + t, 0, pattern)
+            B = mat(p, rep, K, N, 50 + t, 1, pattern)
+            got = to_host(F.gemm(to_dev(A), to_dev(B)))
+            assert same(got, oracle.gemm(p, rep, A, B)), (p, rep, M, N, K, pattern)
+
+
+@pytest.mark.parametrize("p,rep,K", [(1048573, "fp64", 3 * 8192 + 5), (67108859, "fp64", 301),
+                                     (65521, "zpz", 5000), (251, "centred", (1 << 18) + 3)])
+def test_gemm_folds_beyond_lambda(p, rep, K):
+    F = field(p, rep)
+    M, N = 40, 36
+    for pattern in ("random", "maxprod"):
+        A = mat(p, rep, M, K, 60, 0, pattern)
+        B = mat(p, rep, K, N, 60, 1, pattern)
+        got = to_host(F.gemm(to_dev(A), to_dev(B)))
+        assert same(got, oracle.gemm(p, rep, A, B)), (p, rep, K, pattern)
+
+
+@pytest.mark.parametrize("p,rep", [(251, "centred"), (1048573, "fp64"), (2147483647, "zpz")])
+def test_gemm_strided_operands(p, rep):
+    """Leading dimensions larger than the row length, not multiples of 16."""
+    F = field(p, rep)
+    M, N, K = 70, 45, 83
+    Aw = to_dev(mat(p, rep, M, K + 3, 61, 0))
+    Bw = to_dev(mat(p, rep, K, N + 5, 61, 1))
+    A, B = Aw[:, 1:K + 1], Bw[:, 2:N + 2]
+    C = torch.zeros((M, N + 7), dtype=F.dtype, device="cuda")
+    F.gemm(A, B, out=C[:, :N])
+    want = oracle.gemm(p, rep, to_host(A).copy(), to_host(B).copy())
+    assert same(to_host(C[:, :N]).copy(), want)
+    assert not to_host(C[:, N:]).any()  # nothing written past the output view
+
+
+@pytest.mark.parametrize("p,rep", FIELDS, ids=lambda v: str(v))
+def test_gemv_matches_oracle(p, rep):
+    F = field(p, rep)
+    for t, (m, n) in enumerate([(1, 1), (5, 3), (33, 1000), (257, 2049), (1000, 4099)]):
+        for pattern in ("random", "maxprod"):
+            A = mat(p, rep, m, n, 70 + t, 0, pattern)
+            x = stored(p, rep, n, 70 + t, 1, pattern)
+            got = to_host(F.gemv(to_dev(A), to_dev(x)))
+            assert same(got, oracle.gemv(p, rep, A, x)), (p, rep, m, n, pattern)
+
+
+def test_gemm_special_cases():
+    p, rep = 1048573, "fp64"
+    F = field(p, rep)
+    A = mat(p, rep, 50, 40, 80, 0)
+    eye = np.eye(40, dtype=np.float64)
+    assert same(to_host(F.gemm(to_dev(A), to_dev(eye))), A)
+    # K = 0: C is the zero matrix
+    Z = to_host(F.gemm(torch.empty((5, 0), dtype=torch.float64, device="cuda"),
+                       torch.empty((0, 6), dtype=torch.float64, device="cuda")))
+    assert not Z.any()
+
+
+@pytest.mark.parametrize("p,rep,dtype", [(251, "centred", torch.int8),
+                                         (1048573, "fp64", torch.float64)])
+def test_gemm_full_size_sampled(p, rep, dtype):
+    """The 8192 x 8192 times 8192 x 4096 product, checked on 4096 entries."""
+    M, K, N = 8192, 8192, 4096
+    F = field(p, rep)
+    m, lo = (p, 0) if rep != "centred" else (p, -((p - 1) // 2))
+    A = torch.empty((M, K), dtype=dtype, device="cuda")
+    B = torch.empty((K, N), dtype=dtype, device="cuda")
+    synth.fill_device(A, 4, 0, m, lo)
+    synth.fill_device(B, 4, 1, m, lo)
+    C = to_host(F.gemm(A, B))
+    del A, B
+    torch.cuda.empty_cache()
+    Ah = synth.uniform_int(4, 0, M * K, m, lo).reshape(M, K)
+    Bh = synth.uniform_int(4, 1, K * N, m, lo).reshape(K, N)
+    Ah = Ah.astype(np.int8 if rep == "centred" else np.float64)
+    Bh = Bh.astype(np.int8 if rep == "centred" else np.float64)
+    rows = synth.uniform_int(4, 2, 4096, M)
+    cols = synth.uniform_int(4, 3, 4096, N)
+    rows[:4] = [0, 0, M - 1, M - 1]
+    cols[:4] = [0, N - 1, 0, N - 1]
+    want = oracle.gemm_entries(p, rep, Ah, Bh, rows, cols)
+    assert same(C[rows, cols], want)
