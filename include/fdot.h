@@ -184,6 +184,11 @@ fdot_status_t fdot_zech_tables(uint64_t p, uint16_t* value, uint16_t* index,
  * tables (Zech) to the current device.  The handle is immutable and may be
  * shared by threads and streams; destroy it once no enqueued work uses it. */
 fdot_status_t fdot_field_create(uint64_t p, fdot_rep_t rep, fdot_field_t* out);
+/* A field handle with its constants only (no device tables, no GPU touched):
+ * usable where only the field's description is needed (request planning, the
+ * request server in fake-device mode); compute calls on it return
+ * FDOT_E_UNSUPPORTED. */
+fdot_status_t fdot_field_create_host(uint64_t p, fdot_rep_t rep, fdot_field_t* out);
 fdot_status_t fdot_field_destroy(fdot_field_t f);
 fdot_status_t fdot_field_info(fdot_field_t f, fdot_field_info_t* out);
 
@@ -240,6 +245,83 @@ fdot_status_t fdot_workspace_reserve(void* stream, size_t count);
  * lines) is read at the first tuning lookup. */
 fdot_status_t fdot_tune_set(const char* key, int64_t value);
 fdot_status_t fdot_tune_get(const char* key, int64_t* value);
+
+/* ------------------------------------------------------------------ serving
+ * A request server for streams of dot / matrix-vector / matrix products of
+ * mixed primes and sizes (the dot product as the building block of higher
+ * routines, Sec. 1, served continuously).  Requests arriving while others
+ * run are admitted as soon as an in-flight slot and enough of the HBM
+ * budget are free; at every scheduling step the admitted dot requests of one
+ * field are fused into one batched launch, and launches are spread over
+ * several HIP streams so that their work overlaps on the device.  Results
+ * are exact, so a request's result is the same alone and in any mix.
+ * Operands stay device-resident and owned by the caller until the request is
+ * done; the server never copies or frees them. */
+
+typedef enum { FDOT_OP_DOT = 0, FDOT_OP_GEMV = 1, FDOT_OP_GEMM = 2 } fdot_op_t;
+
+typedef struct {
+  int32_t op;          /* fdot_op_t */
+  int32_t reserved;
+  fdot_field_t field;
+  const void* a;       /* DOT: x (n);  GEMV: A (m x n);  GEMM: A (m x k) */
+  const void* b;       /* DOT: y (n);  GEMV: x (n);      GEMM: B (k x n) */
+  void* out;           /* DOT: 1 elem; GEMV: y (m);      GEMM: C (m x n) */
+  uint64_t m, n, k;    /* dense row-major operands, leading dimension = row length */
+  uint64_t footprint;  /* device bytes charged against the budget while the request
+                          is admitted; 0 = its operand and result bytes */
+} fdot_request_t;
+
+typedef struct {
+  uint64_t hbm_budget;   /* admitted footprint allowed at once (bytes) */
+  uint32_t max_inflight; /* admitted requests at once */
+  uint32_t max_queue;    /* waiting requests before submit returns FDOT_E_BUSY */
+  uint32_t streams;      /* HIP streams the launches are spread over */
+  uint32_t max_batch;    /* dot requests fused into one launch */
+  uint32_t fake_device;  /* 1: no GPU; completions are simulated (scheduler tests) */
+  uint32_t plain;        /* 1: no batching: one launch per request, one stream,
+                            arrival order (the comparison baseline) */
+} fdot_server_cfg_t;
+
+typedef struct {
+  uint64_t submit_ns;    /* steady-clock times of the request's life */
+  uint64_t admit_ns;
+  uint64_t launch_ns;
+  uint64_t done_ns;      /* when the scheduler saw its launch complete */
+  int32_t status;        /* FDOT_OK, or the error of its launch */
+  uint32_t batch_size;   /* requests carried by the same launch */
+} fdot_timing_t;
+
+typedef struct {
+  uint64_t submitted, completed, rejected;
+  uint64_t launches;            /* kernel launch groups issued */
+  uint64_t peak_footprint;      /* largest admitted footprint seen */
+  uint32_t peak_inflight;       /* largest number of admitted requests seen */
+  uint32_t reserved;
+} fdot_server_stats_t;
+
+typedef struct fdot_server_s* fdot_server_t;
+
+/* Start a server (its scheduling thread and streams) on the current device.
+ * cfg NULL = defaults (64 GiB budget, 256 slots, 4096 queue, 4 streams,
+ * 4096 per batch). */
+fdot_status_t fdot_server_create(const fdot_server_cfg_t* cfg, fdot_server_t* out);
+/* Queue a request; *ticket identifies it.  FDOT_E_BUSY: the queue is full;
+ * FDOT_E_NOMEM: its footprint exceeds the whole budget; FDOT_E_INVALID_ARG:
+ * malformed request.  Thread-safe. */
+fdot_status_t fdot_server_submit(fdot_server_t s, const fdot_request_t* req, uint64_t* ticket);
+/* *done = 1 once the request's result is in place (timing filled in). */
+fdot_status_t fdot_server_poll(fdot_server_t s, uint64_t ticket, int* done, fdot_timing_t* t);
+/* Block until every submitted request is done, or timeout_ms passes
+ * (FDOT_E_BUSY on timeout). */
+fdot_status_t fdot_server_drain(fdot_server_t s, uint64_t timeout_ms);
+/* Load generator: submit reqs[i] when arrival_s[i] seconds (non-decreasing)
+ * have passed since the call, wait for all, fill timings[i]. */
+fdot_status_t fdot_server_replay(fdot_server_t s, const fdot_request_t* reqs,
+                                 const double* arrival_s, size_t count, fdot_timing_t* timings);
+fdot_status_t fdot_server_stats(fdot_server_t s, fdot_server_stats_t* out);
+/* Drain, stop the scheduling thread, release streams and buffers. */
+fdot_status_t fdot_server_destroy(fdot_server_t s);
 
 #ifdef __cplusplus
 }

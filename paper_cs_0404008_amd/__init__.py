@@ -65,6 +65,7 @@ _sig("fdot_max_prime", [_i32, ctypes.c_uint32, ctypes.POINTER(_u64)])
 _sig("fdot_host_fold", [ctypes.POINTER(FieldInfo), _i32, _u64, ctypes.POINTER(_u64)])
 _sig("fdot_zech_tables", [_u64, _vp, _vp, _vp])
 _sig("fdot_field_create", [_u64, _i32, ctypes.POINTER(_vp)])
+_sig("fdot_field_create_host", [_u64, _i32, ctypes.POINTER(_vp)])
 _sig("fdot_field_destroy", [_vp])
 _sig("fdot_field_info", [_vp, ctypes.POINTER(FieldInfo)])
 _sig("fdot_encode", [_vp, _vp, _vp, _sz, _vp])
@@ -172,11 +173,15 @@ def workspace_reserve(count: int, stream=None) -> None:
 class Field:
     """GF(p) in one representation; the handle owns the device tables."""
 
-    def __init__(self, p: int, rep: str = "zpz"):
+    def __init__(self, p: int, rep: str = "zpz", host_only: bool = False):
         self.p = int(p)
         self.rep = rep
         h = _vp()
-        _check(_lib.fdot_field_create(self.p, REPS[rep], ctypes.byref(h)), "fdot_field_create")
+        if host_only:  # constants only, no GPU (compute calls are refused)
+            _check(_lib.fdot_field_create_host(self.p, REPS[rep], ctypes.byref(h)),
+                   "fdot_field_create_host")
+        else:
+            _check(_lib.fdot_field_create(self.p, REPS[rep], ctypes.byref(h)), "fdot_field_create")
         self._h = h
         info = FieldInfo()
         _check(_lib.fdot_field_info(h, ctypes.byref(info)), "fdot_field_info")
@@ -274,3 +279,109 @@ class Field:
         _check(_lib.fgemm_modp(self._h, M, N, K, _ptr(A), A.stride(0), _ptr(B), B.stride(0),
                                _ptr(out), out.stride(0), _stream(stream)), "fgemm_modp")
         return out
+
+
+# -------------------------------------------------------------------- serving
+OPS = {"dot": 0, "gemv": 1, "gemm": 2}
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("reserved", ctypes.c_int32), ("field", _vp),
+                ("a", _vp), ("b", _vp), ("out", _vp), ("m", _u64), ("n", _u64), ("k", _u64),
+                ("footprint", _u64)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", _u64), ("max_inflight", ctypes.c_uint32),
+                ("max_queue", ctypes.c_uint32), ("streams", ctypes.c_uint32),
+                ("max_batch", ctypes.c_uint32), ("fake_device", ctypes.c_uint32),
+                ("plain", ctypes.c_uint32)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("submit_ns", _u64), ("admit_ns", _u64), ("launch_ns", _u64), ("done_ns", _u64),
+                ("status", ctypes.c_int32), ("batch_size", ctypes.c_uint32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", _u64), ("completed", _u64), ("rejected", _u64), ("launches", _u64),
+                ("peak_footprint", _u64), ("peak_inflight", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+_sig("fdot_server_create", [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)])
+_sig("fdot_server_submit", [_vp, ctypes.POINTER(Request), ctypes.POINTER(_u64)])
+_sig("fdot_server_poll", [_vp, _u64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Timing)])
+_sig("fdot_server_drain", [_vp, _u64])
+_sig("fdot_server_replay", [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_double), _sz,
+                            ctypes.POINTER(Timing)])
+_sig("fdot_server_stats", [_vp, ctypes.POINTER(ServerStats)])
+_sig("fdot_server_destroy", [_vp])
+
+
+def make_request(op: str, field: "Field", a, b, out, m: int = 0, n: int = 0, k: int = 0,
+                 footprint: int = 0) -> Request:
+    """A request on device tensors (a, b, out) of field's dtype; a/b/out may
+    also be raw device addresses (ints)."""
+    addr = lambda t: t if isinstance(t, int) else t.data_ptr()  # noqa: E731
+    return Request(OPS[op], 0, field.handle, addr(a), addr(b), addr(out), m, n, k, footprint)
+
+
+class Server:
+    """The continuous-batching request server of libfdot (one GPU)."""
+
+    def __init__(self, hbm_budget: int = 0, max_inflight: int = 0, max_queue: int = 0,
+                 streams: int = 0, max_batch: int = 0, fake_device: bool = False,
+                 plain: bool = False):
+        cfg = ServerConfig(hbm_budget, max_inflight, max_queue, streams, max_batch,
+                           1 if fake_device else 0, 1 if plain else 0)
+        h = _vp()
+        _check(_lib.fdot_server_create(ctypes.byref(cfg), ctypes.byref(h)), "fdot_server_create")
+        self._h = h
+
+    def close(self, _destroy=_lib.fdot_server_destroy):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def submit(self, req: Request) -> int:
+        t = _u64()
+        _check(_lib.fdot_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)),
+               "fdot_server_submit")
+        return t.value
+
+    def try_submit(self, req: Request):
+        """(status, ticket) without raising."""
+        t = _u64()
+        st = _lib.fdot_server_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+        return st, t.value
+
+    def poll(self, ticket: int):
+        done = ctypes.c_int()
+        tm = Timing()
+        _check(_lib.fdot_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(tm)),
+               "fdot_server_poll")
+        return bool(done.value), tm
+
+    def drain(self, timeout_ms: int = 600000) -> None:
+        _check(_lib.fdot_server_drain(self._h, timeout_ms), "fdot_server_drain")
+
+    def replay(self, reqs, arrivals):
+        """Submit reqs[i] at arrivals[i] seconds after the call; returns the
+        timings (structured numpy array, nanoseconds)."""
+        import numpy as np
+        n = len(reqs)
+        arr = (Request * max(n, 1))(*reqs)
+        at = (ctypes.c_double * max(n, 1))(*[float(x) for x in arrivals])
+        tm = (Timing * max(n, 1))()
+        _check(_lib.fdot_server_replay(self._h, arr, at, n, tm), "fdot_server_replay")
+        dt = np.dtype([("submit_ns", np.uint64), ("admit_ns", np.uint64), ("launch_ns", np.uint64),
+                       ("done_ns", np.uint64), ("status", np.int32), ("batch_size", np.uint32)])
+        return np.frombuffer(bytes(tm), dtype=dt, count=n).copy()
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(_lib.fdot_server_stats(self._h, ctypes.byref(s)), "fdot_server_stats")
+        return {name: getattr(s, name) for name, _ in s._fields_ if name != "reserved"}

@@ -1052,3 +1052,22 @@ fdot_status_t fd_launch_gemv(const fdot_field_s* f, size_t m, size_t n, const vo
   }
   return FDOT_E_UNSUPPORTED;
 }
+
+// Copy results[i] (elem_bytes each) to the output pointer dst[i]: used by the
+// request server to hand each fused dot product its own output.
+__global__ void scatter_kernel(const uint8_t* src, void* const* dst, uint64_t count, uint32_t eb) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint8_t* d = (uint8_t*)dst[i];
+    for (uint32_t b = 0; b < eb; ++b) d[b] = src[i * eb + b];
+  }
+}
+
+fdot_status_t fd_launch_scatter(const void* src, void* const* dst, size_t count, uint32_t elem_bytes,
+                                hipStream_t s) {
+  if (count == 0) return FDOT_OK;
+  const unsigned blocks = (unsigned)((count + 255) / 256 < 1024 ? (count + 255) / 256 : 1024);
+  hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(256), 0, s, (const uint8_t*)src, dst,
+                     (uint64_t)count, elem_bytes);
+  return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
+}

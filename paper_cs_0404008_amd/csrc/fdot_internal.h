@@ -13,6 +13,7 @@ struct fdot_field_s {
   fdot_field_info_t info;
   FieldK k;             // device-ready constants (table pointers on device)
   int device;
+  bool host_only;       // constants only: no device tables, no compute
   uint16_t* d_zval;     // Zech tables on the device (owned)
   uint16_t* d_zplus1;
   uint16_t* d_zidx;

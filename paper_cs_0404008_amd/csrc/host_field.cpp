@@ -325,3 +325,21 @@ fdot_status_t fdot_field_info(fdot_field_t f, fdot_field_info_t* out) {
 }
 
 }  // extern "C"
+
+extern "C" fdot_status_t fdot_field_create_host(uint64_t p, fdot_rep_t rep, fdot_field_t* out) {
+  if (!out) return FDOT_E_INVALID_ARG;
+  *out = nullptr;
+  fdot_field_info_t I;
+  fdot_status_t st = fd_fill_params(p, rep, &I);
+  if (st != FDOT_OK) return st;
+  fdot_field_s* f = new (std::nothrow) fdot_field_s;
+  if (!f) return FDOT_E_NOMEM;
+  memset(f, 0, sizeof(*f));
+  f->info = I;
+  f->info.table_bytes = 0;
+  fd_fieldk_from_info(&I, &f->k);
+  f->device = -1;
+  f->host_only = true;
+  *out = f;
+  return FDOT_OK;
+}

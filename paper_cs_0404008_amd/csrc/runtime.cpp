@@ -158,6 +158,7 @@ fdot_status_t fdot_workspace_reserve(void* stream, size_t count) {
 
 fdot_status_t fdot_encode(fdot_field_t f, const uint32_t* canon, void* rep, size_t n, void* stream) {
   if (!f) return FDOT_E_INVALID_ARG;
+  if (f->host_only) return FDOT_E_UNSUPPORTED;
   if (n && (!canon || !rep || !aligned_to(rep, f->info.elem_bytes) || !aligned_to(canon, 4)))
     return FDOT_E_INVALID_ARG;
   return fd_launch_encode(f, canon, rep, n, (hipStream_t)stream);
@@ -165,6 +166,7 @@ fdot_status_t fdot_encode(fdot_field_t f, const uint32_t* canon, void* rep, size
 
 fdot_status_t fdot_decode(fdot_field_t f, const void* rep, uint32_t* canon, size_t n, void* stream) {
   if (!f) return FDOT_E_INVALID_ARG;
+  if (f->host_only) return FDOT_E_UNSUPPORTED;
   if (n && (!canon || !rep || !aligned_to(rep, f->info.elem_bytes) || !aligned_to(canon, 4)))
     return FDOT_E_INVALID_ARG;
   return fd_launch_decode(f, rep, canon, n, (hipStream_t)stream);
@@ -173,6 +175,7 @@ fdot_status_t fdot_decode(fdot_field_t f, const void* rep, uint32_t* canon, size
 fdot_status_t fdot_modp_algo(fdot_field_t f, fdot_algo_t algo, const void* x, const void* y,
                              size_t n, void* result, void* stream) {
   if (!f || !result) return FDOT_E_INVALID_ARG;
+  if (f->host_only) return FDOT_E_UNSUPPORTED;
   if ((int)algo < FDOT_ALGO_AUTO || (int)algo > FDOT_ALGO_ZECH_EXP) return FDOT_E_INVALID_ARG;
   const size_t es = f->info.elem_bytes;
   if (!aligned_to(result, es)) return FDOT_E_INVALID_ARG;
@@ -191,6 +194,7 @@ fdot_status_t fdot_modp(fdot_field_t f, const void* x, const void* y, size_t n, 
 fdot_status_t fdot_modp_many_algo(fdot_field_t f, fdot_algo_t algo, size_t count,
                                   const fdot_desc_t* desc, void* results, void* stream) {
   if (!f) return FDOT_E_INVALID_ARG;
+  if (f->host_only) return FDOT_E_UNSUPPORTED;
   if ((int)algo < FDOT_ALGO_AUTO || (int)algo > FDOT_ALGO_ZECH_EXP) return FDOT_E_INVALID_ARG;
   if (count == 0) return FDOT_OK;
   if (!desc || !results || !aligned_to(desc, 8) || !aligned_to(results, f->info.elem_bytes))
@@ -210,6 +214,7 @@ fdot_status_t fdot_modp_many(fdot_field_t f, size_t count, const fdot_desc_t* de
 fdot_status_t fgemv_modp(fdot_field_t f, size_t m, size_t n, const void* A, size_t lda,
                          const void* x, void* y, void* stream) {
   if (!f) return FDOT_E_INVALID_ARG;
+  if (f->host_only) return FDOT_E_UNSUPPORTED;
   if (m == 0) return FDOT_OK;
   const size_t es = f->info.elem_bytes;
   if (!A || !y || (n && !x) || lda < n) return FDOT_E_INVALID_ARG;
@@ -221,6 +226,7 @@ fdot_status_t fgemv_modp(fdot_field_t f, size_t m, size_t n, const void* A, size
 fdot_status_t fgemm_modp(fdot_field_t f, size_t M, size_t N, size_t K, const void* A, size_t lda,
                          const void* B, size_t ldb, void* C, size_t ldc, void* stream) {
   if (!f) return FDOT_E_INVALID_ARG;
+  if (f->host_only) return FDOT_E_UNSUPPORTED;
   if (M == 0 || N == 0) return FDOT_OK;
   const size_t es = f->info.elem_bytes;
   if (!C || ldc < N || (K && (!A || !B || lda < K || ldb < N))) return FDOT_E_INVALID_ARG;

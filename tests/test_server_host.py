@@ -1,0 +1,111 @@
+"""The request server's scheduling logic without a GPU (fake-device mode):
+admission by footprint and slots, arrival order, batching, back-pressure,
+rejection of requests that can never fit, and the replay load generator."""
+import time
+
+import numpy as np
+import pytest
+
+fd = pytest.importorskip("paper_cs_0404008_amd")
+
+F1 = fd.Field(32749, "zpz", host_only=True)
+F2 = fd.Field(67108859, "fp64", host_only=True)
+F3 = fd.Field(251, "centred", host_only=True)
+FAKE = 1 << 20  # nonzero fake device addresses (never dereferenced)
+
+
+def dot(F, n, fp=0):
+    return fd.make_request("dot", F, FAKE, FAKE, FAKE, n=n, footprint=fp)
+
+
+def test_host_only_field_refuses_compute():
+    import ctypes
+    L = fd.lib()
+    assert L.fdot_modp(F1.handle, ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE), 10,
+                       ctypes.c_void_p(FAKE), None) == -4
+    assert F1.info["lambda_u64"] == 17200859919
+
+
+def test_everything_completes_and_counts():
+    srv = fd.Server(fake_device=True)
+    tickets = [srv.submit(dot(F1, 1000 + i)) for i in range(200)]
+    tickets += [srv.submit(fd.make_request("gemv", F2, FAKE, FAKE, FAKE, m=100, n=100))
+                for _ in range(20)]
+    tickets += [srv.submit(fd.make_request("gemm", F3, FAKE, FAKE, FAKE, m=64, n=64, k=64))
+                for _ in range(5)]
+    srv.drain(10000)
+    for t in tickets:
+        done, tm = srv.poll(t)
+        assert done and tm.status == 0
+        assert tm.submit_ns <= tm.admit_ns <= tm.launch_ns <= tm.done_ns
+    st = srv.stats()
+    assert st["submitted"] == st["completed"] == len(tickets)
+    srv.close()
+
+
+def test_budget_and_slots_are_respected():
+    budget = 10_000
+    srv = fd.Server(fake_device=True, hbm_budget=budget, max_inflight=3)
+    reqs = [dot(F1, 10, fp=int(fp)) for fp in np.random.default_rng(1).integers(1000, 5000, 300)]
+    for r in reqs:
+        srv.submit(r)
+    srv.drain(20000)
+    st = srv.stats()
+    assert st["peak_footprint"] <= budget
+    assert st["peak_inflight"] <= 3
+    assert st["completed"] == 300
+
+
+def test_admission_keeps_arrival_order():
+    srv = fd.Server(fake_device=True, hbm_budget=6000, max_inflight=4)
+    fps = np.random.default_rng(2).integers(500, 5000, 200)
+    tickets = [srv.submit(dot(F1, 10, fp=int(f))) for f in fps]
+    srv.drain(20000)
+    admits = [srv.poll(t)[1].admit_ns for t in tickets]
+    assert all(a <= b for a, b in zip(admits, admits[1:]))
+
+
+def test_batching_and_plain_mode():
+    srv = fd.Server(fake_device=True, hbm_budget=1 << 40, max_inflight=1024)
+    gemm = srv.submit(fd.make_request("gemm", F3, FAKE, FAKE, FAKE, m=2048, n=2048, k=2048))
+    ts = [srv.submit(dot(F1, 1000)) for _ in range(300)]
+    srv.drain(20000)
+    sizes = [srv.poll(t)[1].batch_size for t in ts]
+    assert max(sizes) > 1                   # same-field dots were fused
+    assert srv.poll(gemm)[1].batch_size == 1
+    plain = fd.Server(fake_device=True, plain=True)
+    ts = [plain.submit(dot(F1, 1000)) for _ in range(50)]
+    plain.drain(20000)
+    assert all(plain.poll(t)[1].batch_size == 1 for t in ts)
+    assert plain.stats()["launches"] == 50
+
+
+def test_back_pressure_and_rejection():
+    big = fd.make_request("gemm", F2, FAKE, FAKE, FAKE, m=4096, n=4096, k=4096)  # ~7 ms simulated
+    srv = fd.Server(fake_device=True, hbm_budget=big.footprint or 3 * 4096 * 4096 * 8,
+                    max_inflight=1, max_queue=4)
+    srv.submit(big)
+    statuses = [srv.try_submit(dot(F1, 10))[0] for _ in range(8)]
+    assert statuses.count(0) <= 5 and -7 in statuses   # FDOT_E_BUSY once the queue is full
+    too_big = fd.make_request("dot", F1, FAKE, FAKE, FAKE, n=10, footprint=1 << 50)
+    assert srv.try_submit(too_big)[0] == -6             # FDOT_E_NOMEM: can never fit
+    assert srv.stats()["rejected"] == 1
+    with pytest.raises(fd.FdotError):
+        srv.submit(fd.make_request("gemv", F1, FAKE, FAKE, FAKE, m=0, n=5))
+    srv.drain(20000)
+
+
+def test_replay_honours_arrivals():
+    srv = fd.Server(fake_device=True)
+    n = 200
+    arrivals = np.cumsum(np.random.default_rng(3).exponential(1e-4, n))
+    reqs = [dot(F1, 5000) for _ in range(n)]
+    t0 = time.monotonic_ns()
+    tm = srv.replay(reqs, arrivals)
+    assert len(tm) == n and (tm["status"] == 0).all()
+    start = tm["submit_ns"].min()
+    offs = (tm["submit_ns"] - start) / 1e9
+    # each request is submitted no earlier than its arrival (relative to the first)
+    assert (offs + 1e-4 >= arrivals - arrivals[0]).all()
+    assert (tm["done_ns"] >= tm["submit_ns"]).all()
+    assert tm["submit_ns"].min() >= t0
