@@ -33,6 +33,33 @@ BATCHES = [  # (p, representation, algorithm, label)
     (4294967291, "zpz", "perterm", "p=4294967291 zpz per-term"),
 ]
 SEED = 2
+KERNEL_OF = {"delayed/zpz": "PZpzDelayed", "delayed/mont": "PMontDelayed",
+             "perterm/zpz": "PZpzPerTerm"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dot_kernel_batched_4096pairs_hbm_traffic.json")
+
+
+def measured_traffic(p_rep_algo):
+    """HBM bytes per launch of the batch kernel from the committed hardware
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or
+    None when it is absent or the kernel source has changed since."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != rec["source_sha256"]:
+            return None
+    except (OSError, ValueError, KeyError):
+        return None
+    _, rep, algo = p_rep_algo
+    pol = KERNEL_OF.get(f"{algo}/{rep}")
+    for name, d in rec["kernels"].items():
+        if pol and f"<{pol}," in name:
+            return int(d["traffic_bytes"])
+    return None
 
 
 def log(*a):
@@ -76,32 +103,39 @@ class Batch:
         self.F.dot_many(self.desc, out=self.out, algo=self.algo)
 
 
-def cpu_baseline(batches, max_instances=384):
+def cpu_baseline(batches, max_instances=384, min_seconds=10.0):
     """The oracle (as it stands) on the first instances of every batch,
-    regenerated on the host from the same seeds."""
+    regenerated on the host from the same seeds, passed over repeatedly
+    until about min_seconds of CPU work have been timed."""
     import oracle
     import synth
+    sample = []
     terms = 0
-    nbytes = 0
-    elapsed = 0.0
     for b in batches:
         ns = b.ns[:max_instances]
         xs = [synth.uniform_int(SEED, 2 * k, int(n), b.p).astype(np.uint32) for k, n in enumerate(ns)]
         ys = [synth.uniform_int(SEED, 2 * k + 1, int(n), b.p).astype(np.uint32) for k, n in enumerate(ns)]
-        t0 = time.perf_counter()
         res = oracle.dot_many(b.p, b.rep, xs, ys)
-        elapsed += time.perf_counter() - t0
         gpu = b.out[:len(ns)].cpu().numpy()
         if res.tobytes() != gpu.tobytes():
             raise SystemExit(f"GPU and oracle disagree on batch p={b.p}")
+        sample.append((b, xs, ys))
         terms += int(np.sum(ns))
-        nbytes += int(np.sum(ns)) * 8
+    rounds = 0
+    elapsed = 0.0
+    while elapsed < min_seconds and rounds < 1000:
+        t0 = time.perf_counter()
+        for b, xs, ys in sample:
+            oracle.dot_many(b.p, b.rep, xs, ys)
+        elapsed += time.perf_counter() - t0
+        rounds += 1
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(nbytes / elapsed / 1e9, 4), "unit": "GB/s", "cores": cores,
-            "kind": "oracle", "gelem_per_s": round(terms / elapsed / 1e9, 4),
+    nbytes = terms * 8
+    return {"value": round(nbytes * rounds / elapsed / 1e9, 4), "unit": "GB/s", "cores": cores,
+            "kind": "oracle", "gelem_per_s": round(terms * rounds / elapsed / 1e9, 4),
             "sample": f"first {max_instances} instances of each of the 3 batches "
-                      f"({terms} terms, {nbytes / 1e9:.2f} GB), per-term __int128 reduction, "
-                      f"OpenMP over instances; {elapsed:.2f} s"}
+                      f"({terms} terms, {nbytes / 1e9:.2f} GB) timed over {rounds} passes "
+                      f"({elapsed:.1f} s); per-term __int128 reduction, OpenMP over instances"}
 
 
 def time_events(fn, reps):
@@ -116,7 +150,8 @@ def time_events(fn, reps):
 
 
 def extras_plain(fd, b, limit=4096):
-    """One fdot_modp launch per pair, same stream, same kernels."""
+    """One fdot_modp launch per pair, same stream, same kernels: issued from
+    Python (eager) and replayed from one HIP graph (no host overhead)."""
     outs = torch.empty(len(b.ns), dtype=b.out.dtype, device="cuda")
 
     def plain():
@@ -125,11 +160,15 @@ def extras_plain(fd, b, limit=4096):
 
     plain()
     t = time_events(plain, 1)
+    tg = graph_time(fd, plain, reps=3)
     tb = time_events(b.run, 3)
+    tbg = graph_time(fd, b.run, reps=5)
     if outs.cpu().numpy().tobytes() != b.out.cpu().numpy().tobytes():
         raise SystemExit("plain and batched results differ")
-    return {"batch": f"p={b.p} {b.rep} {b.algo}", "plain_ms": round(t * 1e3, 3),
-            "batched_ms": round(tb * 1e3, 3), "speedup": round(t / tb, 2)}
+    return {"batch": f"p={b.p} {b.rep} {b.algo}", "plain_eager_ms": round(t * 1e3, 3),
+            "plain_graph_ms": round(tg * 1e3, 3), "batched_ms": round(tb * 1e3, 3),
+            "batched_graph_ms": round(tbg * 1e3, 3),
+            "speedup_vs_eager": round(t / tb, 2), "speedup_vs_graph": round(tg / tb, 2)}
 
 
 def graph_time(fd, fn, reps=20):
@@ -197,6 +236,117 @@ def extras_config3(fd):
     return out
 
 
+def extras_gemm(fd):
+    """fgemm_modp at 8192 x 8192 times 8192 x 4096: p = 251 centred int8 on
+    int8 matrix cores, p = 2^20-3 residues in doubles on FP64 matrix cores."""
+    import synth
+    M, K, N = 8192, 8192, 4096
+    out = {}
+    for p, rep, dt, lo, peak, label in [(251, "centred", torch.int8, -125, 5000.0, "int8 p=251"),
+                                        (1048573, "fp64", torch.float64, 0, 78.6, "fp64 p=2^20-3")]:
+        F = fd.Field(p, rep)
+        A = torch.empty((M, K), dtype=dt, device="cuda")
+        B = torch.empty((K, N), dtype=dt, device="cuda")
+        synth.fill_device(A, 4, 0, p, lo)
+        synth.fill_device(B, 4, 1, p, lo)
+        C = torch.empty((M, N), dtype=dt, device="cuda")
+        F.gemm(A, B, out=C)
+        t = time_events(lambda: F.gemm(A, B, out=C), 3)
+        tops = 2.0 * M * N * K / t / 1e12
+        out[label] = {"ms": round(t * 1e3, 3), "TOPS": round(tops, 1),
+                      "frac_of_peak": round(tops / peak, 4), "peak_TOPS": peak}
+        del A, B, C
+        torch.cuda.empty_cache()
+    return out
+
+
+SERVED_PRIMES = {251: ("zpz", "centred"), 32749: ("zpz", "zpz"), 65521: ("zpz", "zpz"),
+                 67108859: ("fp64", "fp64"), 2147483647: ("mont", "mont")}
+SERVED_DT = {"zpz": torch.uint32, "mont": torch.uint32, "fp64": torch.float64,
+             "centred": torch.int8}
+
+
+def served_workload(fd, n_req, seed=5):
+    """Requests of the served stream: 60% dot (n log-uniform 1e3..1e7), 30%
+    square matvec (n uniform 2000..20000), 10% square fgemm (n uniform
+    512..4096), prime uniform over SERVED_PRIMES.  Operands are prefixes of one
+    pre-generated pool per field and kind (device-resident, read-only);
+    every request has its own output."""
+    import synth
+    rng = np.random.default_rng(seed)
+    fields, pools, reqs, outs = {}, {}, [], []
+
+    def pool(p, rep, kind, shape_a, shape_b):
+        key = (p, rep, kind)
+        if key not in pools:
+            m, lo = (p, 0) if rep != "centred" else (p, -((p - 1) // 2))
+            a = torch.empty(shape_a, dtype=SERVED_DT[rep], device="cuda")
+            b = torch.empty(shape_b, dtype=SERVED_DT[rep], device="cuda")
+            synth.fill_device(a, seed, 2 * len(pools), m, lo)
+            synth.fill_device(b, seed, 2 * len(pools) + 1, m, lo)
+            pools[key] = (a, b)
+        return pools[key]
+
+    for _ in range(n_req):
+        p = list(SERVED_PRIMES)[rng.integers(len(SERVED_PRIMES))]
+        u = rng.random()
+        if u < 0.6:
+            op, rep = "dot", SERVED_PRIMES[p][0]
+            n = int(10 ** rng.uniform(3, 7))
+            a, b = pool(p, rep, op, 10 ** 7, 10 ** 7)
+            out = torch.empty(1, dtype=SERVED_DT[rep], device="cuda")
+            kw = dict(n=n)
+        elif u < 0.9:
+            op, rep = "gemv", SERVED_PRIMES[p][0]
+            n = int(rng.integers(2000, 20001))
+            a, b = pool(p, rep, op, 20000 * 20000, 20000)
+            out = torch.empty(n, dtype=SERVED_DT[rep], device="cuda")
+            kw = dict(m=n, n=n)
+        else:
+            op, rep = "gemm", SERVED_PRIMES[p][1]
+            n = int(rng.integers(512, 4097))
+            a, b = pool(p, rep, op, 4096 * 4096, 4096 * 4096)
+            out = torch.empty(n * n, dtype=SERVED_DT[rep], device="cuda")
+            kw = dict(m=n, n=n, k=n)
+        if (p, rep) not in fields:
+            fields[(p, rep)] = fd.Field(p, rep)
+        reqs.append(fd.make_request(op, fields[(p, rep)], a, b, out, **kw))
+        outs.append(out)
+    return fields, pools, reqs, outs
+
+
+def extras_served(fd, n_req=400):
+    """Served stream vs one launch per request at the same Poisson load.
+    mu = the plain path's service rate (all requests at once, one stream)."""
+    fields, pools, reqs, outs = served_workload(fd, n_req)
+    budget = 64 << 30
+
+    def run(plain, arrivals):
+        srv = fd.Server(plain=plain, hbm_budget=budget, max_inflight=256, streams=4)
+        tm = srv.replay(reqs, arrivals)
+        srv.close()
+        if (tm["status"] != 0).any():
+            raise SystemExit("served request failed")
+        lat = (tm["done_ns"] - tm["submit_ns"]) / 1e6
+        span = (tm["done_ns"].max() - tm["submit_ns"].min()) / 1e9
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "throughput_rps": round(len(reqs) / span, 1)}
+
+    run(True, np.zeros(len(reqs)))  # warm-up: workspaces, code objects
+    burst = run(True, np.zeros(len(reqs)))
+    mu = burst["throughput_rps"]
+    res = {"requests": n_req, "mu_plain_rps": mu, "hbm_budget_GiB": budget >> 30,
+           "mix": "60% dot n~10^U(3,7), 30% matvec n~U(2000,20000), 10% fgemm n~U(512,4096); "
+                  "p uniform over {251, 32749, 65521, 2^26-5, 2^31-1}"}
+    rng = np.random.default_rng(55)
+    gaps = rng.exponential(1.0, len(reqs))
+    for load in (0.5, 0.8, 2.0):
+        arrivals = np.cumsum(gaps) / (load * mu)
+        res[f"load_{load}mu"] = {"plain": run(True, arrivals), "served": run(False, arrivals)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,7 +354,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--extras", choices=["all", "none"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 1 GiB device-to-device three times (the known-size "
+                         "reference for hardware byte counters), then exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 4, "copies": 3}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -254,7 +415,9 @@ def main():
                          for i in range(len(batches))},
         "roofline": {"bound": "hbm", "kernel": f"dot_kernel batched, {BATCHES[dom][3]}",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(BATCHES[dom][:3]),
+                     "algorithmic_bytes": batches[dom].bytes},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -270,6 +433,12 @@ def main():
         torch.cuda.empty_cache()
         log("extras: fp64 / zech ...")
         extras["config3"] = extras_config3(fd)
+        torch.cuda.empty_cache()
+        log("extras: fgemm ...")
+        extras["fgemm_config4"] = extras_gemm(fd)
+        torch.cuda.empty_cache()
+        log("extras: served stream ...")
+        extras["served_config5"] = extras_served(fd)
         result["extras"] = extras
     print(json.dumps(result), flush=True)
 

@@ -662,12 +662,18 @@ __global__ __launch_bounds__(PLAN_NT) void plan_kernel(const fdot_desc_t* desc, 
     *total = s[t];
     *next = 0;
   }
-  // chunk -> pair table (the batch kernel falls back to a binary search over
-  // the offsets when the batch has more chunks than the table holds)
-  const uint64_t tot = s[PLAN_NT - 1];
-  __syncthreads();  // offsets written by every thread of this workgroup
-  if (tot <= owner_cap)
-    for (uint64_t c = t; c < tot; c += PLAN_NT) owner[c] = (uint32_t)find_instance(offsets, count, c);
+  // chunk -> pair table, each thread filling the chunk ranges of its own
+  // pairs (the batch kernel falls back to a binary search over the offsets
+  // when the batch has more chunks than the table holds)
+  if (s[PLAN_NT - 1] <= owner_cap) {
+    uint64_t c = s[t] - local;
+    for (uint64_t k = b; k < e; ++k) {
+      const uint64_t n = desc[k].n;
+      const uint64_t cs = chunk_of(n, chunk, slice_shift);
+      const uint64_t end = c + (n + cs - 1) / cs;
+      for (; c < end; ++c) owner[c] = (uint32_t)k;
+    }
+  }
 }
 
 __global__ void zero_kernel(uint8_t* p, size_t bytes) {
