@@ -33,6 +33,7 @@ struct Workspace {
   uint64_t* offsets = nullptr;        // cap + 1 (chunk prefix sums)
   uint64_t* total = nullptr;          // 1
   unsigned long long* next = nullptr; // 1: chunk counter of the batched form
+  bool captured = false;  // handed to a graph capture: never freed on growth
 };
 
 // Host-side helpers (host_field.cpp).

@@ -24,6 +24,7 @@
 
 #include <map>
 #include <mutex>
+#include <set>
 #include <utility>
 
 #include "fdot_internal.h"
@@ -343,24 +344,28 @@ __global__ __launch_bounds__(256) void transpose_i8_kernel(const int8_t* B, uint
 // demand (outside graph capture).
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, std::pair<void*, size_t>> g_scratch;
+std::set<void*> g_scratch_captured;
 
 fdot_status_t scratch_for(hipStream_t s, size_t bytes, void** out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return FDOT_E_DEVICE;
   std::lock_guard<std::mutex> g(g_mu);
   auto& e = g_scratch[std::make_pair(dev, s)];
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const bool capturing =
+      hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
   if (e.second >= bytes) {
+    if (capturing) g_scratch_captured.insert(e.first);
     *out = e.first;
     return FDOT_OK;
   }
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
-    return FDOT_E_BUSY;
+  if (capturing) return FDOT_E_BUSY;  // growing allocates
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) return FDOT_E_NOMEM;
   if (e.first) {
     hipStreamSynchronize(s);
-    hipFree(e.first);
+    // a buffer that a captured graph holds stays allocated until the process ends
+    if (!g_scratch_captured.count(e.first)) hipFree(e.first);
   }
   e = std::make_pair(p, bytes);
   *out = p;

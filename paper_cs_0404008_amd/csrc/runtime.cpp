@@ -8,6 +8,7 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "fdot_internal.h"
 
@@ -15,6 +16,7 @@ namespace {
 
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
+std::vector<void*> g_ws_retired;  // workspaces a captured graph may still use
 
 std::mutex g_tune_mu;
 std::map<std::string, int64_t> g_tune;
@@ -72,14 +74,18 @@ fdot_status_t fd_workspace_get(hipStream_t s, size_t count, Workspace** out) {
   if (hipGetDevice(&dev) != hipSuccess) return FDOT_E_DEVICE;
   std::lock_guard<std::mutex> g(g_ws_mu);
   Workspace*& w = g_ws[std::make_pair(dev, s)];
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const bool capturing =
+      hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
   if (w && w->cap >= count) {
+    // A captured graph keeps this buffer's address: later growth must not
+    // free it while such a graph may still be replayed.
+    if (capturing) w->captured = true;
     *out = w;
     return FDOT_OK;
   }
   // Growing allocates, which a stream under graph capture cannot do.
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
-    return FDOT_E_BUSY;
+  if (capturing) return FDOT_E_BUSY;
   size_t cap = count < 4096 ? 4096 : count;
   const size_t owner_cap = cap * 64 < (1u << 20) ? (1u << 20) : cap * 64;
   const size_t bytes_acc = cap * 8, bytes_owner = (owner_cap * 4 + 7) / 8 * 8,
@@ -93,7 +99,11 @@ fdot_status_t fd_workspace_get(hipStream_t s, size_t count, Workspace** out) {
   }
   if (w) {  // the old buffer may still be in use by work queued on s
     hipStreamSynchronize(s);
-    hipFree(w->base);
+    if (w->captured)
+      g_ws_retired.push_back(w->base);  // kept until the process ends
+    else
+      hipFree(w->base);
+    w->captured = false;
   } else {
     w = new Workspace;
   }

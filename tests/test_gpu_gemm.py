@@ -129,3 +129,11 @@ def test_gemm_full_size_sampled(p, rep, dtype):
     cols[:4] = [0, N - 1, 0, N - 1]
     want = oracle.gemm_entries(p, rep, Ah, Bh, rows, cols)
     assert same(C[rows, cols], want)
+    # Freivalds: A (B r) = C r mod p for random r; a wrong C passes one trial
+    # with probability at most 1/p.  Exact in int64: |sums| < 8192 * p^2 < 2^54.
+    Ai, Bi, Ci = (v.astype(np.int64) for v in (Ah, Bh, C))
+    for t in range(8):
+        r = synth.uniform_int(4, 10 + t, N, p).astype(np.int64)
+        lhs = (Ai @ ((Bi @ r) % p)) % p
+        rhs = (Ci @ r) % p
+        assert np.array_equal(lhs, rhs), t
