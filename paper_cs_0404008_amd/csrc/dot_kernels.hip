@@ -2,21 +2,27 @@
 // batched form (many pairs of uneven length in one launch), plus the
 // representation conversions and the matrix-vector product.
 //
-// Work decomposition.  A vector pair is cut into chunks, and each chunk into
-// four interleaved slices; the unit of work is one wavefront streaming one
-// slice with 16-byte loads, each lane accumulating its share in registers (the
-// delayed reduction of Sec. 3.1-3.2, the on-demand correction of Sec. 3.3, or
-// a per-term reduction) and folding to a residue below p at the end.  The
-// wavefront sums its lanes' residues with cross-lane shuffles, folds once
-// more, and adds the result r < p to the pair's combination word with one
-// 64-bit atomic: the low 48 bits collect the residues, the high 16 bits count
-// finished units.  A pair has at most 65535 units, so the low field cannot
-// overflow into the count, and the wavefront whose atomic returns
-// count = units-1 holds the complete sum: it reduces it, encodes the result
-// in the pair's representation and puts the word back to zero for the next
-// call.  No workgroup barrier, no memory fence: waves never wait for one
-// another.  Integer sums are exact and associative, so the result is the same
-// bit pattern whatever order the units finish in.
+// Work decomposition.  The unit of work is one wavefront streaming a slice of
+// one pair with 16-byte loads, each lane accumulating its share in registers
+// (the delayed reduction of Sec. 3.1-3.2, the on-demand correction of
+// Sec. 3.3, or a per-term reduction) and folding to a residue below p at the
+// end.  The single form cuts its pair into chunks, about one per resident
+// wavefront.  The batched form lays the pairs end to end (each padded to a
+// multiple of 64 elements) and cuts that sequence into equal ranges, one per
+// group of S wavefronts, so that every wavefront streams the same number of
+// bytes whatever the lengths of the pairs: a range covers the tail of one
+// pair, whole pairs and the head of the next, and each piece is one unit.
+//
+// Combination.  The wavefront sums its lanes' residues with cross-lane
+// shuffles, folds once more, and adds the result r < p to the pair's
+// combination word with one 64-bit atomic: the low 48 bits collect the
+// residues, the high 16 bits count finished units.  A pair has at most 65535
+// units, so the low field cannot overflow into the count, and the wavefront
+// whose atomic returns count = units-1 holds the complete sum: it reduces it,
+// encodes the result in the pair's representation and puts the word back to
+// zero for the next call.  No workgroup barrier, no memory fence: waves never
+// wait for one another.  Integer sums are exact and associative, so the
+// result is the same bit pattern whatever order the units finish in.
 #include <stdio.h>
 #include <string.h>
 
@@ -61,20 +67,17 @@ struct Job {
   const void* x;             // single form
   const void* y;
   uint64_t n;
+  uint64_t chunk;            // single form: elements per chunk (at least; see chunk_of)
   const fdot_desc_t* desc;   // batched form
   uint64_t count;
-  const uint64_t* offsets;   // chunk prefix sums (count + 1)
-  const uint64_t* total;     // number of chunks of the batch
-  unsigned long long* next;  // next unclaimed chunk (reset by the plan kernel)
-  const uint32_t* owner;     // chunk -> pair, when the batch has <= owner_cap chunks
-  uint64_t owner_cap;
-  uint64_t chunk;            // elements per chunk (at least; see chunk_of)
+  const uint64_t* first;     // batched: position of each pair in the padded sequence
+  const uint32_t* units;     // batched: units of each pair
+  const uint32_t* start;     // batched: first pair of each range
+  const uint64_t* tq;        // batched: padded total T, range length Q, ranges R
   unsigned long long* acc;   // combination words, one per pair
   void* results;
   uint32_t fold_vecs;        // vectors between two folds
-  uint32_t slice_shift;      // log2 of the wavefronts sharing one chunk
-  uint32_t dynamic;          // batched form: units claimed from a counter
-  uint32_t pad;
+  uint32_t slice_shift;      // log2 of the wavefronts sharing one chunk or range
 };
 
 // Chunk length used for a pair of length n: the configured chunk, or longer
@@ -423,16 +426,21 @@ struct Folds<P, decltype((void)P::kFolds)> { static constexpr bool value = P::kF
 
 // --------------------------------------------------------------- the driver
 
+// Sixteen-byte-aligned zeros: the address that masked-off loads read, so
+// that loads near the end of a range can be issued unconditionally.
+__device__ const u32x4 g_zero16[2] = {{0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}};
+
 // One wavefront streams its slice of [x, x+len) against [y, y+len) through a
 // lane policy.  The range is read as 1 KiB blocks (64 lanes x 16 bytes); slice
 // s of S takes blocks s, s+S, s+2S, ..., so the S wavefronts working on one
-// chunk sweep it together as one contiguous stream (far fewer DRAM row
-// switches than S independent streams).  Slice 0 also takes a short scalar
-// head that aligns both pointers to 16 bytes when they share the same offset,
-// and the scalar tail; pointers with different offsets are read with scalar
-// loads.  A folding policy folds before any accumulator can have taken more
-// than fold_vecs vectors: once per unrolled step when fold_vecs >= U, after
-// every vector otherwise.
+// chunk sweep it together as one contiguous stream.  Slice 0 also takes a
+// short scalar head that aligns both pointers to 16 bytes when they share the
+// same offset, and the scalar tail, whose loads are issued with the first
+// step; pointers with different offsets are read with scalar loads.  The last
+// partial step is one masked step (lanes past the end read zeros), so the
+// end of a range costs one memory latency.  A folding policy folds before any
+// accumulator can have taken more than fold_vecs vectors: once per step when
+// fold_vecs >= U, after every vector otherwise.
 template <class Pol>
 __device__ __forceinline__ void wave_range(Pol& L, const typename Pol::E* x,
                                            const typename Pol::E* y, uint64_t len,
@@ -454,6 +462,11 @@ __device__ __forceinline__ void wave_range(Pol& L, const typename Pol::E* x,
   const u32x4* xv = (const u32x4*)(x + head);
   const u32x4* yv = (const u32x4*)(y + head);
   const uint64_t nv = (len - head) / VW;
+  const uint64_t t0 = head + nv * VW;
+  // the scalar tail, loaded now and consumed at the end
+  const bool has_tail = slice == 0 && lane < len - t0;
+  const E tx = load_s(has_tail ? x + t0 + lane : (const E*)g_zero16);
+  const E ty = load_s(has_tail ? y + t0 + lane : (const E*)g_zero16);
   const uint64_t step = (uint64_t)S * W;  // vectors from one block of this slice to the next
   uint64_t i = (uint64_t)slice * W + lane;
   uint32_t pending = 0;                   // vectors taken since the last fold
@@ -499,17 +512,30 @@ __device__ __forceinline__ void wave_range(Pol& L, const typename Pol::E* x,
       }
     }
   }
-  for (; i < nv; i += step) {
-    L.vec(load_v(xv + i), load_v(yv + i), F);
-    if constexpr (kF) {
-      if (++pending >= fv) {
-        L.fold(F);
-        pending = 0;
+  // the last, partial step: fewer than U vectors are left for this lane
+  if (i < nv) {
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    u32x4 a[U - 1], b[U - 1];
+#pragma unroll
+    for (int u = 0; u < U - 1; ++u) {
+      const uint64_t idx = i + (uint64_t)u * step;
+      a[u] = load_nt(idx < nv ? xv + idx : g_zero16);
+      b[u] = load_nt(idx < nv ? yv + idx : g_zero16);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U - 1; ++u) {
+      const bool ok = i + (uint64_t)u * step < nv;
+      L.vec(ok ? a[u] : zero, ok ? b[u] : zero, F);
+      if constexpr (kF) {
+        if (++pending >= fv) {
+          L.fold(F);
+          pending = 0;
+        }
       }
     }
   }
-  const uint64_t t0 = head + nv * VW;
-  if (slice == 0 && lane < len - t0) L.one(load_s(x + t0 + lane), load_s(y + t0 + lane), F, J);
+  if (has_tail) L.one(tx, ty, F, J);
 }
 
 __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
@@ -518,126 +544,190 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
   return v;
 }
 
-// Largest k with offsets[k] <= c (skips empty instances).
-__device__ __forceinline__ uint64_t find_instance(const uint64_t* offsets, uint64_t count,
-                                                  uint64_t c) {
-  uint64_t lo = 0, hi = count;
-  while (lo < hi) {
-    const uint64_t mid = (lo + hi + 1) >> 1;
-    if (offsets[mid] <= c) lo = mid; else hi = mid - 1;
-  }
-  return lo;
+// Copies the policy's table (p entries of 16 bits) into LDS, once per
+// workgroup.
+template <class Pol, int NTH>
+__device__ __forceinline__ void load_table(const FieldK& F, uint16_t* s_tab) {
+  const uint16_t* src = std::is_same<Pol, PZechExp>::value ? F.zval : F.zplus1;
+  for (uint32_t i = threadIdx.x; i < F.p32; i += NTH) s_tab[i] = src[i];
+  __syncthreads();
 }
 
-template <class Pol, int NTH, bool MANY>
+// Adds a unit's residue to its pair's combination word.  The returned old
+// word is checked one unit later, so that the wavefront does not wait for the
+// atomic before streaming its next unit; the wavefront that completes a pair
+// stores its result.
+template <class Pol>
+struct Combiner {
+  bool pending = false;
+  uint64_t pk = 0, pnck = 0, pr = 0;
+  unsigned long long pold = 0;
+  __device__ __forceinline__ void settle(const FieldK& F, const Job& J) {
+    if (pending && (pold >> 48) + 1 == pnck) {
+      // Every other unit of that pair has been added: the word is ours.
+      atomicExch(J.acc + pk, 0ull);
+      Pol::store(J.results, pk, mod_u64((pold & kSumMask) + pr, F), F);
+    }
+    pending = false;
+  }
+  // lane 0 only
+  __device__ __forceinline__ void add(uint64_t k, uint64_t nck, uint64_t wsum, const FieldK& F,
+                                      const Job& J) {
+    settle(F, J);
+    pr = mod_u64(wsum, F);
+    pold = atomicAdd(J.acc + k, (unsigned long long)(pr + kCountOne));
+    pk = k;
+    pnck = nck;
+    pending = true;
+  }
+};
+
+// Single form: unit u = slice (u mod S) of chunk (u / S), S = 2^slice_shift;
+// consecutive waves of a workgroup take consecutive units, and the grid
+// strides over the rest.
+template <class Pol, int NTH>
 __global__ __launch_bounds__(NTH) void dot_kernel(const FieldK F, const Job J) {
   using E = typename Pol::E;
   extern __shared__ uint16_t s_tab[];
   constexpr bool kTab = HasTable<Pol>::value;
-  if constexpr (kTab) {
-    // The policy's table (p entries of 16 bits) is copied once per workgroup.
-    const uint16_t* src = std::is_same<Pol, PZechExp>::value ? F.zval : F.zplus1;
-    for (uint32_t i = threadIdx.x; i < F.p32; i += NTH) s_tab[i] = src[i];
-    __syncthreads();
-  }
+  if constexpr (kTab) load_table<Pol, NTH>(F, s_tab);
   const uint32_t lane = threadIdx.x & 63u;
-  // Work unit u = slice (u mod S) of chunk (u / S), S = 2^slice_shift: the S
-  // wavefronts of a chunk sweep it side by side.  Units are claimed from a
-  // counter (batched form, J.dynamic) or dealt round-robin: consecutive waves
-  // of a workgroup take consecutive units.
   const uint32_t sh = J.slice_shift;
   const uint32_t S = 1u << sh;
-  const uint64_t cs1 = MANY ? 0 : chunk_of(J.n, J.chunk, sh);
-  const uint64_t total_chunks = MANY ? *J.total : (J.n + cs1 - 1) / cs1;
-  const uint64_t total = total_chunks << sh;
-  const bool use_owner = MANY && total_chunks <= J.owner_cap;
-  const bool dyn = MANY && J.dynamic;
+  const uint64_t cs = chunk_of(J.n, J.chunk, sh);
+  const uint64_t total = ((J.n + cs - 1) / cs) << sh;
   const uint64_t wstride = (uint64_t)gridDim.x * (NTH / 64);
-  uint64_t u = (uint64_t)blockIdx.x * (NTH / 64) + (threadIdx.x >> 6);
-  if (dyn) {
-    unsigned long long c0 = 0;
-    if (lane == 0) c0 = atomicAdd(J.next, 1ull);
-    u = __shfl(c0, 0, 64);
-  }
-  // The combination atomic of a unit is checked one unit later, so that the
-  // wavefront does not wait for its return before streaming the next unit.
-  bool has_pending = false;
-  uint64_t pk = 0, pnck = 0, pr = 0;
-  unsigned long long pold = 0;
-  while (u < total) {
-    unsigned long long nxt = 0;
-    if (dyn && lane == 0) nxt = atomicAdd(J.next, 1ull);  // claim the next unit early
+  Combiner<Pol> C;
+  for (uint64_t u = (uint64_t)blockIdx.x * (NTH / 64) + (threadIdx.x >> 6); u < total;
+       u += wstride) {
     const uint64_t c = u >> sh;
     const uint32_t slice = (uint32_t)(u & (S - 1));
-    uint64_t k, beg, len, nck;
-    const E* x;
-    const E* y;
-    if (MANY) {
-      k = use_owner ? (uint64_t)J.owner[c] : find_instance(J.offsets, J.count, c);
-      const uint64_t first = J.offsets[k];
-      nck = (J.offsets[k + 1] - first) << sh;
-      const fdot_desc_t d = J.desc[k];
-      const uint64_t cs = chunk_of(d.n, J.chunk, sh);
-      beg = (c - first) * cs;
-      len = d.n - beg < cs ? d.n - beg : cs;
-      x = (const E*)d.x + beg;
-      y = (const E*)d.y + beg;
-    } else {
-      k = 0;
-      nck = total;
-      beg = c * cs1;
-      len = J.n - beg < cs1 ? J.n - beg : cs1;
-      x = (const E*)J.x + beg;
-      y = (const E*)J.y + beg;
-    }
+    const uint64_t beg = c * cs;
+    const uint64_t len = J.n - beg < cs ? J.n - beg : cs;
     Pol L;
     L.init(F);
     if constexpr (kTab) L.tab = s_tab;
-    wave_range<Pol>(L, x, y, len, lane, slice, S, F, J);
+    wave_range<Pol>(L, (const E*)J.x + beg, (const E*)J.y + beg, len, lane, slice, S, F, J);
     const uint64_t wsum = wave_sum(L.finish(F));
-    if (lane == 0) {
-      if (has_pending && (pold >> 48) + 1 == pnck) {
-        // Every other unit of that pair has been added: the word is ours.
-        atomicExch(J.acc + pk, 0ull);
-        Pol::store(J.results, pk, mod_u64((pold & kSumMask) + pr, F), F);
-      }
-      pr = mod_u64(wsum, F);
-      pold = atomicAdd(J.acc + k, (unsigned long long)(pr + kCountOne));
-      pk = k;
-      pnck = nck;
-      has_pending = true;
-    }
-    u = dyn ? (uint64_t)__shfl(nxt, 0, 64) : u + wstride;
+    if (lane == 0) C.add(0, total, wsum, F, J);
   }
-  if (lane == 0 && has_pending && (pold >> 48) + 1 == pnck) {
-    atomicExch(J.acc + pk, 0ull);
-    Pol::store(J.results, pk, mod_u64((pold & kSumMask) + pr, F), F);
+  if (lane == 0) C.settle(F, J);
+}
+
+// Batched form.  The padded sequence [0, T) is cut into R ranges of Q
+// elements (the last one shorter), dealt cyclically to G groups of S
+// wavefronts: group g streams ranges g, g+G, g+2G, ..., each of its S
+// wavefronts one interleaved slice.  Every group gets the same number of
+// ranges (the plan picks Q so), and at any moment the groups work on
+// neighbouring ranges, so the whole GPU sweeps one window of memory.
+
+struct PairRef {
+  uint64_t first;  // position in the padded sequence
+  uint32_t units;
+  fdot_desc_t d;
+};
+
+__device__ __forceinline__ PairRef load_pair(const Job& J, uint64_t k) {
+  PairRef P;
+  P.first = J.first[k];
+  P.units = J.units[k];
+  P.d = J.desc[k];
+  return P;
+}
+
+// Streams every piece of the padded sequence inside [lo, hi): pairs k, k+1,
+// ... (P describes pair k) up to the first that begins at or after hi.  The
+// next pair's descriptor is fetched while the current piece streams.
+template <class Pol>
+__device__ __forceinline__ void many_range(const FieldK& F, const Job& J, uint16_t* s_tab,
+                                           uint64_t k, PairRef P, uint64_t lo, uint64_t hi,
+                                           uint32_t lane, uint32_t slice, uint32_t S,
+                                           Combiner<Pol>& C) {
+  using E = typename Pol::E;
+  while (P.first < hi) {
+    const bool more = k + 1 < J.count;
+    PairRef P2 = P;
+    if (more) P2 = load_pair(J, k + 1);
+    if (P.d.n) {
+      const uint64_t a = P.first > lo ? P.first : lo;
+      const uint64_t end = P.first + P.d.n;
+      const uint64_t b = end < hi ? end : hi;
+      Pol L;
+      L.init(F);
+      if constexpr (HasTable<Pol>::value) L.tab = s_tab;
+      if (b > a)
+        wave_range<Pol>(L, (const E*)P.d.x + (a - P.first), (const E*)P.d.y + (a - P.first), b - a,
+                        lane, slice, S, F, J);
+      const uint64_t wsum = wave_sum(L.finish(F));
+      if (lane == 0) C.add(k, P.units, wsum, F, J);
+    }
+    if (!more) break;
+    ++k;
+    P = P2;
   }
 }
 
-// Chunk plan of a batch: offsets[k] = sum_{j<k} chunks(n_j),
-// offsets[count] = total; resets the claim counter.  Empty instances get the
-// zero element (all-zero bits in every representation) at once, since no
-// chunk will finish them.
+template <class Pol, int NTH>
+__global__ __launch_bounds__(NTH) void many_kernel(const FieldK F, const Job J) {
+  extern __shared__ uint16_t s_tab[];
+  if constexpr (HasTable<Pol>::value) load_table<Pol, NTH>(F, s_tab);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t sh = J.slice_shift;
+  const uint32_t S = 1u << sh;
+  const uint32_t w = blockIdx.x * (NTH / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t G = ((uint64_t)gridDim.x * (NTH / 64)) >> sh;
+  const uint64_t T = J.tq[0], Q = J.tq[1], R = J.tq[2];
+  uint64_t r = w >> sh;
+  if (r >= R) return;
+  Combiner<Pol> C;
+  // Two-deep prefetch over this group's ranges: while range r streams, the
+  // first pair of range r+G is being described and the start table entry of
+  // range r+2G is being read.
+  uint64_t k = J.start[r];
+  PairRef P = load_pair(J, k);
+  uint64_t kn = r + G < R ? J.start[r + G] : 0;
+  for (;;) {
+    const bool has_next = r + G < R;
+    PairRef Pn = P;
+    if (has_next) Pn = load_pair(J, kn);
+    const uint64_t kn2 = r + 2 * G < R ? J.start[r + 2 * G] : 0;
+    const uint64_t lo = r * Q;
+    const uint64_t hi = T - lo < Q ? T : lo + Q;
+    many_range<Pol>(F, J, s_tab, k, P, lo, hi, lane, w & (S - 1), S, C);
+    if (!has_next) break;
+    r += G;
+    k = kn;
+    P = Pn;
+    kn = kn2;
+  }
+  if (lane == 0) C.settle(F, J);
+}
+
+// Plan of a batch (one workgroup).  first[k] = sum over j < k of n_j rounded
+// up to a multiple of 64, T = first[count].  Q is T over a whole number of
+// ranges per group (about q_target elements each), rounded up to a multiple
+// of 64 so that a piece of a pair keeps the pair's alignment; R = ceil(T/Q),
+// at most max_ranges (the longer Q then).  units[k] = S x (ranges meeting
+// pair k's padded span); start[r] = the pair whose padded span holds r Q.
+// Empty pairs get the zero element (all-zero bits in every representation)
+// at once, since no unit will finish them.
 constexpr int PLAN_NT = 1024;
+
+__device__ __forceinline__ uint64_t pad64(uint64_t n) { return (n + 63) & ~63ull; }
+
 __global__ __launch_bounds__(PLAN_NT) void plan_kernel(const fdot_desc_t* desc, uint64_t count,
-                                                       uint64_t chunk, uint64_t* offsets,
-                                                       uint64_t* total, void* results,
-                                                       uint32_t elem_bytes,
-                                                       unsigned long long* next,
-                                                       uint32_t* owner, uint64_t owner_cap,
-                                                       uint32_t slice_shift) {
+                                                       uint32_t groups, uint32_t S,
+                                                       uint64_t q_target, uint32_t max_ranges,
+                                                       uint64_t* first, uint32_t* units,
+                                                       uint32_t* start, uint64_t* tq,
+                                                       void* results, uint32_t elem_bytes) {
   __shared__ uint64_t s[PLAN_NT];
   const uint32_t t = threadIdx.x;
   const uint64_t seg = (count + PLAN_NT - 1) / PLAN_NT;
   const uint64_t b = t * seg < count ? t * seg : count;
   const uint64_t e = b + seg < count ? b + seg : count;
   uint64_t local = 0;
-  for (uint64_t k = b; k < e; ++k) {
-    const uint64_t n = desc[k].n;
-    const uint64_t cs = chunk_of(n, chunk, slice_shift);
-    local += (n + cs - 1) / cs;
-  }
+  for (uint64_t k = b; k < e; ++k) local += pad64(load_s(&desc[k].n));
   s[t] = local;
   __syncthreads();
   for (uint32_t o = 1; o < PLAN_NT; o <<= 1) {  // inclusive scan
@@ -646,33 +736,34 @@ __global__ __launch_bounds__(PLAN_NT) void plan_kernel(const fdot_desc_t* desc, 
     s[t] += v;
     __syncthreads();
   }
+  const uint64_t T = s[PLAN_NT - 1];
+  const uint64_t per_round = (uint64_t)groups * (q_target < 64 ? 64 : q_target);
+  uint64_t rounds = (T + per_round / 2) / per_round;
+  if (rounds < 1) rounds = 1;
+  const uint64_t slots = (uint64_t)groups * rounds;
+  uint64_t Q = pad64((T + slots - 1) / slots);
+  if (Q == 0) Q = 64;
+  if ((T + Q - 1) / Q > max_ranges) Q = pad64((T + max_ranges - 1) / max_ranges);
   uint64_t run = s[t] - local;
   for (uint64_t k = b; k < e; ++k) {
-    offsets[k] = run;
-    const uint64_t n = desc[k].n;
-    const uint64_t cs = chunk_of(n, chunk, slice_shift);
-    run += (n + cs - 1) / cs;
-    if (n == 0) {
-      uint8_t* r = (uint8_t*)results + k * elem_bytes;
-      for (uint32_t i = 0; i < elem_bytes; ++i) r[i] = 0;
+    const uint64_t n = load_s(&desc[k].n);
+    const uint64_t pn = pad64(n);
+    first[k] = run;
+    if (pn) {
+      const uint64_t r0 = run / Q, r1 = (run + pn - 1) / Q;
+      units[k] = (uint32_t)((r1 - r0 + 1) * S);
+      for (uint64_t r = (run + Q - 1) / Q; r <= r1; ++r) start[r] = (uint32_t)k;
+    } else {
+      units[k] = 0;
+      uint8_t* res = (uint8_t*)results + k * elem_bytes;
+      for (uint32_t i = 0; i < elem_bytes; ++i) res[i] = 0;
     }
+    run += pn;
   }
-  if (t == PLAN_NT - 1) {
-    offsets[count] = s[t];
-    *total = s[t];
-    *next = 0;
-  }
-  // chunk -> pair table, each thread filling the chunk ranges of its own
-  // pairs (the batch kernel falls back to a binary search over the offsets
-  // when the batch has more chunks than the table holds)
-  if (s[PLAN_NT - 1] <= owner_cap) {
-    uint64_t c = s[t] - local;
-    for (uint64_t k = b; k < e; ++k) {
-      const uint64_t n = desc[k].n;
-      const uint64_t cs = chunk_of(n, chunk, slice_shift);
-      const uint64_t end = c + (n + cs - 1) / cs;
-      for (; c < end; ++c) owner[c] = (uint32_t)k;
-    }
+  if (t == 0) {
+    tq[0] = T;
+    tq[1] = Q;
+    tq[2] = (T + Q - 1) / Q;
   }
 }
 
@@ -827,44 +918,80 @@ static int resident_per_cu(const void* fn, int nth, size_t lds) {
   auto key = std::make_pair(fn, lds);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
-  if (lds > 65536) hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nth, lds) != hipSuccess || nb < 1) nb = 1;
   cache[key] = nb;
   return nb;
 }
 
+struct Launch {
+  FieldK F;
+  Job J;
+  bool many;
+  uint64_t work_waves;  // single form: units to cover
+  unsigned wg_per_cu;
+  size_t lds;
+  hipStream_t s;
+  const Workspace* ws;  // batched form
+  uint32_t max_groups;  // batched form: most groups of S wavefronts
+  uint64_t range;       // batched form: elements per range (target)
+  uint32_t elem_bytes;
+};
+
 template <class Pol, int NTH>
-static fdot_status_t launch_dot_t(const FieldK& F, const Job& J, bool many, uint64_t work_waves,
-                                  unsigned wg_per_cu, size_t lds, hipStream_t s) {
-  const void* fn = many ? (const void*)dot_kernel<Pol, NTH, true>
-                        : (const void*)dot_kernel<Pol, NTH, false>;
-  unsigned per_cu = (unsigned)resident_per_cu(fn, NTH, lds);
-  if (wg_per_cu < per_cu) per_cu = wg_per_cu;
+static fdot_status_t launch_t(Launch A) {
+  constexpr int WPW = NTH / 64;
+  const void* fn = A.many ? (const void*)many_kernel<Pol, NTH> : (const void*)dot_kernel<Pol, NTH>;
+  unsigned per_cu = (unsigned)resident_per_cu(fn, NTH, A.lds);
+  if (A.wg_per_cu < per_cu) per_cu = A.wg_per_cu;
   uint64_t grid = (uint64_t)fd_cu_count() * per_cu;
-  const uint64_t need = (work_waves + NTH / 64 - 1) / (NTH / 64);
-  if (need < grid) grid = need;
-  if (grid < 1) grid = 1;
-  if (many)
-    hipLaunchKernelGGL((dot_kernel<Pol, NTH, true>), dim3((unsigned)grid), dim3(NTH), lds, s, F, J);
-  else
-    hipLaunchKernelGGL((dot_kernel<Pol, NTH, false>), dim3((unsigned)grid), dim3(NTH), lds, s, F, J);
+  if (!A.many) {
+    const uint64_t need = (A.work_waves + WPW - 1) / WPW;
+    if (need < grid) grid = need;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL((dot_kernel<Pol, NTH>), dim3((unsigned)grid), dim3(NTH), A.lds, A.s, A.F,
+                       A.J);
+    return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
+  }
+  // Groups of S resident wavefronts; a pair meets at most R ranges, so
+  // S x R must fit the 16-bit unit count of its combination word.
+  const uint32_t S = 1u << A.J.slice_shift;
+  uint64_t groups = grid * WPW / S;
+  if (groups > A.max_groups) groups = A.max_groups;
+  if (groups < 1) groups = 1;
+  grid = (groups * S + WPW - 1) / WPW;
+  uint64_t max_ranges = kMaxUnits / S;
+  if (max_ranges > kMaxRanges) max_ranges = kMaxRanges;
+  if (max_ranges < groups) max_ranges = groups;  // S x groups <= resident waves < 2^16
+  Job J = A.J;
+  J.first = A.ws->first;
+  J.units = A.ws->units;
+  J.start = A.ws->start;
+  J.tq = A.ws->tq;
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(PLAN_NT), 0, A.s, J.desc, J.count,
+                     (uint32_t)groups, S, A.range, (uint32_t)max_ranges, A.ws->first,
+                     A.ws->units, A.ws->start, A.ws->tq, J.results, A.elem_bytes);
+  if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
+  hipLaunchKernelGGL((many_kernel<Pol, NTH>), dim3((unsigned)grid), dim3(NTH), A.lds, A.s, A.F, J);
   return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
 }
 
-static fdot_status_t dispatch(const Plan& pl, const FieldK& F, const Job& J, bool many,
-                              uint64_t work_waves, unsigned wpc, hipStream_t s) {
+static fdot_status_t dispatch(const Plan& pl, const Launch& A0) {
+  Launch A = A0;
+  A.lds = pl.lds;
   switch (pl.kind) {
-    case Kind::ZpzDelayed: return launch_dot_t<PZpzDelayed, 256>(F, J, many, work_waves, wpc, 0, s);
-    case Kind::ZpzPerTerm: return launch_dot_t<PZpzPerTerm, 256>(F, J, many, work_waves, wpc, 0, s);
-    case Kind::ZpzOverflow: return launch_dot_t<POverflow<false>, 256>(F, J, many, work_waves, wpc, 0, s);
-    case Kind::MontDelayed: return launch_dot_t<PMontDelayed, 256>(F, J, many, work_waves, wpc, 0, s);
-    case Kind::MontPerTerm: return launch_dot_t<PMontPerTerm, 256>(F, J, many, work_waves, wpc, 0, s);
-    case Kind::MontOverflow: return launch_dot_t<POverflow<true>, 256>(F, J, many, work_waves, wpc, 0, s);
-    case Kind::F64: return launch_dot_t<PF64, 256>(F, J, many, work_waves, wpc, 0, s);
-    case Kind::ZechExp: return launch_dot_t<PZechExp, 1024>(F, J, many, work_waves, wpc, pl.lds, s);
-    case Kind::ZechTplus1: return launch_dot_t<PZechTplus1, 1024>(F, J, many, work_waves, wpc, pl.lds, s);
-    case Kind::Centred: return launch_dot_t<PCentred, 256>(F, J, many, work_waves, wpc, 0, s);
+    case Kind::ZpzDelayed: return launch_t<PZpzDelayed, 256>(A);
+    case Kind::ZpzPerTerm: return launch_t<PZpzPerTerm, 256>(A);
+    case Kind::ZpzOverflow: return launch_t<POverflow<false>, 256>(A);
+    case Kind::MontDelayed: return launch_t<PMontDelayed, 256>(A);
+    case Kind::MontPerTerm: return launch_t<PMontPerTerm, 256>(A);
+    case Kind::MontOverflow: return launch_t<POverflow<true>, 256>(A);
+    case Kind::F64: return launch_t<PF64, 256>(A);
+    case Kind::ZechExp: return launch_t<PZechExp, 1024>(A);
+    case Kind::ZechTplus1: return launch_t<PZechTplus1, 1024>(A);
+    case Kind::Centred: return launch_t<PCentred, 256>(A);
   }
   return FDOT_E_UNSUPPORTED;
 }
@@ -881,19 +1008,24 @@ static const char* rep_key(int rep) {
 }
 
 // Launch parameters from the tuning table.  slices.<rep>: wavefronts that
-// share one chunk (1, 2, 4 or 8); dynamic.<rep>: batched units claimed from a
-// counter (1) or dealt round-robin (0); chunk.<rep>: elements per chunk of
-// the batched form (default 128 KiB per operand);
-// min_chunk.<rep>: smallest chunk of the single form, which otherwise spreads
-// a vector over every resident wavefront; wg_per_cu.<rep>: workgroups per CU
-// (further clamped by residency).
+// share one chunk of the single form (1, 2, 4 or 8); many.slices.<rep>: the
+// same for one range of the batched form (default 1);
+// many.groups.<rep>: most groups of the batched form (default: all resident
+// wavefronts / S); many.range.<rep>: bytes per operand of one range (default
+// 512 KiB); chunk.<rep>: largest chunk of the single form (default 128 KiB per
+// operand); min_chunk.<rep>: smallest chunk of the single form, which
+// otherwise spreads a vector over every resident wavefront; wg_per_cu.<rep>:
+// workgroups per CU (further clamped by residency).
 struct Shape {
   uint64_t chunk;
   unsigned wg_per_cu;
   int waves_per_wg;
   uint32_t slice_shift;
-  uint32_t dynamic;
+  uint32_t max_groups;
+  uint64_t range;
 };
+
+static uint32_t log2_slices(int64_t sl) { return sl >= 8 ? 3 : sl >= 4 ? 2 : sl >= 2 ? 1 : 0; }
 
 static Shape shape_for(const fdot_field_s* f, uint64_t n_single) {
   char key[64];
@@ -902,24 +1034,33 @@ static Shape shape_for(const fdot_field_s* f, uint64_t n_single) {
   const uint64_t eb = f->info.elem_bytes;
   Shape sh;
   sh.waves_per_wg = zech ? 16 : 4;
-  snprintf(key, sizeof key, "slices.%s", r);
-  const int64_t sl = fd_tune(key, 1);
-  sh.slice_shift = sl >= 8 ? 3 : sl >= 4 ? 2 : sl >= 2 ? 1 : 0;
-  snprintf(key, sizeof key, "dynamic.%s", r);
-  sh.dynamic = fd_tune(key, 0) != 0;
   snprintf(key, sizeof key, "wg_per_cu.%s", r);
-  int64_t wpc = fd_tune(key, zech ? 2 : 2);
+  int64_t wpc = fd_tune(key, 2);
   sh.wg_per_cu = (unsigned)(wpc < 1 ? 1 : wpc);
+  sh.max_groups = kMaxRanges;
+  sh.range = 0;
+  sh.chunk = 0;
+  if (!n_single) {
+    snprintf(key, sizeof key, "many.slices.%s", r);
+    sh.slice_shift = log2_slices(fd_tune(key, 1));
+    snprintf(key, sizeof key, "many.groups.%s", r);
+    const int64_t mg = fd_tune(key, (int64_t)kMaxRanges);
+    sh.max_groups = (uint32_t)(mg < 1 ? 1 : mg > (int64_t)kMaxRanges ? kMaxRanges : mg);
+    snprintf(key, sizeof key, "many.range.%s", r);
+    const int64_t rb = fd_tune(key, 524288);
+    sh.range = (uint64_t)(rb < 64 ? 64 : rb) / eb;
+    return sh;
+  }
+  snprintf(key, sizeof key, "slices.%s", r);
+  sh.slice_shift = log2_slices(fd_tune(key, 1));
   snprintf(key, sizeof key, "chunk.%s", r);
   int64_t chunk = fd_tune(key, (int64_t)(131072 / eb));
-  if (n_single) {
-    snprintf(key, sizeof key, "min_chunk.%s", r);
-    int64_t mn = fd_tune(key, (int64_t)(16384 / eb));
-    const uint64_t waves = (uint64_t)fd_cu_count() * sh.wg_per_cu * sh.waves_per_wg;
-    const int64_t spread = (int64_t)((n_single + waves - 1) / waves);
-    chunk = spread < chunk ? spread : chunk;
-    if (chunk < mn) chunk = mn;
-  }
+  snprintf(key, sizeof key, "min_chunk.%s", r);
+  int64_t mn = fd_tune(key, (int64_t)(16384 / eb));
+  const uint64_t waves = (uint64_t)fd_cu_count() * sh.wg_per_cu * sh.waves_per_wg;
+  const int64_t spread = (int64_t)((n_single + waves - 1) / waves);
+  chunk = spread < chunk ? spread : chunk;
+  if (chunk < mn) chunk = mn;
   chunk = (chunk + 15) / 16 * 16;
   if (chunk < 64) chunk = 64;
   sh.chunk = (uint64_t)chunk;
@@ -953,18 +1094,23 @@ fdot_status_t fd_launch_dot(const fdot_field_s* f, fdot_algo_t algo, const void*
   Plan pl;
   fdot_status_t st = make_plan(f, algo, &pl);
   if (st != FDOT_OK) return st;
-  Job J;
-  memset(&J, 0, sizeof J);
-  J.x = x;
-  J.y = y;
-  J.n = n;
-  J.chunk = sh.chunk;
-  J.acc = ws->acc;
-  J.results = result;
-  J.fold_vecs = pl.fold_vecs;
-  J.slice_shift = sh.slice_shift;
+  Launch A;
+  memset(&A, 0, sizeof A);
+  A.F = f->k;
+  A.J.x = x;
+  A.J.y = y;
+  A.J.n = n;
+  A.J.chunk = sh.chunk;
+  A.J.acc = ws->acc;
+  A.J.results = result;
+  A.J.fold_vecs = pl.fold_vecs;
+  A.J.slice_shift = sh.slice_shift;
+  A.many = false;
   const uint64_t cs = chunk_of(n, sh.chunk, sh.slice_shift);
-  return dispatch(pl, f->k, J, false, ((n + cs - 1) / cs) << sh.slice_shift, sh.wg_per_cu, s);
+  A.work_waves = ((n + cs - 1) / cs) << sh.slice_shift;
+  A.wg_per_cu = sh.wg_per_cu;
+  A.s = s;
+  return dispatch(pl, A);
 }
 
 fdot_status_t fd_launch_many(const fdot_field_s* f, fdot_algo_t algo, size_t count,
@@ -975,26 +1121,23 @@ fdot_status_t fd_launch_many(const fdot_field_s* f, fdot_algo_t algo, size_t cou
   Plan pl;
   fdot_status_t st = make_plan(f, algo, &pl);
   if (st != FDOT_OK) return st;
-  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(PLAN_NT), 0, s, desc, (uint64_t)count, sh.chunk,
-                     ws->offsets, ws->total, results, f->info.elem_bytes, ws->next, ws->owner,
-                     (uint64_t)ws->owner_cap, sh.slice_shift);
-  if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
-  Job J;
-  memset(&J, 0, sizeof J);
-  J.desc = desc;
-  J.count = count;
-  J.offsets = ws->offsets;
-  J.total = ws->total;
-  J.next = ws->next;
-  J.owner = ws->owner;
-  J.owner_cap = ws->owner_cap;
-  J.slice_shift = sh.slice_shift;
-  J.dynamic = sh.dynamic;
-  J.chunk = sh.chunk;
-  J.acc = ws->acc;
-  J.results = results;
-  J.fold_vecs = pl.fold_vecs;
-  return dispatch(pl, f->k, J, true, ~0ull >> 8, sh.wg_per_cu, s);
+  Launch A;
+  memset(&A, 0, sizeof A);
+  A.F = f->k;
+  A.J.desc = desc;
+  A.J.count = count;
+  A.J.acc = ws->acc;
+  A.J.results = results;
+  A.J.fold_vecs = pl.fold_vecs;
+  A.J.slice_shift = sh.slice_shift;
+  A.many = true;
+  A.wg_per_cu = sh.wg_per_cu;
+  A.s = s;
+  A.ws = ws;
+  A.max_groups = sh.max_groups;
+  A.range = sh.range;
+  A.elem_bytes = f->info.elem_bytes;
+  return dispatch(pl, A);
 }
 
 fdot_status_t fd_launch_encode(const fdot_field_s* f, const uint32_t* canon, void* rep, size_t n,
@@ -1027,7 +1170,9 @@ static fdot_status_t launch_gemv_t(const fdot_field_s* f, const Job& J, size_t m
                                    const void* A, size_t lda, const void* x, void* y, size_t lds,
                                    hipStream_t s) {
   auto fn = gemv_kernel<Pol>;
-  if (lds > 65536) hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
   hipLaunchKernelGGL(fn, dim3((unsigned)((m + 3) / 4)), dim3(256), lds, s, f->k, J, (uint64_t)m,
                      (uint64_t)n, (uint64_t)lda, A, x, y);
   return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;

@@ -19,20 +19,24 @@ struct fdot_field_s {
   uint16_t* d_zidx;
 };
 
-// Device scratch owned per stream: one combination word per instance (residue
-// sum and finished-chunk count, returned to zero by the wavefront that
-// finishes the instance, so no clearing happens between calls), and the chunk
-// plan of a batch (prefix offsets, chunk -> instance table, claim counter).
+// Most ranges of one batched launch (one per group of resident wavefronts).
+constexpr uint32_t kMaxRanges = 1u << 16;
+
+// Device scratch owned per stream: one combination word per pair (residue
+// sum and finished-unit count, returned to zero by the wavefront that
+// finishes the pair, so no clearing happens between calls), and the plan of
+// a batch (pair positions and unit counts, first pair of each range, total
+// and range length), rewritten by every batched call.
+
 struct Workspace {
   int device = -1;
-  size_t cap = 0;          // instances
+  size_t cap = 0;                     // pairs
   void* base = nullptr;
-  unsigned long long* acc = nullptr;  // cap
-  uint32_t* owner = nullptr;          // owner_cap: chunk -> instance
-  size_t owner_cap = 0;
-  uint64_t* offsets = nullptr;        // cap + 1 (chunk prefix sums)
-  uint64_t* total = nullptr;          // 1
-  unsigned long long* next = nullptr; // 1: chunk counter of the batched form
+  unsigned long long* acc = nullptr;  // cap: combination words
+  uint64_t* first = nullptr;          // cap: position of each pair in the padded sequence
+  uint32_t* units = nullptr;          // cap: units of each pair
+  uint32_t* start = nullptr;          // kMaxRanges: first pair of each range
+  uint64_t* tq = nullptr;             // 8: the batch's ranges and their claim counter
   bool captured = false;  // handed to a graph capture: never freed on growth
 };
 

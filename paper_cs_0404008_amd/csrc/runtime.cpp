@@ -87,10 +87,9 @@ fdot_status_t fd_workspace_get(hipStream_t s, size_t count, Workspace** out) {
   // Growing allocates, which a stream under graph capture cannot do.
   if (capturing) return FDOT_E_BUSY;
   size_t cap = count < 4096 ? 4096 : count;
-  const size_t owner_cap = cap * 64 < (1u << 20) ? (1u << 20) : cap * 64;
-  const size_t bytes_acc = cap * 8, bytes_owner = (owner_cap * 4 + 7) / 8 * 8,
-               bytes_off = (cap + 1) * 8;
-  const size_t bytes = bytes_acc + bytes_owner + bytes_off + 16;
+  const size_t bytes_acc = cap * 8, bytes_first = cap * 8, bytes_units = (cap * 4 + 7) / 8 * 8,
+               bytes_start = (size_t)kMaxRanges * 4;
+  const size_t bytes = bytes_acc + bytes_first + bytes_units + bytes_start + 64;
   void* base = nullptr;
   if (hipMalloc(&base, bytes) != hipSuccess) return FDOT_E_NOMEM;
   if (fd_launch_zero(base, bytes, s) != FDOT_OK) {
@@ -112,11 +111,10 @@ fdot_status_t fd_workspace_get(hipStream_t s, size_t count, Workspace** out) {
   w->base = base;
   char* b = (char*)base;
   w->acc = (unsigned long long*)b;
-  w->owner = (uint32_t*)(b + bytes_acc);
-  w->owner_cap = owner_cap;
-  w->offsets = (uint64_t*)(b + bytes_acc + bytes_owner);
-  w->total = (uint64_t*)(b + bytes_acc + bytes_owner + bytes_off);
-  w->next = (unsigned long long*)(b + bytes_acc + bytes_owner + bytes_off + 8);
+  w->first = (uint64_t*)(b + bytes_acc);
+  w->units = (uint32_t*)(b + bytes_acc + bytes_first);
+  w->start = (uint32_t*)(b + bytes_acc + bytes_first + bytes_units);
+  w->tq = (uint64_t*)(b + bytes_acc + bytes_first + bytes_units + bytes_start);
   *out = w;
   return FDOT_OK;
 }

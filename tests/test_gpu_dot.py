@@ -111,43 +111,63 @@ def test_batched_matches_oracle_and_single(p, rep, algo):
     assert same(got, again)
 
 
-def test_many_chunks_per_workgroup():
-    """Force few workgroups and small chunks so each workgroup loops over many
-    chunks of many instances."""
+@pytest.mark.parametrize("slices,groups,range_bytes",
+                         [(1, None, None), (4, None, None), (2, 7, 64), (4, 3, None),
+                          (1, 1, 256), (8, 5000, 1 << 20), (1, 65536, 4096), (4, None, 64),
+                          (8, 2, 1 << 30)])
+def test_batched_range_shapes(slices, groups, range_bytes):
+    """The batched form with few groups (each streams pieces of many pairs)
+    and many (each pair split over many ranges), one to eight wavefronts per
+    range, and ranges from 64 bytes to the whole batch."""
     p, rep = 65521, "zpz"
     F = field(p, rep)
-    fd.tune_set("chunk.zpz", 1024)
-    fd.tune_set("wg_per_cu.zpz", 1)
+    keys = {"many.slices.zpz": slices, "many.groups.zpz": groups, "many.range.zpz": range_bytes}
+    for k, v in keys.items():
+        fd.tune_set(k, v)
     try:
-        ns = [int(v) for v in synth.log_uniform_lengths(9, 0, 300, 2.0, 5.0)]
+        ns = [int(v) for v in synth.log_uniform_lengths(9, 0, 300, 0.0, 5.0)]
+        ns[7] = 0
+        ns[100] = 1_000_003
         xs = [to_dev(stored(p, rep, n, 33, 2 * k)) for k, n in enumerate(ns)]
         ys = [to_dev(stored(p, rep, n, 33, 2 * k + 1)) for k, n in enumerate(ns)]
-        got = to_host(F.dot_many(fd.Field.make_desc(xs, ys)))
         want = oracle.dot_many(p, rep, [to_host(x) for x in xs], [to_host(y) for y in ys])
-        assert same(got, want)
-        n = 1_000_003
-        x, y = stored(p, rep, n, 34, 0), stored(p, rep, n, 34, 1)
-        assert same(to_host(F.dot(to_dev(x), to_dev(y)))[0], oracle.dot(p, rep, x, y))
+        for _ in range(2):
+            got = to_host(F.dot_many(fd.Field.make_desc(xs, ys)))
+            assert same(got, want)
+        # a batch of one pair and a batch smaller than the number of ranges
+        got = to_host(F.dot_many(fd.Field.make_desc(xs[100:101], ys[100:101])))
+        assert same(got, want[100:101])
+        got = to_host(F.dot_many(fd.Field.make_desc(xs[:5], ys[:5])))
+        assert same(got, want[:5])
     finally:
-        fd.tune_set("chunk.zpz", None)
-        fd.tune_set("wg_per_cu.zpz", None)
+        for k in keys:
+            fd.tune_set(k, None)
 
 
 def test_centred_fold_path():
-    """One chunk long enough that a lane's int32 accumulator must be flushed
-    to 64 bits several times."""
+    """A piece long enough that a lane's int32 accumulator must be flushed
+    to 64 bits several times, in the single and the batched form."""
     p, rep = 251, "centred"
     F = field(p, rep)
     fd.tune_set("chunk.centred", 1 << 24)
     fd.tune_set("min_chunk.centred", 1 << 24)
+    fd.tune_set("many.slices.centred", 1)
+    fd.tune_set("many.groups.centred", 1)
+    fd.tune_set("many.range.centred", 1 << 30)
     try:
         n = (1 << 24) + 77
         for pattern in ("random", "maxprod"):
             x, y = stored(p, rep, n, 35, 0, pattern), stored(p, rep, n, 35, 1, pattern)
-            assert same(to_host(F.dot(to_dev(x), to_dev(y)))[0], oracle.dot(p, rep, x, y))
+            want = oracle.dot(p, rep, x, y)
+            xd, yd = to_dev(x), to_dev(y)
+            assert same(to_host(F.dot(xd, yd))[0], want)
+            got = to_host(F.dot_many(fd.Field.make_desc([xd, xd[:1000]], [yd, yd[:1000]])))
+            assert same(got[0], want)
+            assert same(got[1], oracle.dot(p, rep, x[:1000], y[:1000]))
     finally:
-        fd.tune_set("chunk.centred", None)
-        fd.tune_set("min_chunk.centred", None)
+        for k in ("chunk.centred", "min_chunk.centred", "many.slices.centred",
+                  "many.groups.centred", "many.range.centred"):
+            fd.tune_set(k, None)
 
 
 @pytest.mark.parametrize("p,rep", [(32749, "zpz"), (2147483647, "mont"), (4294967291, "mont"),

@@ -108,7 +108,8 @@ def test_graph_replays_are_independent_of_history():
     x = torch.empty(1 << 20, dtype=torch.uint32, device="cuda")
     y = torch.empty(1 << 20, dtype=torch.uint32, device="cuda")
     refill([x, y], 65521, "zpz", 698)
-    g, out = capture(lambda: F.dot_many(fd.Field.make_desc([x], [y])))
+    desc1 = fd.Field.make_desc([x], [y])
+    g, out = capture(lambda: F.dot_many(desc1))
     s = capture.stream
     want = oracle.dot(65521, "zpz", to_host(x), to_host(y))
     for r in range(REPLAYS):
