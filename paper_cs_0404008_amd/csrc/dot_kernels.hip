@@ -74,10 +74,14 @@ struct Job {
   const uint32_t* units;     // batched: units of each pair
   const uint32_t* start;     // batched: first pair of each range
   const uint64_t* tq;        // batched: padded total T, range length Q, ranges R
+  uint64_t q_target;         // batched: elements per range (target)
+  uint32_t groups;           // batched: groups of S wavefronts
+  uint32_t max_ranges;       // batched: most ranges
   unsigned long long* acc;   // combination words, one per pair
   void* results;
   uint32_t fold_vecs;        // vectors between two folds
   uint32_t slice_shift;      // log2 of the wavefronts sharing one chunk or range
+  uint32_t elem_bytes;       // bytes of one result
 };
 
 // Chunk length used for a pair of length n: the configured chunk, or longer
@@ -627,27 +631,58 @@ struct PairRef {
   fdot_desc_t d;
 };
 
-__device__ __forceinline__ PairRef load_pair(const Job& J, uint64_t k) {
-  PairRef P;
-  P.first = J.first[k];
-  P.units = J.units[k];
-  P.d = J.desc[k];
-  return P;
-}
+// Where a batch's plan lives: the tables written by plan_kernel, or the
+// workgroup's own prefix sums in LDS (fused form, small batches).
+struct PlanTables {
+  const Job* J;
+  __device__ __forceinline__ PairRef pair(uint64_t k) const {
+    PairRef P;
+    P.first = J->first[k];
+    P.units = J->units[k];
+    P.d = J->desc[k];
+    return P;
+  }
+  __device__ __forceinline__ uint64_t start(uint64_t r, uint64_t) const { return J->start[r]; }
+};
+
+struct PlanLds {
+  const Job* J;
+  const uint64_t* pf;  // pf[k] = first[k], pf[count] = T
+  uint64_t Q;
+  uint32_t S;
+  __device__ __forceinline__ PairRef pair(uint64_t k) const {
+    PairRef P;
+    P.first = pf[k];
+    const uint64_t end = pf[k + 1];
+    P.units = end > P.first ? (uint32_t)((end - 1) / Q - P.first / Q + 1) * S : 0u;
+    P.d = J->desc[k];
+    return P;
+  }
+  // the pair whose padded span holds lo: largest k with pf[k] <= lo
+  __device__ __forceinline__ uint64_t start(uint64_t, uint64_t lo) const {
+    uint64_t a = 0, b = J->count;
+    while (a + 1 < b) {
+      const uint64_t m = (a + b) >> 1;
+      if (pf[m] <= lo) a = m; else b = m;
+    }
+    while (a + 1 < J->count && pf[a + 1] <= lo) ++a;
+    return a;
+  }
+};
 
 // Streams every piece of the padded sequence inside [lo, hi): pairs k, k+1,
 // ... (P describes pair k) up to the first that begins at or after hi.  The
 // next pair's descriptor is fetched while the current piece streams.
-template <class Pol>
-__device__ __forceinline__ void many_range(const FieldK& F, const Job& J, uint16_t* s_tab,
-                                           uint64_t k, PairRef P, uint64_t lo, uint64_t hi,
-                                           uint32_t lane, uint32_t slice, uint32_t S,
+template <class Pol, class Src>
+__device__ __forceinline__ void many_range(const FieldK& F, const Job& J, const Src& src,
+                                           uint16_t* s_tab, uint64_t k, PairRef P, uint64_t lo,
+                                           uint64_t hi, uint32_t lane, uint32_t slice, uint32_t S,
                                            Combiner<Pol>& C) {
   using E = typename Pol::E;
   while (P.first < hi) {
     const bool more = k + 1 < J.count;
     PairRef P2 = P;
-    if (more) P2 = load_pair(J, k + 1);
+    if (more) P2 = src.pair(k + 1);
     if (P.d.n) {
       const uint64_t a = P.first > lo ? P.first : lo;
       const uint64_t end = P.first + P.d.n;
@@ -667,38 +702,117 @@ __device__ __forceinline__ void many_range(const FieldK& F, const Job& J, uint16
   }
 }
 
-template <class Pol, int NTH>
+// Range length and count of a batch of padded total T: a whole number of
+// ranges per group, about q_target elements each, rounded up to a multiple
+// of 64 so that a piece of a pair keeps the pair's alignment; at most
+// max_ranges ranges (the longer Q then).
+__host__ __device__ __forceinline__ void batch_ranges(uint64_t T, uint64_t groups,
+                                                      uint64_t q_target, uint64_t max_ranges,
+                                                      uint64_t* Q_out, uint64_t* R_out) {
+  const uint64_t per_round = groups * (q_target < 64 ? 64 : q_target);
+  uint64_t rounds = (T + per_round / 2) / per_round;
+  if (rounds < 1) rounds = 1;
+  const uint64_t slots = groups * rounds;
+  uint64_t Q = ((T + slots - 1) / slots + 63) & ~63ull;
+  if (Q == 0) Q = 64;
+  if ((T + Q - 1) / Q > max_ranges) Q = ((T + max_ranges - 1) / max_ranges + 63) & ~63ull;
+  *Q_out = Q;
+  *R_out = (T + Q - 1) / Q;
+}
+
+// Batched kernel.  FUSED: the workgroup first builds the batch's prefix
+// sums in LDS itself (batches of at most kFusedMax pairs), instead of
+// reading the tables of a separate plan launch; workgroup 0 also writes
+// the zero element of empty pairs.
+constexpr uint32_t kFusedMax = 7680;  // LDS: (7680 + 1 + 256) x 8 bytes < 64 KiB
+
+template <class Pol, int NTH, bool FUSED>
 __global__ __launch_bounds__(NTH) void many_kernel(const FieldK F, const Job J) {
-  extern __shared__ uint16_t s_tab[];
+  extern __shared__ __align__(16) unsigned char s_raw[];
+  uint16_t* s_tab = (uint16_t*)s_raw;
   if constexpr (HasTable<Pol>::value) load_table<Pol, NTH>(F, s_tab);
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t sh = J.slice_shift;
   const uint32_t S = 1u << sh;
   const uint32_t w = blockIdx.x * (NTH / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint64_t G = ((uint64_t)gridDim.x * (NTH / 64)) >> sh;
-  const uint64_t T = J.tq[0], Q = J.tq[1], R = J.tq[2];
+  const uint64_t G = J.groups;
+  uint64_t T, Q, R;
+  PlanLds lsrc;
+  if constexpr (FUSED) {
+    uint64_t* pf = (uint64_t*)s_raw;         // count + 1
+    uint64_t* part = pf + J.count + 1;       // NTH
+    const uint32_t t = threadIdx.x;
+    for (uint64_t k = t; k < J.count; k += NTH) pf[k + 1] = (load_s(&J.desc[k].n) + 63) & ~63ull;
+    if (t == 0) pf[0] = 0;
+    __syncthreads();
+    const uint64_t seg = (J.count + NTH - 1) / NTH;
+    const uint64_t b = t * seg < J.count ? t * seg : J.count;
+    const uint64_t e = b + seg < J.count ? b + seg : J.count;
+    uint64_t run = 0;
+    for (uint64_t k = b; k < e; ++k) {
+      run += pf[k + 1];
+      pf[k + 1] = run;
+    }
+    part[t] = run;
+    __syncthreads();
+    for (uint32_t o = 1; o < NTH; o <<= 1) {  // inclusive scan of the segment totals
+      const uint64_t v = t >= o ? part[t - o] : 0;
+      __syncthreads();
+      part[t] += v;
+      __syncthreads();
+    }
+    const uint64_t off = part[t] - run;
+    for (uint64_t k = b; k < e; ++k) pf[k + 1] += off;
+    __syncthreads();
+    T = pf[J.count];
+    batch_ranges(T, G, J.q_target, J.max_ranges, &Q, &R);
+    if (blockIdx.x == 0) {
+      for (uint64_t k = t; k < J.count; k += NTH)
+        if (pf[k + 1] == pf[k]) {
+          uint8_t* res = (uint8_t*)J.results + k * J.elem_bytes;
+          for (uint32_t i = 0; i < J.elem_bytes; ++i) res[i] = 0;
+        }
+    }
+    lsrc.J = &J;
+    lsrc.pf = pf;
+    lsrc.Q = Q;
+    lsrc.S = S;
+  } else {
+    T = J.tq[0];
+    Q = J.tq[1];
+    R = J.tq[2];
+  }
   uint64_t r = w >> sh;
-  if (r >= R) return;
+  if (r >= R || r >= G) return;
   Combiner<Pol> C;
-  // Two-deep prefetch over this group's ranges: while range r streams, the
-  // first pair of range r+G is being described and the start table entry of
-  // range r+2G is being read.
-  uint64_t k = J.start[r];
-  PairRef P = load_pair(J, k);
-  uint64_t kn = r + G < R ? J.start[r + G] : 0;
-  for (;;) {
-    const bool has_next = r + G < R;
-    PairRef Pn = P;
-    if (has_next) Pn = load_pair(J, kn);
-    const uint64_t kn2 = r + 2 * G < R ? J.start[r + 2 * G] : 0;
-    const uint64_t lo = r * Q;
-    const uint64_t hi = T - lo < Q ? T : lo + Q;
-    many_range<Pol>(F, J, s_tab, k, P, lo, hi, lane, w & (S - 1), S, C);
-    if (!has_next) break;
-    r += G;
-    k = kn;
-    P = Pn;
-    kn = kn2;
+  auto run_ranges = [&](const auto& src) {
+    // Two-deep prefetch over this group's ranges: while range r streams, the
+    // first pair of range r+G is being described and the start of range
+    // r+2G is being looked up.
+    uint64_t k = src.start(r, r * Q);
+    PairRef P = src.pair(k);
+    uint64_t kn = r + G < R ? src.start(r + G, (r + G) * Q) : 0;
+    for (;;) {
+      const bool has_next = r + G < R;
+      PairRef Pn = P;
+      if (has_next) Pn = src.pair(kn);
+      const uint64_t kn2 = r + 2 * G < R ? src.start(r + 2 * G, (r + 2 * G) * Q) : 0;
+      const uint64_t lo = r * Q;
+      const uint64_t hi = T - lo < Q ? T : lo + Q;
+      many_range<Pol>(F, J, src, s_tab, k, P, lo, hi, lane, w & (S - 1), S, C);
+      if (!has_next) break;
+      r += G;
+      k = kn;
+      P = Pn;
+      kn = kn2;
+    }
+  };
+  if constexpr (FUSED) {
+    run_ranges(lsrc);
+  } else {
+    PlanTables tsrc;
+    tsrc.J = &J;
+    run_ranges(tsrc);
   }
   if (lane == 0) C.settle(F, J);
 }
@@ -737,13 +851,8 @@ __global__ __launch_bounds__(PLAN_NT) void plan_kernel(const fdot_desc_t* desc, 
     __syncthreads();
   }
   const uint64_t T = s[PLAN_NT - 1];
-  const uint64_t per_round = (uint64_t)groups * (q_target < 64 ? 64 : q_target);
-  uint64_t rounds = (T + per_round / 2) / per_round;
-  if (rounds < 1) rounds = 1;
-  const uint64_t slots = (uint64_t)groups * rounds;
-  uint64_t Q = pad64((T + slots - 1) / slots);
-  if (Q == 0) Q = 64;
-  if ((T + Q - 1) / Q > max_ranges) Q = pad64((T + max_ranges - 1) / max_ranges);
+  uint64_t Q, R;
+  batch_ranges(T, groups, q_target, max_ranges, &Q, &R);
   uint64_t run = s[t] - local;
   for (uint64_t k = b; k < e; ++k) {
     const uint64_t n = load_s(&desc[k].n);
@@ -763,7 +872,7 @@ __global__ __launch_bounds__(PLAN_NT) void plan_kernel(const fdot_desc_t* desc, 
   if (t == 0) {
     tq[0] = T;
     tq[1] = Q;
-    tq[2] = (T + Q - 1) / Q;
+    tq[2] = R;
   }
 }
 
@@ -937,14 +1046,19 @@ struct Launch {
   const Workspace* ws;  // batched form
   uint32_t max_groups;  // batched form: most groups of S wavefronts
   uint64_t range;       // batched form: elements per range (target)
+  uint32_t fused;       // batched form: largest batch planned inside the kernel
   uint32_t elem_bytes;
 };
 
 template <class Pol, int NTH>
 static fdot_status_t launch_t(Launch A) {
   constexpr int WPW = NTH / 64;
-  const void* fn = A.many ? (const void*)many_kernel<Pol, NTH> : (const void*)dot_kernel<Pol, NTH>;
-  unsigned per_cu = (unsigned)resident_per_cu(fn, NTH, A.lds);
+  const bool fused = A.many && !HasTable<Pol>::value && A.J.count <= A.fused;
+  const size_t lds = fused ? (size_t)(A.J.count + 1 + NTH) * sizeof(uint64_t) : A.lds;
+  const void* fn = !A.many ? (const void*)dot_kernel<Pol, NTH>
+                   : fused ? (const void*)many_kernel<Pol, NTH, true>
+                           : (const void*)many_kernel<Pol, NTH, false>;
+  unsigned per_cu = (unsigned)resident_per_cu(fn, NTH, (lds + 8191) & ~(size_t)8191);
   if (A.wg_per_cu < per_cu) per_cu = A.wg_per_cu;
   uint64_t grid = (uint64_t)fd_cu_count() * per_cu;
   if (!A.many) {
@@ -970,11 +1084,20 @@ static fdot_status_t launch_t(Launch A) {
   J.units = A.ws->units;
   J.start = A.ws->start;
   J.tq = A.ws->tq;
-  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(PLAN_NT), 0, A.s, J.desc, J.count,
-                     (uint32_t)groups, S, A.range, (uint32_t)max_ranges, A.ws->first,
-                     A.ws->units, A.ws->start, A.ws->tq, J.results, A.elem_bytes);
-  if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
-  hipLaunchKernelGGL((many_kernel<Pol, NTH>), dim3((unsigned)grid), dim3(NTH), A.lds, A.s, A.F, J);
+  J.q_target = A.range;
+  J.groups = (uint32_t)groups;
+  J.max_ranges = (uint32_t)max_ranges;
+  if (fused) {
+    hipLaunchKernelGGL((many_kernel<Pol, NTH, true>), dim3((unsigned)grid), dim3(NTH), lds, A.s,
+                       A.F, J);
+  } else {
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(PLAN_NT), 0, A.s, J.desc, J.count,
+                       (uint32_t)groups, S, A.range, (uint32_t)max_ranges, A.ws->first,
+                       A.ws->units, A.ws->start, A.ws->tq, J.results, A.elem_bytes);
+    if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
+    hipLaunchKernelGGL((many_kernel<Pol, NTH, false>), dim3((unsigned)grid), dim3(NTH), A.lds,
+                       A.s, A.F, J);
+  }
   return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
 }
 
@@ -1012,8 +1135,10 @@ static const char* rep_key(int rep) {
 // same for one range of the batched form (default 1);
 // many.groups.<rep>: most groups of the batched form (default: all resident
 // wavefronts / S); many.range.<rep>: bytes per operand of one range (default
-// 512 KiB); chunk.<rep>: largest chunk of the single form (default 128 KiB per
-// operand); min_chunk.<rep>: smallest chunk of the single form, which
+// 512 KiB); many.fused.<rep>: largest batch whose plan is built inside the
+// batched kernel (default 512, at most 7680; larger batches get a separate
+// plan launch); chunk.<rep>: largest chunk of the single form (default 128
+// KiB per operand); min_chunk.<rep>: smallest chunk of the single form, which
 // otherwise spreads a vector over every resident wavefront; wg_per_cu.<rep>:
 // workgroups per CU (further clamped by residency).
 struct Shape {
@@ -1023,6 +1148,7 @@ struct Shape {
   uint32_t slice_shift;
   uint32_t max_groups;
   uint64_t range;
+  uint32_t fused;  // largest batch planned inside the kernel (0: never)
 };
 
 static uint32_t log2_slices(int64_t sl) { return sl >= 8 ? 3 : sl >= 4 ? 2 : sl >= 2 ? 1 : 0; }
@@ -1039,6 +1165,7 @@ static Shape shape_for(const fdot_field_s* f, uint64_t n_single) {
   sh.wg_per_cu = (unsigned)(wpc < 1 ? 1 : wpc);
   sh.max_groups = kMaxRanges;
   sh.range = 0;
+  sh.fused = 0;
   sh.chunk = 0;
   if (!n_single) {
     snprintf(key, sizeof key, "many.slices.%s", r);
@@ -1049,6 +1176,9 @@ static Shape shape_for(const fdot_field_s* f, uint64_t n_single) {
     snprintf(key, sizeof key, "many.range.%s", r);
     const int64_t rb = fd_tune(key, 524288);
     sh.range = (uint64_t)(rb < 64 ? 64 : rb) / eb;
+    snprintf(key, sizeof key, "many.fused.%s", r);
+    const int64_t fz = fd_tune(key, 512);
+    sh.fused = (uint32_t)(fz < 0 ? 0 : fz > (int64_t)kFusedMax ? kFusedMax : fz);
     return sh;
   }
   snprintf(key, sizeof key, "slices.%s", r);
@@ -1136,7 +1266,9 @@ fdot_status_t fd_launch_many(const fdot_field_s* f, fdot_algo_t algo, size_t cou
   A.ws = ws;
   A.max_groups = sh.max_groups;
   A.range = sh.range;
+  A.fused = sh.fused;
   A.elem_bytes = f->info.elem_bytes;
+  A.J.elem_bytes = f->info.elem_bytes;
   return dispatch(pl, A);
 }
 

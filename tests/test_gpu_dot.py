@@ -111,17 +111,20 @@ def test_batched_matches_oracle_and_single(p, rep, algo):
     assert same(got, again)
 
 
+@pytest.mark.parametrize("fused", [None, 0, 7680])
 @pytest.mark.parametrize("slices,groups,range_bytes",
                          [(1, None, None), (4, None, None), (2, 7, 64), (4, 3, None),
                           (1, 1, 256), (8, 5000, 1 << 20), (1, 65536, 4096), (4, None, 64),
                           (8, 2, 1 << 30)])
-def test_batched_range_shapes(slices, groups, range_bytes):
+def test_batched_range_shapes(slices, groups, range_bytes, fused):
     """The batched form with few groups (each streams pieces of many pairs)
     and many (each pair split over many ranges), one to eight wavefronts per
-    range, and ranges from 64 bytes to the whole batch."""
+    range, and ranges from 64 bytes to the whole batch; with the plan built
+    by a separate launch and inside the kernel."""
     p, rep = 65521, "zpz"
     F = field(p, rep)
-    keys = {"many.slices.zpz": slices, "many.groups.zpz": groups, "many.range.zpz": range_bytes}
+    keys = {"many.slices.zpz": slices, "many.groups.zpz": groups, "many.range.zpz": range_bytes,
+            "many.fused.zpz": fused}
     for k, v in keys.items():
         fd.tune_set(k, v)
     try:
