@@ -25,6 +25,7 @@
 #include <map>
 #include <mutex>
 #include <set>
+#include <type_traits>
 #include <utility>
 
 #include "fdot_internal.h"
@@ -124,8 +125,33 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const FieldK F, int rep, 
   // ak, ak+1) and 4 pairs of B (row bk + 4q, columns bc, bc+1).
   const uint32_t ar = tid / 8, ak = 2 * (tid % 8);
   const uint32_t bk = tid / 64, bc = 2 * (tid % 64);
+  // VEC: every fetch is one unconditional load of an element pair (rows
+  // start on a pair boundary and K and N are even, so a pair whose first
+  // element is inside the matrix lies inside it; pairs outside are read from
+  // the matrix's first pair), masked and converted when staged: no
+  // branch separates a load from its use, so a K-tile's loads stay in flight
+  // together.  Otherwise element loads under bounds checks.
+  typedef typename std::conditional<sizeof(E) == 8, double, unsigned int>::type S1;
+  typedef S1 S2 __attribute__((ext_vector_type(2)));
+  S2 xa[4], xb[4];
+  uint32_t oka = 0, okb = 0;
   double ra[4][2], rb[4][2];
   auto fetch = [&](uint32_t k0) {
+    if constexpr (VEC) {
+      oka = okb = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t gm = m0 + ar + 32 * q, gk = k0 + ak;
+        const bool a0 = gm < M && gk < K, a1 = a0 && gk + 1 < K;
+        xa[q] = gld((const S2*)(A + (a0 ? (uint64_t)gm * lda + gk : 0)));
+        oka |= ((uint32_t)a0 | (uint32_t)a1 << 1) << (2 * q);
+        const uint32_t gk2 = k0 + bk + 4 * q, gn = n0 + bc;
+        const bool b0 = gk2 < K && gn < N, b1 = b0 && gn + 1 < N;
+        xb[q] = gld((const S2*)(B + (b0 ? (uint64_t)gk2 * ldb + gn : 0)));
+        okb |= ((uint32_t)b0 | (uint32_t)b1 << 1) << (2 * q);
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint32_t gm = m0 + ar + 32 * q, gk = k0 + ak;
@@ -147,6 +173,15 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const FieldK F, int rep, 
   if (K > 0) fetch(0);
   for (uint32_t k0 = 0; k0 < K; k0 += FK) {
     __syncthreads();  // every wave is done reading the previous tile
+    if constexpr (VEC) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ra[q][0] = (oka >> (2 * q)) & 1u ? to_term<E, CENTRE>((E)xa[q].x, F) : 0.0;
+        ra[q][1] = (oka >> (2 * q + 1)) & 1u ? to_term<E, CENTRE>((E)xa[q].y, F) : 0.0;
+        rb[q][0] = (okb >> (2 * q)) & 1u ? to_term<E, CENTRE>((E)xb[q].x, F) : 0.0;
+        rb[q][1] = (okb >> (2 * q + 1)) & 1u ? to_term<E, CENTRE>((E)xb[q].y, F) : 0.0;
+      }
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       As[(ar + 32 * q) * FAP + ak] = ra[q][0];
@@ -324,6 +359,158 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(const FieldK F, uint32_t M
       }
 }
 
+// Large-tile int8 kernel: C tile 256 x 256 per workgroup, each wavefront a
+// 128 x 128 sub-tile as 4 x 4 blocks of 32 x 32 (the accumulators, 256
+// registers per lane, live in the accumulation registers; one wavefront per
+// SIMD).  Per MFMA the wavefront reads half as many LDS bytes as with 2 x 2
+// blocks.  K is staged IK at a time through two LDS buffers: the next
+// K-tile, fetched into registers during the current one's products, is
+// written to the other buffer, so one barrier per K-tile suffices.  FOLDS:
+// the accumulators are folded inside the loop, which keeps them in ordinary
+// registers and spills; the launcher uses this kernel only when K fits one
+// fold block (FOLDS false: accumulators read once, at the end).
+template <int IK, int BJ, bool VEC, bool FOLDS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BJ == 4 ? 1 : 2, BJ == 4 ? 1 : 2)))
+void gemm_i8_big_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, const int8_t* A,
+                        uint64_t lda, const int8_t* Bt, uint64_t ldbt, int8_t* C, uint64_t ldc,
+                        uint32_t fold_steps) {
+  constexpr int TM = 256, TN = 64 * BJ, P = IK;  // rows unpadded, chunks swizzled
+  constexpr int CPR = IK / 16;                    // 16-byte chunks per row
+  constexpr int SW = CPR == 4 ? 2 : 1;            // log2(16 / CPR)
+  constexpr int NV = TM * IK / 16 / 256;   // 16-byte vectors of A per thread
+  constexpr int NVB = TN * IK / 16 / 256;  // and of B
+  extern __shared__ __attribute__((aligned(16))) int8_t s_i8[];
+  int8_t* As = s_i8;                      // [2][TM][P]
+  int8_t* Bs = s_i8 + 2 * TM * P;         // [2][TN][P]
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const uint32_t tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
+  uint32_t tm, tn;
+  tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, &tm, &tn);
+  const uint32_t m0 = tm * TM, n0 = tn * TN;
+  const uint32_t wm = (w >> 1) * 128, wn = (w & 1) * 32 * BJ;
+  // Operand rows are 16-byte aligned and K is a multiple of 16 (the launcher
+  // checks): every fetch is one unconditional 16-byte load from a clamped
+  // address, zeroed when staged if it lies outside the matrix, so no branch
+  // separates a load from its use and the loads of a K-tile stay in flight
+  // together.
+  static_assert(VEC, "the large-tile kernel needs 16-byte rows");
+  struct Regs {
+    v4i a[NV], b[NVB];
+    uint32_t okA, okB;
+  };
+  auto fetch = [&](Regs& R, uint32_t k0) {
+    R.okA = R.okB = 0;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const uint32_t e = tid + 256u * q;
+      const uint32_t r = e / (IK / 16), gk = k0 + (e % (IK / 16)) * 16;
+      const uint32_t kc = gk < K ? gk : K - 16;
+      const uint32_t ra = m0 + r < M ? m0 + r : M - 1;
+      R.a[q] = gld((const v4i*)(A + (uint64_t)ra * lda + kc));
+      R.okA |= (uint32_t)(m0 + r < M && gk < K) << q;
+    }
+#pragma unroll
+    for (int q = 0; q < NVB; ++q) {
+      const uint32_t e = tid + 256u * q;
+      const uint32_t r = e / (IK / 16), gk = k0 + (e % (IK / 16)) * 16;
+      const uint32_t kc = gk < K ? gk : K - 16;
+      const uint32_t rb = n0 + r < N ? n0 + r : N - 1;
+      R.b[q] = gld((const v4i*)(Bt + (uint64_t)rb * ldbt + kc));
+      R.okB |= (uint32_t)(n0 + r < N && gk < K) << q;
+    }
+  };
+  // LDS layout: chunk c of row r is stored at chunk c ^ ((r >> SW) mod CPR)
+  // of that row, so that the 16 lanes of one LDS access (a column of 16
+  // rows when the MFMA operands are read, CPR chunks of 16 / CPR rows when a
+  // K-tile is written) touch 16 distinct 16-byte bank groups.
+  auto swz = [](uint32_t r, uint32_t c) -> uint32_t {
+    return (((c >> 4) ^ (r >> SW)) & (CPR - 1)) << 4;
+  };
+  auto stage = [&](const Regs& R, int buf) {
+    const v4i zero = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const uint32_t e = tid + 256u * q;
+      const uint32_t r = e / (IK / 16), c = (e % (IK / 16)) * 16;
+      *(v4i*)&As[(buf * TM + r) * P + swz(r, c)] = ((R.okA >> q) & 1u) ? R.a[q] : zero;
+    }
+#pragma unroll
+    for (int q = 0; q < NVB; ++q) {
+      const uint32_t e = tid + 256u * q;
+      const uint32_t r = e / (IK / 16), c = (e % (IK / 16)) * 16;
+      *(v4i*)&Bs[(buf * TN + r) * P + swz(r, c)] = ((R.okB >> q) & 1u) ? R.b[q] : zero;
+    }
+  };
+  v16i acc[4][BJ];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < IK / 32; ++s) {
+      const uint32_t kc = 32 * s + 16 * (lane / 32);
+      v4i a[4], b[BJ];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t r = wm + 32 * i + lane % 32;
+        a[i] = *(const v4i*)&As[(buf * TM + r) * P + swz(r, kc)];
+      }
+#pragma unroll
+      for (int j = 0; j < BJ; ++j) {
+        const uint32_t r = wn + 32 * j + lane % 32;
+        b[j] = *(const v4i*)&Bs[(buf * TN + r) * P + swz(r, kc)];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < BJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  };
+  uint32_t steps = 0;
+  auto fold = [&]() {
+    if (FOLDS && ++steps == fold_steps) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < BJ; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[i][j][r] = centred_mod(acc[i][j][r], F);
+      steps = 0;
+    }
+  };
+  // One register set, fetched one K-tile ahead.
+  const uint32_t tiles_k = (K + IK - 1) / IK;
+  Regs R;
+  if (tiles_k > 0) {
+    fetch(R, 0);
+    stage(R, 0);
+    __syncthreads();
+    if (tiles_k > 1) fetch(R, IK);
+  }
+  for (uint32_t t = 0; t < tiles_k; ++t) {
+    const int buf = t & 1;
+    compute(buf);
+    if (t + 1 < tiles_k) stage(R, buf ^ 1);
+    __syncthreads();  // the other buffer is complete; nobody reads this one any more
+    if (t + 2 < tiles_k) fetch(R, (t + 2) * IK);
+    fold();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t gm = m0 + wm + 32 * i + 8 * (r / 4) + 4 * (lane / 32) + r % 4;
+        const uint32_t gn = n0 + wn + 32 * j + lane % 32;
+        if (gm < M && gn < N) C[(uint64_t)gm * ldc + gn] = (int8_t)centred_mod(acc[i][j][r], F);
+      }
+}
+
 // Bt = B^T for int8 matrices, 64 x 64 tiles through LDS.
 __global__ __launch_bounds__(256) void transpose_i8_kernel(const int8_t* B, uint64_t ldb, uint32_t K,
                                                            uint32_t N, int8_t* Bt, uint64_t ldbt) {
@@ -404,12 +591,20 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
                          (int8_t*)bt, (uint64_t)K);
       if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
     }
-    // Workgroup tile: 0 = 256 x 256, 1 = 256 x 128, 2 = 128 x 128; K-tile 64 or 128.
-    const int64_t shape = fd_tune("gemm.i8.tile", 2);
+    // Workgroup tile: 4 = 256 x 128 and 3 = 256 x 256 double-buffered (large
+    // matrices; 4 by default), 0 = 256 x 256,
+    // 1 = 256 x 128, 2 = 128 x 128; K-tile 64 or 128.
+    int64_t shape = fd_tune("gemm.i8.tile", M >= 1024 && N >= 1024 ? 4 : 2);
+    // the large tile keeps its accumulators unfolded (only when K fits one fold
+    // block) and needs 16-byte rows
+    if ((shape == 3 || shape == 4) &&
+        ((uint64_t)K > (lam / 128) * 128 || K % 16 != 0 || lda % 16 != 0 ||
+                       ((uintptr_t)A) % 16 != 0 || M < 256 || N < 256))
+      shape = 2;
     const int64_t kt = fd_tune("gemm.i8.ktile", 128) == 64 ? 64 : 128;
     const uint32_t fold_steps = (uint32_t)(lam / (uint64_t)kt);
     const bool vec = (lda % 16 == 0) && (((uintptr_t)A) % 16 == 0) && (K % 16 == 0);
-    const uint32_t TM = shape == 2 ? 128 : 256, TN = shape == 0 ? 256 : 128;
+    const uint32_t TM = shape == 2 ? 128 : 256, TN = (shape == 0 || shape == 3) ? 256 : 128;
     const uint64_t tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
     if (tiles > 0x7FFFFFFFull) return FDOT_E_INVALID_ARG;
 #define FD_I8_LAUNCH(BI, BJ, KT, V)                                                               \
@@ -421,7 +616,28 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
   if (shape == 2) { if (vec) FD_I8_LAUNCH(2, 2, KT, true); else FD_I8_LAUNCH(2, 2, KT, false); }  \
   else if (shape == 1) { if (vec) FD_I8_LAUNCH(4, 2, KT, true); else FD_I8_LAUNCH(4, 2, KT, false); } \
   else { if (vec) FD_I8_LAUNCH(4, 4, KT, true); else FD_I8_LAUNCH(4, 4, KT, false); }
-    if (kt == 64) { FD_I8_SHAPE(64) } else { FD_I8_SHAPE(128) }
+    if (shape == 3 || shape == 4) {
+      // 3: 256 x 256 tile, one wavefront per SIMD; 4: 256 x 128, two
+      const int64_t bkt = shape == 4 ? 64 : (fd_tune("gemm.i8.big.ktile", 128) == 64 ? 64 : 128);
+      const uint32_t big_fold = (uint32_t)(lam / (uint64_t)bkt);
+#define FD_I8_BIG(KT, BJ)                                                                          \
+  {                                                                                                \
+    const size_t lds = (size_t)2 * (256 + 64 * BJ) * KT;                                           \
+    static bool attr_set = false;                                                                  \
+    if (!attr_set) {                                                                               \
+      (void)hipFuncSetAttribute((const void*)gemm_i8_big_kernel<KT, BJ, true, false>,            \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);             \
+      attr_set = true;                                                                             \
+    }                                                                                              \
+    const uint64_t big_tiles = ((M + 255) / 256) * ((N + 64 * BJ - 1) / (64 * BJ));                \
+    hipLaunchKernelGGL((gemm_i8_big_kernel<KT, BJ, true, false>), dim3((unsigned)big_tiles),       \
+                       dim3(256), lds, s, f->k, (uint32_t)M, (uint32_t)N, (uint32_t)K,             \
+                       (const int8_t*)A, (uint64_t)lda, (const int8_t*)bt, (uint64_t)K,            \
+                       (int8_t*)C, (uint64_t)ldc, big_fold);                                       \
+  }
+      if (shape == 4) FD_I8_BIG(64, 2) else if (bkt == 64) FD_I8_BIG(64, 4) else FD_I8_BIG(128, 4)
+#undef FD_I8_BIG
+    } else if (kt == 64) { FD_I8_SHAPE(64) } else { FD_I8_SHAPE(128) }
 #undef FD_I8_SHAPE
 #undef FD_I8_LAUNCH
     return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
@@ -457,10 +673,11 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
 #define FD_F64_PICK(E, CEN)                                                                        \
   if (vec) { if (subfold) FD_F64_LAUNCH(E, CEN, true, true); else FD_F64_LAUNCH(E, CEN, true, false); } \
   else { if (subfold) FD_F64_LAUNCH(E, CEN, false, true); else FD_F64_LAUNCH(E, CEN, false, false); }
-  // Pair loads need both rows of A and B to start on a pair boundary.
   const size_t esz = I.elem_bytes, pair = 2 * esz;
-  const bool vec = lda % 2 == 0 && ldb % 2 == 0 && ((uintptr_t)A) % pair == 0 &&
-                   ((uintptr_t)B) % pair == 0;
+  // Pair loads need both rows of A and B to start on a pair boundary, and K
+  // and N even so that no pair reaches past the end of a row.
+  const bool vec = lda % 2 == 0 && ldb % 2 == 0 && K % 2 == 0 && N % 2 == 0 &&
+                   ((uintptr_t)A) % pair == 0 && ((uintptr_t)B) % pair == 0;
   if (I.rep == FDOT_REP_FP64) {
     if (centre) { FD_F64_PICK(double, true) } else { FD_F64_PICK(double, false) }
   } else {
