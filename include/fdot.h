@@ -79,8 +79,14 @@ typedef enum {
                                 for MONT_U32 one extra reduction at the end */
   FDOT_ALGO_ZECH_TPLUS1 = 4, /* Sec. 2.4: products by index addition, sums by
                                 Zech addition through the plus-one table */
-  FDOT_ALGO_ZECH_EXP = 5     /* Sec. 2.4 + 3.1: products by index addition,
+  FDOT_ALGO_ZECH_EXP = 5,    /* Sec. 2.4 + 3.1: products by index addition,
                                 then the value table and a delayed integer sum */
+  FDOT_ALGO_HYBRID = 6       /* Sec. 3.4: blocks of lambda products with
+                                lambda p (p-1) < 2^64 (Eq. 2, strict reading)
+                                added without a test, one wrap test and CORR
+                                per block; ZPZ_U32 and MONT_U32 (one extra
+                                reduction at the end); where lambda < 2 the
+                                same as OVERFLOW */
 } fdot_algo_t;
 
 /* Accumulator kinds for the bound calculator. */

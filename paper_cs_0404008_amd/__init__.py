@@ -23,7 +23,8 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 REPS = {"zpz": 0, "mont": 1, "fp64": 2, "zech": 3, "centred": 4}
-ALGOS = {"auto": 0, "delayed": 1, "perterm": 2, "overflow": 3, "zech_tplus1": 4, "zech_exp": 5}
+ALGOS = {"auto": 0, "delayed": 1, "perterm": 2, "overflow": 3, "zech_tplus1": 4, "zech_exp": 5,
+         "hybrid": 6}
 ACCS = {"u64": 0, "u32": 1, "f64": 2, "i32_centred": 3, "f64_centred": 4, "mont_redc": 5,
         "u64_hybrid": 6}
 BOUNDS = {"axpy_signed": 0, "axpy_unsigned": 1, "montgomery": 2, "zech_index": 3}

@@ -209,6 +209,50 @@ struct POverflow {
   }
 };
 
+// Block-overflow (Sec. 3.4): products are added without a test for blocks of
+// at most lambda of them, lambda p (p-1) < 2^64, so a block wraps the sum at
+// most once; the wrap shows as a sum below the block's starting value and is
+// corrected with CORR = 2^64 mod p, which cannot wrap again (the sum after a
+// wrap is below lambda (p-1)^2).  Two accumulators, each taking two products
+// per vector; fold() closes the blocks.  MONT as in POverflow.
+template <bool MONT>
+struct PHybrid {
+  using E = uint32_t;
+  static constexpr int VW = 4;
+  static constexpr int U = FDOT_UNROLL;
+  static constexpr bool kFolds = true;
+  uint64_t s0, s1, b0, b1;
+  uint64_t corr;
+  __device__ void init(const FieldK& F) {
+    s0 = s1 = b0 = b1 = 0;
+    corr = F.corr;
+  }
+  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK&) {
+    s0 += (uint64_t)a.x * b.x;
+    s1 += (uint64_t)a.y * b.y;
+    s0 += (uint64_t)a.z * b.z;
+    s1 += (uint64_t)a.w * b.w;
+  }
+  __device__ void fold(const FieldK&) {
+    s0 += s0 < b0 ? corr : 0;
+    s1 += s1 < b1 ? corr : 0;
+    b0 = s0;
+    b1 = s1;
+  }
+  __device__ void one(E a, E b, const FieldK& F, const Job&) {
+    fold(F);
+    ovf_add(s0, (uint64_t)a * b, corr);
+    b0 = s0;
+  }
+  __device__ uint32_t finish(const FieldK& F) {
+    fold(F);
+    return mod_u64((uint64_t)mod_u64(s0, F) + mod_u64(s1, F), F);
+  }
+  __device__ static void store(void* out, uint64_t k, uint32_t r, const FieldK& F) {
+    ((uint32_t*)out)[k] = MONT ? redc(r, F) : r;
+  }
+};
+
 // Montgomery residues (B = 2^32) with one REDC per block (Sec. 3.2.1): a
 // block sums at most lambda_redc products X*Y, each carrying B^2, and stays
 // below p*B, so REDC returns (block sum)*B^-1 mod p, which is already in
@@ -953,9 +997,17 @@ __global__ __launch_bounds__(256) void gemv_kernel(const FieldK F, const Job J, 
 
 // ---------------------------------------------------------------- launching
 enum class Kind {
-  ZpzDelayed, ZpzPerTerm, ZpzOverflow, MontDelayed, MontPerTerm, MontOverflow,
-  F64, ZechExp, ZechTplus1, Centred
+  ZpzDelayed, ZpzPerTerm, ZpzOverflow, ZpzHybrid, MontDelayed, MontPerTerm, MontOverflow,
+  MontHybrid, F64, ZechExp, ZechTplus1, Centred
 };
+
+// Sec. 3.4, Eq. 2 (strict reading): largest lambda with lambda p (p-1) < 2^64.
+static uint64_t hybrid_lambda(uint64_t p) {
+  const unsigned __int128 pp = (unsigned __int128)p * (p - 1);
+  if (pp == 0) return ~0ull;
+  const unsigned __int128 l = (~(unsigned __int128)0 >> 64) / pp;
+  return l > ~0ull ? ~0ull : (uint64_t)l;
+}
 
 struct Plan {
   Kind kind;
@@ -975,7 +1027,15 @@ static fdot_status_t make_plan(const fdot_field_s* f, fdot_algo_t algo, Plan* pl
   pl->lds = 0;
   switch (I.rep) {
     case FDOT_REP_ZPZ_U32:
-      if (algo == FDOT_ALGO_OVERFLOW) { pl->kind = Kind::ZpzOverflow; return FDOT_OK; }
+      if (algo == FDOT_ALGO_OVERFLOW || (algo == FDOT_ALGO_HYBRID && hybrid_lambda(I.p) < 2)) {
+        pl->kind = Kind::ZpzOverflow;
+        return FDOT_OK;
+      }
+      if (algo == FDOT_ALGO_HYBRID) {
+        pl->kind = Kind::ZpzHybrid;
+        pl->fold_vecs = clamp_vecs(hybrid_lambda(I.p) / 2);  // two products per vector per sum
+        return FDOT_OK;
+      }
       if (algo == FDOT_ALGO_PERTERM || (algo == FDOT_ALGO_DELAYED && I.lambda_u64 < 2)) {
         pl->kind = Kind::ZpzPerTerm;
         return FDOT_OK;
@@ -985,7 +1045,15 @@ static fdot_status_t make_plan(const fdot_field_s* f, fdot_algo_t algo, Plan* pl
       pl->fold_vecs = clamp_vecs(I.lambda_u64 / 2);  // two products per vector per accumulator
       return FDOT_OK;
     case FDOT_REP_MONT_U32:
-      if (algo == FDOT_ALGO_OVERFLOW) { pl->kind = Kind::MontOverflow; return FDOT_OK; }
+      if (algo == FDOT_ALGO_OVERFLOW || (algo == FDOT_ALGO_HYBRID && hybrid_lambda(I.p) < 2)) {
+        pl->kind = Kind::MontOverflow;
+        return FDOT_OK;
+      }
+      if (algo == FDOT_ALGO_HYBRID) {
+        pl->kind = Kind::MontHybrid;
+        pl->fold_vecs = clamp_vecs(hybrid_lambda(I.p) / 2);
+        return FDOT_OK;
+      }
       if (algo == FDOT_ALGO_PERTERM || (algo == FDOT_ALGO_DELAYED && I.lambda_redc < 2)) {
         pl->kind = Kind::MontPerTerm;
         return FDOT_OK;
@@ -1108,6 +1176,8 @@ static fdot_status_t dispatch(const Plan& pl, const Launch& A0) {
     case Kind::ZpzDelayed: return launch_t<PZpzDelayed, 256>(A);
     case Kind::ZpzPerTerm: return launch_t<PZpzPerTerm, 256>(A);
     case Kind::ZpzOverflow: return launch_t<POverflow<false>, 256>(A);
+    case Kind::ZpzHybrid: return launch_t<PHybrid<false>, 256>(A);
+    case Kind::MontHybrid: return launch_t<PHybrid<true>, 256>(A);
     case Kind::MontDelayed: return launch_t<PMontDelayed, 256>(A);
     case Kind::MontPerTerm: return launch_t<PMontPerTerm, 256>(A);
     case Kind::MontOverflow: return launch_t<POverflow<true>, 256>(A);
@@ -1325,6 +1395,8 @@ fdot_status_t fd_launch_gemv(const fdot_field_s* f, size_t m, size_t n, const vo
     case Kind::ZpzDelayed: return launch_gemv_t<PZpzDelayed>(f, J, m, n, A, lda, x, y, 0, s);
     case Kind::ZpzPerTerm: return launch_gemv_t<PZpzPerTerm>(f, J, m, n, A, lda, x, y, 0, s);
     case Kind::ZpzOverflow: return launch_gemv_t<POverflow<false>>(f, J, m, n, A, lda, x, y, 0, s);
+    case Kind::ZpzHybrid: return launch_gemv_t<PHybrid<false>>(f, J, m, n, A, lda, x, y, 0, s);
+    case Kind::MontHybrid: return launch_gemv_t<PHybrid<true>>(f, J, m, n, A, lda, x, y, 0, s);
     case Kind::MontDelayed: return launch_gemv_t<PMontDelayed>(f, J, m, n, A, lda, x, y, 0, s);
     case Kind::MontPerTerm: return launch_gemv_t<PMontPerTerm>(f, J, m, n, A, lda, x, y, 0, s);
     case Kind::MontOverflow: return launch_gemv_t<POverflow<true>>(f, J, m, n, A, lda, x, y, 0, s);

@@ -101,20 +101,22 @@ __device__ __forceinline__ void load_pair(const E* base, uint64_t off, bool in0,
 }
 
 // C tile 128 x 128 per workgroup; wavefront w owns rows 64*(w/2).., columns
-// 64*(w%2).. as 4 x 4 blocks of 16 x 16.  K is staged through LDS 16 at a
-// time (A row-major with a padded pitch, B as stored), consumed in 4 steps of
-// one MFMA K (4); the next K-tile is fetched into registers while the current
-// one is multiplied.  The accumulators are folded after every fold_sub MFMA
+// 64*(w%2).. as 4 x 4 blocks of 16 x 16.  K is staged through two LDS
+// buffers 16 at a time (A row-major with a padded pitch, B as stored),
+// consumed in 4 steps of one MFMA K (4); the next K-tile is fetched into
+// registers while the current one is multiplied.  The accumulators are folded after every fold_sub MFMA
 // steps (SUBFOLD, for block lengths below one K-tile) or K-tiles.
 constexpr int FAP = FK + 1;    // A pitch in LDS (doubles): conflict-free column reads
 constexpr int FBP = FN + 2;    // B pitch in LDS (doubles): keeps 16-byte alignment
+constexpr size_t kF64Lds = (size_t)2 * (FM * FAP + FK * FBP) * sizeof(double);  // two buffers
 template <typename E, bool CENTRE, bool VEC, bool SUBFOLD>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const FieldK F, int rep, uint32_t M,
                                                        uint32_t N, uint32_t K, const E* A,
                                                        uint64_t lda, const E* B, uint64_t ldb,
                                                        void* C, uint64_t ldc, uint32_t fold_sub) {
-  __shared__ double As[FM * FAP];
-  __shared__ double Bs[FK * FBP];
+  extern __shared__ __attribute__((aligned(16))) double s_f64[];
+  double* const As0 = s_f64;                   // [2][FM * FAP]
+  double* const Bs0 = s_f64 + 2 * FM * FAP;    // [2][FK * FBP]
   const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
   const uint32_t tiles_m = (M + FM - 1) / FM, tiles_n = (N + FN - 1) / FN;
   uint32_t tm, tn;
@@ -169,10 +171,9 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const FieldK F, int rep, 
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
-  uint32_t sub = 0;
-  if (K > 0) fetch(0);
-  for (uint32_t k0 = 0; k0 < K; k0 += FK) {
-    __syncthreads();  // every wave is done reading the previous tile
+  auto stage = [&](int buf) {
+    double* As = As0 + buf * FM * FAP;
+    double* Bs = Bs0 + buf * FK * FBP;
     if constexpr (VEC) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -189,8 +190,30 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const FieldK F, int rep, 
       Bs[(bk + 4 * q) * FBP + bc] = rb[q][0];
       Bs[(bk + 4 * q) * FBP + bc + 1] = rb[q][1];
     }
+  };
+  auto fold_all = [&]() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] = fold_keep(acc[i][j][r], F, CENTRE);
+  };
+  // Two LDS buffers: the next K-tile, fetched into registers during the
+  // current one's products, is staged into the other buffer, so one barrier
+  // per K-tile suffices.
+  uint32_t sub = 0;
+  if (K > 0) {
+    fetch(0);
+    stage(0);
     __syncthreads();
-    if (k0 + FK < K) fetch(k0 + FK);
+    if (FK < K) fetch(FK);
+  }
+  uint32_t t = 0;
+  for (uint32_t k0 = 0; k0 < K; k0 += FK, ++t) {
+    const int buf = t & 1;
+    const double* As = As0 + buf * FM * FAP;
+    const double* Bs = Bs0 + buf * FK * FBP;
 #pragma unroll
     for (int s = 0; s < FK / 4; ++s) {
       const uint32_t kr = 4 * s + lane / 16;
@@ -205,23 +228,16 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const FieldK F, int rep, 
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
       if (SUBFOLD && ++sub == fold_sub) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[i][j][r] = fold_keep(acc[i][j][r], F, CENTRE);
+        fold_all();
         sub = 0;
       }
     }
+    if (k0 + FK < K) stage(buf ^ 1);
+    __syncthreads();  // the other buffer is complete; nobody reads this one any more
+    if (k0 + 2 * FK < K) fetch(k0 + 2 * FK);
     // Without SUBFOLD, fold_sub counts whole K-tiles.
     if (!SUBFOLD && ++sub == fold_sub) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc[i][j][r] = fold_keep(acc[i][j][r], F, CENTRE);
+      fold_all();
       sub = 0;
     }
   }
@@ -667,9 +683,17 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
   const uint32_t fold_sub = (uint32_t)(subfold ? lam / 4 : lam / FK);
   const dim3 grid((unsigned)tiles), block(256);
 #define FD_F64_LAUNCH(E, CEN, V, SF)                                                              \
-  hipLaunchKernelGGL((gemm_f64_kernel<E, CEN, V, SF>), grid, block, 0, s, f->k, I.rep,            \
-                     (uint32_t)M, (uint32_t)N, (uint32_t)K, (const E*)A, (uint64_t)lda,           \
-                     (const E*)B, (uint64_t)ldb, C, (uint64_t)ldc, fold_sub)
+  do {                                                                                             \
+    static bool attr_set = false;                                                                  \
+    if (!attr_set) {                                                                               \
+      (void)hipFuncSetAttribute((const void*)gemm_f64_kernel<E, CEN, V, SF>,                     \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kF64Lds);         \
+      attr_set = true;                                                                             \
+    }                                                                                              \
+    hipLaunchKernelGGL((gemm_f64_kernel<E, CEN, V, SF>), grid, block, kF64Lds, s, f->k, I.rep,     \
+                       (uint32_t)M, (uint32_t)N, (uint32_t)K, (const E*)A, (uint64_t)lda,         \
+                       (const E*)B, (uint64_t)ldb, C, (uint64_t)ldc, fold_sub);                    \
+  } while (0)
 #define FD_F64_PICK(E, CEN)                                                                        \
   if (vec) { if (subfold) FD_F64_LAUNCH(E, CEN, true, true); else FD_F64_LAUNCH(E, CEN, true, false); } \
   else { if (subfold) FD_F64_LAUNCH(E, CEN, false, true); else FD_F64_LAUNCH(E, CEN, false, false); }

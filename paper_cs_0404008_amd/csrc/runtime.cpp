@@ -184,7 +184,7 @@ fdot_status_t fdot_modp_algo(fdot_field_t f, fdot_algo_t algo, const void* x, co
                              size_t n, void* result, void* stream) {
   if (!f || !result) return FDOT_E_INVALID_ARG;
   if (f->host_only) return FDOT_E_UNSUPPORTED;
-  if ((int)algo < FDOT_ALGO_AUTO || (int)algo > FDOT_ALGO_ZECH_EXP) return FDOT_E_INVALID_ARG;
+  if ((int)algo < FDOT_ALGO_AUTO || (int)algo > FDOT_ALGO_HYBRID) return FDOT_E_INVALID_ARG;
   const size_t es = f->info.elem_bytes;
   if (!aligned_to(result, es)) return FDOT_E_INVALID_ARG;
   if (n && (!x || !y || !aligned_to(x, es) || !aligned_to(y, es))) return FDOT_E_INVALID_ARG;
@@ -203,7 +203,7 @@ fdot_status_t fdot_modp_many_algo(fdot_field_t f, fdot_algo_t algo, size_t count
                                   const fdot_desc_t* desc, void* results, void* stream) {
   if (!f) return FDOT_E_INVALID_ARG;
   if (f->host_only) return FDOT_E_UNSUPPORTED;
-  if ((int)algo < FDOT_ALGO_AUTO || (int)algo > FDOT_ALGO_ZECH_EXP) return FDOT_E_INVALID_ARG;
+  if ((int)algo < FDOT_ALGO_AUTO || (int)algo > FDOT_ALGO_HYBRID) return FDOT_E_INVALID_ARG;
   if (count == 0) return FDOT_OK;
   if (!desc || !results || !aligned_to(desc, 8) || !aligned_to(results, f->info.elem_bytes))
     return FDOT_E_INVALID_ARG;

@@ -23,9 +23,9 @@ P_FP_MAX = 94906249       # largest prime with lambda_f64 >= 1
 
 CASES = (
     [(p, "zpz", a) for p in (251, 32749, 65521, P_LAMBDA100, 2147483647, 4294967291)
-     for a in ("auto", "delayed", "perterm", "overflow")]
+     for a in ("auto", "delayed", "perterm", "overflow", "hybrid")]
     + [(p, "mont", a) for p in (3, 32749, 65521, 2147483647, 2654435761, 4294967291)
-       for a in ("auto", "delayed", "perterm", "overflow")]
+       for a in ("auto", "delayed", "perterm", "overflow", "hybrid")]
     + [(p, "fp64", a) for p in (251, 1048573, 67108859, P_FP_LAMBDA3, P_FP_MAX)
        for a in ("auto", "delayed", "perterm")]
     + [(p, "zech", a) for p in (3, 251, 32749, 65521) for a in ("auto", "zech_exp", "zech_tplus1")]
@@ -89,6 +89,7 @@ def test_misaligned_and_aliased(p, rep):
 @pytest.mark.parametrize("p,rep,algo", [(65521, "zpz", "auto"), (2147483647, "mont", "delayed"),
                                         (4294967291, "zpz", "perterm"),
                                         (4294967291, "zpz", "overflow"),
+                                        (2897, "zpz", "hybrid"), (2147483647, "mont", "hybrid"),
                                         (67108859, "fp64", "auto"), (32749, "zech", "zech_exp"),
                                         (32749, "zech", "zech_tplus1"), (251, "centred", "auto")])
 def test_batched_matches_oracle_and_single(p, rep, algo):
