@@ -413,7 +413,8 @@ def main():
         "gelem_per_s": round(total_terms / step_gpu / 1e9, 3),
         "per_batch_ms": {BATCHES[i][3]: round(per_batch[i] / args.steps * 1e3, 4)
                          for i in range(len(batches))},
-        "roofline": {"bound": "hbm", "kernel": f"dot_kernel batched, {BATCHES[dom][3]}",
+        "roofline": {"bound": "hbm",
+                     "kernel": f"one batched call (plan_kernel + many_kernel), {BATCHES[dom][3]}",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(BATCHES[dom][:3]),
