@@ -109,8 +109,8 @@ __device__ __forceinline__ void load_pair(const E* base, uint64_t off, bool in0,
 constexpr int FAP = FK + 1;    // A pitch in LDS (doubles): conflict-free column reads
 constexpr int FBP = FN + 2;    // B pitch in LDS (doubles): keeps 16-byte alignment
 constexpr size_t kF64Lds = (size_t)2 * (FM * FAP + FK * FBP) * sizeof(double);  // two buffers
-template <typename E, bool CENTRE, bool VEC, bool SUBFOLD>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(const FieldK F, int rep, uint32_t M,
+template <typename E, bool CENTRE, bool VEC, bool SUBFOLD, int NW>
+__global__ __launch_bounds__(64 * NW) void gemm_f64_kernel(const FieldK F, int rep, uint32_t M,
                                                        uint32_t N, uint32_t K, const E* A,
                                                        uint64_t lda, const E* B, uint64_t ldb,
                                                        void* C, uint64_t ldc, uint32_t fold_sub) {
@@ -122,9 +122,13 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const FieldK F, int rep, 
   uint32_t tm, tn;
   tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, &tm, &tn);
   const uint32_t m0 = tm * FM, n0 = tn * FN;
-  const uint32_t wm = (w >> 1) * 64, wn = (w & 1) * 64;
-  // This thread's share of a K-tile: 4 pairs of A (row ar + 32q, columns
-  // ak, ak+1) and 4 pairs of B (row bk + 4q, columns bc, bc+1).
+  // NW = 4: wavefront w owns a 64 x 64 sub-tile (4 x 4 blocks of 16 x 16);
+  // NW = 8: a 32 x 64 sub-tile (2 x 4 blocks), two wavefronts per SIMD;
+  // NW = 16: a 16 x 64 sub-tile, four per SIMD.
+  constexpr int NT = 64 * NW, BI = 16 / NW, QN = 1024 / NT;
+  const uint32_t wm = (w >> 1) * (16 * BI), wn = (w & 1) * 64;
+  // This thread's share of a K-tile: QN pairs of A (row ar + (NT/8) q,
+  // columns ak, ak+1) and QN pairs of B (row bk + NW q, columns bc, bc+1).
   const uint32_t ar = tid / 8, ak = 2 * (tid % 8);
   const uint32_t bk = tid / 64, bc = 2 * (tid % 64);
   // VEC: every fetch is one unconditional load of an element pair (rows
@@ -135,19 +139,19 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const FieldK F, int rep, 
   // together.  Otherwise element loads under bounds checks.
   typedef typename std::conditional<sizeof(E) == 8, double, unsigned int>::type S1;
   typedef S1 S2 __attribute__((ext_vector_type(2)));
-  S2 xa[4], xb[4];
+  S2 xa[QN], xb[QN];
   uint32_t oka = 0, okb = 0;
-  double ra[4][2], rb[4][2];
+  double ra[QN][2], rb[QN][2];
   auto fetch = [&](uint32_t k0) {
     if constexpr (VEC) {
       oka = okb = 0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t gm = m0 + ar + 32 * q, gk = k0 + ak;
+      for (int q = 0; q < QN; ++q) {
+        const uint32_t gm = m0 + ar + (NT / 8) * q, gk = k0 + ak;
         const bool a0 = gm < M && gk < K, a1 = a0 && gk + 1 < K;
         xa[q] = gld((const S2*)(A + (a0 ? (uint64_t)gm * lda + gk : 0)));
         oka |= ((uint32_t)a0 | (uint32_t)a1 << 1) << (2 * q);
-        const uint32_t gk2 = k0 + bk + 4 * q, gn = n0 + bc;
+        const uint32_t gk2 = k0 + bk + NW * q, gn = n0 + bc;
         const bool b0 = gk2 < K && gn < N, b1 = b0 && gn + 1 < N;
         xb[q] = gld((const S2*)(B + (b0 ? (uint64_t)gk2 * ldb + gn : 0)));
         okb |= ((uint32_t)b0 | (uint32_t)b1 << 1) << (2 * q);
@@ -155,20 +159,20 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const FieldK F, int rep, 
       return;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t gm = m0 + ar + 32 * q, gk = k0 + ak;
+    for (int q = 0; q < QN; ++q) {
+      const uint32_t gm = m0 + ar + (NT / 8) * q, gk = k0 + ak;
       const bool rin = gm < M;
       load_pair<E, CENTRE, VEC>(A, (uint64_t)gm * lda + gk, rin && gk < K, rin && gk + 1 < K, F,
                                 ra[q][0], ra[q][1]);
-      const uint32_t gk2 = k0 + bk + 4 * q, gn = n0 + bc;
+      const uint32_t gk2 = k0 + bk + NW * q, gn = n0 + bc;
       const bool kin = gk2 < K;
       load_pair<E, CENTRE, VEC>(B, (uint64_t)gk2 * ldb + gn, kin && gn < N, kin && gn + 1 < N, F,
                                 rb[q][0], rb[q][1]);
     }
   };
-  v4d acc[4][4];
+  v4d acc[BI][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < BI; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
   auto stage = [&](int buf) {
@@ -176,7 +180,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const FieldK F, int rep, 
     double* Bs = Bs0 + buf * FK * FBP;
     if constexpr (VEC) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < QN; ++q) {
         ra[q][0] = (oka >> (2 * q)) & 1u ? to_term<E, CENTRE>((E)xa[q].x, F) : 0.0;
         ra[q][1] = (oka >> (2 * q + 1)) & 1u ? to_term<E, CENTRE>((E)xa[q].y, F) : 0.0;
         rb[q][0] = (okb >> (2 * q)) & 1u ? to_term<E, CENTRE>((E)xb[q].x, F) : 0.0;
@@ -184,16 +188,16 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const FieldK F, int rep, 
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      As[(ar + 32 * q) * FAP + ak] = ra[q][0];
-      As[(ar + 32 * q) * FAP + ak + 1] = ra[q][1];
-      Bs[(bk + 4 * q) * FBP + bc] = rb[q][0];
-      Bs[(bk + 4 * q) * FBP + bc + 1] = rb[q][1];
+    for (int q = 0; q < QN; ++q) {
+      As[(ar + (NT / 8) * q) * FAP + ak] = ra[q][0];
+      As[(ar + (NT / 8) * q) * FAP + ak + 1] = ra[q][1];
+      Bs[(bk + NW * q) * FBP + bc] = rb[q][0];
+      Bs[(bk + NW * q) * FBP + bc + 1] = rb[q][1];
     }
   };
   auto fold_all = [&]() {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < BI; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -217,13 +221,13 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const FieldK F, int rep, 
 #pragma unroll
     for (int s = 0; s < FK / 4; ++s) {
       const uint32_t kr = 4 * s + lane / 16;
-      double a[4], b[4];
+      double a[BI], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[(wm + 16 * i + lane % 16) * FAP + kr];
+      for (int i = 0; i < BI; ++i) a[i] = As[(wm + 16 * i + lane % 16) * FAP + kr];
 #pragma unroll
       for (int j = 0; j < 4; ++j) b[j] = Bs[kr * FBP + wn + 16 * j + lane % 16];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < BI; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
@@ -242,7 +246,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const FieldK F, int rep, 
     }
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < BI; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -527,6 +531,136 @@ void gemm_i8_big_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, cons
       }
 }
 
+// s_waitcnt for "at most N vector-memory operations outstanding", leaving the
+// other counters alone (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt
+// 6:4, lgkmcnt 11:8).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Workgroup barrier without a memory fence: a fence would wait for every
+// outstanding load, including the K-tiles still being prefetched.  Callers
+// wait for the loads they need themselves; the empty asm statements keep the
+// compiler from moving LDS accesses across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// int8 kernel fed by direct global-to-LDS loads (global_load_lds_dwordx4:
+// each lane's 16 bytes land at LDS base + 16 x lane, no registers involved),
+// so K-tiles can be prefetched NS-1 tiles ahead through NS LDS stages.  C
+// tile 256 x (64 BJ); each wavefront a 128 x (32 BJ) sub-tile as 4 x BJ
+// blocks of 32 x 32; K-tiles of 64.  Rows of a stage are 64 bytes, chunk c
+// of row r stored at chunk c ^ ((r >> 2) mod 4) (the lane that fills a
+// chunk position fetches the chunk that belongs there), so LDS reads and
+// writes touch 16 distinct 16-byte bank groups.  Needs K a multiple of 64
+// (no zero fill is possible on this path) and 16-byte rows; rows of A and
+// B^T past M and N are read from the last row and only reach outputs that
+// are not stored.
+template <int BJ, int NS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BJ == 4 ? 1 : 2, BJ == 4 ? 1 : 2)))
+void gemm_i8_dma_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, const int8_t* A,
+                        uint64_t lda, const int8_t* Bt, uint64_t ldbt, int8_t* C, uint64_t ldc) {
+  constexpr int IK = 64, TM = 256, TN = 64 * BJ;
+  constexpr int SA = TM * IK, SB = TN * IK, SS = SA + SB;  // bytes per stage
+  constexpr int NIA = SA / 1024 / 4, NIB = SB / 1024 / 4;  // DMA instructions per wave
+  constexpr int PER = NIA + NIB;
+  extern __shared__ __attribute__((aligned(16))) int8_t s_dma[];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
+  const uint32_t w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
+  uint32_t tm, tn;
+  tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, &tm, &tn);
+  const uint32_t m0 = tm * TM, n0 = tn * TN;
+  const uint32_t wm = (w >> 1) * 128, wn = (w & 1) * 32 * BJ;
+  // this lane's part of every DMA instruction: row lane/4 of a 16-row band,
+  // chunk position lane%4
+  const uint32_t lr = lane >> 2, lp = lane & 3u;
+  const uint8_t* gA[NIA];
+  const uint8_t* gB[NIB];
+#pragma unroll
+  for (int j = 0; j < NIA; ++j) {
+    const uint32_t r = 16 * (NIA * w + j) + lr;
+    const uint32_t row = m0 + r < M ? m0 + r : M - 1;
+    gA[j] = (const uint8_t*)A + (uint64_t)row * lda + 16 * (lp ^ ((r >> 2) & 3u));
+  }
+#pragma unroll
+  for (int j = 0; j < NIB; ++j) {
+    const uint32_t r = 16 * (NIB * w + j) + lr;
+    const uint32_t row = n0 + r < N ? n0 + r : N - 1;
+    gB[j] = (const uint8_t*)Bt + (uint64_t)row * ldbt + 16 * (lp ^ ((r >> 2) & 3u));
+  }
+  auto issue = [&](uint32_t t, uint32_t stage) {
+    int8_t* base = s_dma + stage * SS;
+    const uint64_t k0 = (uint64_t)t * IK;
+#pragma unroll
+    for (int j = 0; j < NIA; ++j)
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void*)(gA[j] + k0),
+          (__attribute__((address_space(3))) void*)(base + 1024 * (NIA * w + j)), 16, 0, 0);
+#pragma unroll
+    for (int j = 0; j < NIB; ++j)
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void*)(gB[j] + k0),
+          (__attribute__((address_space(3))) void*)(base + SA + 1024 * (NIB * w + j)), 16, 0, 0);
+  };
+  auto swz = [](uint32_t r, uint32_t c) -> uint32_t { return (((c >> 4) ^ (r >> 2)) & 3u) << 4; };
+  v16i acc[4][BJ];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
+  const uint32_t tiles_k = K / IK;
+#pragma unroll
+  for (int st = 0; st < NS - 1; ++st)
+    if ((uint32_t)st < tiles_k) issue(st, st);
+  for (uint32_t t = 0; t < tiles_k; ++t) {
+    // this wave's loads of tile t are done (later tiles may still be in
+    // flight), then everybody's are, and everybody has finished tile t-1
+    if (t + NS - 2 < tiles_k) wait_vmcnt<(NS - 2) * PER>(); else wait_vmcnt<0>();
+    lds_barrier();
+    if (t + NS - 1 < tiles_k) issue(t + NS - 1, (t + NS - 1) % NS);
+    const int8_t* As = s_dma + (t % NS) * SS;
+    const int8_t* Bs = As + SA;
+#pragma unroll
+    for (int s = 0; s < IK / 32; ++s) {
+      const uint32_t kc = 32 * s + 16 * (lane / 32);
+      v4i a[4], b[BJ];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t r = wm + 32 * i + lane % 32;
+        a[i] = *(const v4i*)&As[r * IK + swz(r, kc)];
+      }
+#pragma unroll
+      for (int j = 0; j < BJ; ++j) {
+        const uint32_t r = wn + 32 * j + lane % 32;
+        b[j] = *(const v4i*)&Bs[r * IK + swz(r, kc)];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < BJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t gm = m0 + wm + 32 * i + 8 * (r / 4) + 4 * (lane / 32) + r % 4;
+        const uint32_t gn = n0 + wn + 32 * j + lane % 32;
+        if (gm < M && gn < N) C[(uint64_t)gm * ldc + gn] = (int8_t)centred_mod(acc[i][j][r], F);
+      }
+}
+
 // Bt = B^T for int8 matrices, 64 x 64 tiles through LDS.
 __global__ __launch_bounds__(256) void transpose_i8_kernel(const int8_t* B, uint64_t ldb, uint32_t K,
                                                            uint32_t N, int8_t* Bt, uint64_t ldbt) {
@@ -613,7 +747,7 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
     int64_t shape = fd_tune("gemm.i8.tile", M >= 1024 && N >= 1024 ? 4 : 2);
     // the large tile keeps its accumulators unfolded (only when K fits one fold
     // block) and needs 16-byte rows
-    if ((shape == 3 || shape == 4) &&
+    if ((shape >= 3 && shape <= 6) &&
         ((uint64_t)K > (lam / 128) * 128 || K % 16 != 0 || lda % 16 != 0 ||
                        ((uintptr_t)A) % 16 != 0 || M < 256 || N < 256))
       shape = 2;
@@ -632,9 +766,26 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
   if (shape == 2) { if (vec) FD_I8_LAUNCH(2, 2, KT, true); else FD_I8_LAUNCH(2, 2, KT, false); }  \
   else if (shape == 1) { if (vec) FD_I8_LAUNCH(4, 2, KT, true); else FD_I8_LAUNCH(4, 2, KT, false); } \
   else { if (vec) FD_I8_LAUNCH(4, 4, KT, true); else FD_I8_LAUNCH(4, 4, KT, false); }
-    if (shape == 3 || shape == 4) {
+    if ((shape == 5 || shape == 6) && K % 64 == 0) {
+#define FD_I8_DMA(BJ, NS)                                                                          \
+  {                                                                                                \
+    const size_t lds = (size_t)NS * (256 + 64 * BJ) * 64;                                          \
+    static bool attr_set = false;                                                                  \
+    if (!attr_set) {                                                                               \
+      (void)hipFuncSetAttribute((const void*)gemm_i8_dma_kernel<BJ, NS>,                          \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);             \
+      attr_set = true;                                                                             \
+    }                                                                                              \
+    const uint64_t dma_tiles = ((M + 255) / 256) * ((N + 64 * BJ - 1) / (64 * BJ));                \
+    hipLaunchKernelGGL((gemm_i8_dma_kernel<BJ, NS>), dim3((unsigned)dma_tiles), dim3(256), lds, s, \
+                       f->k, (uint32_t)M, (uint32_t)N, (uint32_t)K, (const int8_t*)A,              \
+                       (uint64_t)lda, (const int8_t*)bt, (uint64_t)K, (int8_t*)C, (uint64_t)ldc); \
+  }
+      if (shape == 5) FD_I8_DMA(2, 3) else FD_I8_DMA(4, 4)
+#undef FD_I8_DMA
+    } else if (shape == 3 || shape == 4 || shape == 5 || shape == 6) {
       // 3: 256 x 256 tile, one wavefront per SIMD; 4: 256 x 128, two
-      const int64_t bkt = shape == 4 ? 64 : (fd_tune("gemm.i8.big.ktile", 128) == 64 ? 64 : 128);
+      const int64_t bkt = (shape == 4 || shape == 5) ? 64 : (fd_tune("gemm.i8.big.ktile", 128) == 64 ? 64 : 128);
       const uint32_t big_fold = (uint32_t)(lam / (uint64_t)bkt);
 #define FD_I8_BIG(KT, BJ)                                                                          \
   {                                                                                                \
@@ -651,7 +802,7 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
                        (const int8_t*)A, (uint64_t)lda, (const int8_t*)bt, (uint64_t)K,            \
                        (int8_t*)C, (uint64_t)ldc, big_fold);                                       \
   }
-      if (shape == 4) FD_I8_BIG(64, 2) else if (bkt == 64) FD_I8_BIG(64, 4) else FD_I8_BIG(128, 4)
+      if (shape == 4 || shape == 5) FD_I8_BIG(64, 2) else if (bkt == 64) FD_I8_BIG(64, 4) else FD_I8_BIG(128, 4)
 #undef FD_I8_BIG
     } else if (kt == 64) { FD_I8_SHAPE(64) } else { FD_I8_SHAPE(128) }
 #undef FD_I8_SHAPE
@@ -681,18 +832,27 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
   if (tiles > 0x7FFFFFFFull) return FDOT_E_INVALID_ARG;
   const bool subfold = lam < FK;
   const uint32_t fold_sub = (uint32_t)(subfold ? lam / 4 : lam / FK);
-  const dim3 grid((unsigned)tiles), block(256);
-#define FD_F64_LAUNCH(E, CEN, V, SF)                                                              \
+  const dim3 grid((unsigned)tiles);
+  // wavefronts per workgroup: 8 of 32 x 64 (two per SIMD, default), 16 of
+  // 16 x 64 or 4 of 64 x 64
+  const int64_t nw = fd_tune("gemm.f64.waves", 8);
+#define FD_F64_LAUNCH_NW(E, CEN, V, SF, NW)                                                       \
   do {                                                                                             \
     static bool attr_set = false;                                                                  \
     if (!attr_set) {                                                                               \
-      (void)hipFuncSetAttribute((const void*)gemm_f64_kernel<E, CEN, V, SF>,                     \
+      (void)hipFuncSetAttribute((const void*)gemm_f64_kernel<E, CEN, V, SF, NW>,                 \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kF64Lds);         \
       attr_set = true;                                                                             \
     }                                                                                              \
-    hipLaunchKernelGGL((gemm_f64_kernel<E, CEN, V, SF>), grid, block, kF64Lds, s, f->k, I.rep,     \
-                       (uint32_t)M, (uint32_t)N, (uint32_t)K, (const E*)A, (uint64_t)lda,         \
+    hipLaunchKernelGGL((gemm_f64_kernel<E, CEN, V, SF, NW>), grid, dim3(64 * NW), kF64Lds, s, f->k,\
+                       I.rep, (uint32_t)M, (uint32_t)N, (uint32_t)K, (const E*)A, (uint64_t)lda,  \
                        (const E*)B, (uint64_t)ldb, C, (uint64_t)ldc, fold_sub);                    \
+  } while (0)
+#define FD_F64_LAUNCH(E, CEN, V, SF)                                                              \
+  do {                                                                                             \
+    if (nw == 8) FD_F64_LAUNCH_NW(E, CEN, V, SF, 8);                                              \
+    else if (nw == 16) FD_F64_LAUNCH_NW(E, CEN, V, SF, 16);                                        \
+    else FD_F64_LAUNCH_NW(E, CEN, V, SF, 4);                                                       \
   } while (0)
 #define FD_F64_PICK(E, CEN)                                                                        \
   if (vec) { if (subfold) FD_F64_LAUNCH(E, CEN, true, true); else FD_F64_LAUNCH(E, CEN, true, false); } \
@@ -709,5 +869,6 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
   }
 #undef FD_F64_PICK
 #undef FD_F64_LAUNCH
+#undef FD_F64_LAUNCH_NW
   return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
 }

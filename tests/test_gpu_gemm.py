@@ -137,3 +137,43 @@ def test_gemm_full_size_sampled(p, rep, dtype):
         lhs = (Ai @ ((Bi @ r) % p)) % p
         rhs = (Ci @ r) % p
         assert np.array_equal(lhs, rhs), t
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4, 5, 6])
+def test_gemm_int8_tile_variants(shape):
+    """Every int8 matrix-core tiling (register-staged, double-buffered and
+    direct-to-LDS), on ragged M and N and a K that some of them take in one
+    fold block, against the oracle."""
+    p, rep = 251, "centred"
+    F = field(p, rep)
+    fd.tune_set("gemm.i8.tile", shape)
+    try:
+        for (M, N, K) in [(1100, 1030, 1024), (1024, 1280, 2048 + 64), (1100, 1030, 1000)]:
+            A = mat(p, rep, M, K, 70, 0, "random")
+            B = mat(p, rep, K, N, 70, 1, "random")
+            got = to_host(F.gemm(to_dev(A), to_dev(B)))
+            rows = synth.uniform_int(71, 0, 512, M)
+            cols = synth.uniform_int(71, 1, 512, N)
+            rows[:2] = [0, M - 1]
+            cols[:2] = [0, N - 1]
+            want = oracle.gemm_entries(p, rep, A, B, rows, cols)
+            assert same(got[rows, cols], want), (shape, M, N, K)
+    finally:
+        fd.tune_set("gemm.i8.tile", None)
+
+
+@pytest.mark.parametrize("waves", [4, 8, 16])
+def test_gemm_fp64_wave_layouts(waves):
+    """The FP64 matrix-core kernel with 4, 8 and 16 wavefronts per workgroup,
+    plain and centred residues, ragged shapes, against the oracle."""
+    fd.tune_set("gemm.f64.waves", waves)
+    try:
+        for p, K in [(1048573, 300), (67108859, 130), (1048573, 3 * 8192 + 6)]:
+            F = field(p, "fp64")
+            M, N = 150, 142
+            A = mat(p, "fp64", M, K, 72, 0, "random")
+            B = mat(p, "fp64", K, N, 72, 1, "random")
+            got = to_host(F.gemm(to_dev(A), to_dev(B)))
+            assert same(got, oracle.gemm(p, "fp64", A, B)), (waves, p, K)
+    finally:
+        fd.tune_set("gemm.f64.waves", None)
