@@ -561,13 +561,15 @@ __device__ __forceinline__ void lds_barrier() {
 // (no zero fill is possible on this path) and 16-byte rows; rows of A and
 // B^T past M and N are read from the last row and only reach outputs that
 // are not stored.
-template <int BJ, int NS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BJ == 4 ? 1 : 2, BJ == 4 ? 1 : 2)))
+template <int BJ, int NS, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(BJ == 4 ? 1 : 2, BJ == 4 ? 1 : 2)))
 void gemm_i8_dma_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, const int8_t* A,
                         uint64_t lda, const int8_t* Bt, uint64_t ldbt, int8_t* C, uint64_t ldc) {
-  constexpr int IK = 64, TM = 256, TN = 64 * BJ;
-  constexpr int SA = TM * IK, SB = TN * IK, SS = SA + SB;  // bytes per stage
-  constexpr int NIA = SA / 1024 / 4, NIB = SB / 1024 / 4;  // DMA instructions per wave
+  // NW = 4 wavefronts as 2 x 2, or 8 as 2 x 4 (the workgroup tile twice as
+  // wide); each wavefront a 128 x (32 BJ) sub-tile.
+  constexpr int IK = 64, TM = 256, TN = 64 * BJ * (NW / 4), WC = NW / 2;
+  constexpr int SA = TM * IK, SB = TN * IK, SS = SA + SB;    // bytes per stage
+  constexpr int NIA = SA / 1024 / NW, NIB = SB / 1024 / NW;  // DMA instructions per wave
   constexpr int PER = NIA + NIB;
   extern __shared__ __attribute__((aligned(16))) int8_t s_dma[];
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
@@ -576,7 +578,7 @@ void gemm_i8_dma_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, cons
   uint32_t tm, tn;
   tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, &tm, &tn);
   const uint32_t m0 = tm * TM, n0 = tn * TN;
-  const uint32_t wm = (w >> 1) * 128, wn = (w & 1) * 32 * BJ;
+  const uint32_t wm = (w / WC) * 128, wn = (w % WC) * 32 * BJ;
   // this lane's part of every DMA instruction: row lane/4 of a 16-row band,
   // chunk position lane%4
   const uint32_t lr = lane >> 2, lp = lane & 3u;
@@ -661,19 +663,41 @@ void gemm_i8_dma_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, cons
       }
 }
 
-// Bt = B^T for int8 matrices, 64 x 64 tiles through LDS.
+// Bt = B^T for int8 matrices, 64 x 64 tiles through LDS.  Each thread
+// moves 16 bytes each way: one 16-byte load of a row segment of B (when the
+// segment is inside B and aligned), sixteen LDS byte reads down a column, one
+// 16-byte store of a row segment of Bt; bytewise at the edges.
 __global__ __launch_bounds__(256) void transpose_i8_kernel(const int8_t* B, uint64_t ldb, uint32_t K,
                                                            uint32_t N, int8_t* Bt, uint64_t ldbt) {
   __shared__ int8_t t[64][65];
   const uint32_t k0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  for (uint32_t e = threadIdx.x; e < 64 * 64; e += 256) {
-    const uint32_t r = e / 64, c = e % 64;
-    t[r][c] = (k0 + r < K && n0 + c < N) ? B[(uint64_t)(k0 + r) * ldb + n0 + c] : (int8_t)0;
+  const uint32_t r = threadIdx.x / 4, c = (threadIdx.x % 4) * 16;  // 64 rows x 4 segments
+  const bool vin = ((ldb | ldbt | (uintptr_t)B | (uintptr_t)Bt) & 15u) == 0;
+  if (vin && k0 + r < K && n0 + c + 16 <= N) {
+    const v4i v = gld((const v4i*)(B + (uint64_t)(k0 + r) * ldb + n0 + c));
+    int8_t b[16];
+    __builtin_memcpy(b, &v, 16);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t[r][c + i] = b[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      t[r][c + i] = (k0 + r < K && n0 + c + i < N) ? B[(uint64_t)(k0 + r) * ldb + n0 + c + i] : (int8_t)0;
   }
   __syncthreads();
-  for (uint32_t e = threadIdx.x; e < 64 * 64; e += 256) {
-    const uint32_t r = e / 64, c = e % 64;  // r: n, c: k
-    if (n0 + r < N && k0 + c < K) Bt[(uint64_t)(n0 + r) * ldbt + k0 + c] = t[c][r];
+  // row r of this Bt tile is column r of the B tile: k = c .. c+15
+  int8_t b[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) b[i] = t[c + i][r];
+  if (n0 + r >= N) return;
+  if (vin && k0 + c + 16 <= K) {
+    v4i v;
+    __builtin_memcpy(&v, b, 16);
+    *(v4i*)(Bt + (uint64_t)(n0 + r) * ldbt + k0 + c) = v;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (k0 + c + i < K) Bt[(uint64_t)(n0 + r) * ldbt + k0 + c + i] = b[i];
   }
 }
 
@@ -741,13 +765,18 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
                          (int8_t*)bt, (uint64_t)K);
       if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
     }
-    // Workgroup tile: 4 = 256 x 128 and 3 = 256 x 256 double-buffered (large
-    // matrices; 4 by default), 0 = 256 x 256,
-    // 1 = 256 x 128, 2 = 128 x 128; K-tile 64 or 128.
-    int64_t shape = fd_tune("gemm.i8.tile", M >= 1024 && N >= 1024 ? 4 : 2);
+    // Kernel and workgroup tile (tune key gemm.i8.tile): large matrices use 7 by
+    // default.  Direct-to-LDS loads (K a multiple of 64): 7 = 256 x 256 with
+    // eight wavefronts and four stages, 5 = 256 x 128 with three stages,
+    // 6 = 256 x 256 with four wavefronts and four stages.  Register-staged,
+    // double-buffered: 4 = 256 x 128, 3 = 256 x 256.  Register-staged with
+    // in-loop folds (any K): 2 = 128 x 128 (small matrices), 1 = 256 x 128,
+    // 0 = 256 x 256.  A tiling whose conditions fail falls back to the next
+    // one that applies.
+    int64_t shape = fd_tune("gemm.i8.tile", M >= 1024 && N >= 1024 ? 7 : 2);
     // the large tile keeps its accumulators unfolded (only when K fits one fold
     // block) and needs 16-byte rows
-    if ((shape >= 3 && shape <= 6) &&
+    if ((shape >= 3 && shape <= 7) &&
         ((uint64_t)K > (lam / 128) * 128 || K % 16 != 0 || lda % 16 != 0 ||
                        ((uintptr_t)A) % 16 != 0 || M < 256 || N < 256))
       shape = 2;
@@ -766,26 +795,27 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
   if (shape == 2) { if (vec) FD_I8_LAUNCH(2, 2, KT, true); else FD_I8_LAUNCH(2, 2, KT, false); }  \
   else if (shape == 1) { if (vec) FD_I8_LAUNCH(4, 2, KT, true); else FD_I8_LAUNCH(4, 2, KT, false); } \
   else { if (vec) FD_I8_LAUNCH(4, 4, KT, true); else FD_I8_LAUNCH(4, 4, KT, false); }
-    if ((shape == 5 || shape == 6) && K % 64 == 0) {
-#define FD_I8_DMA(BJ, NS)                                                                          \
+    if ((shape == 5 || shape == 6 || shape == 7) && K % 64 == 0) {
+#define FD_I8_DMA(BJ, NS, NW)                                                                      \
   {                                                                                                \
-    const size_t lds = (size_t)NS * (256 + 64 * BJ) * 64;                                          \
+    constexpr int DTN = 64 * BJ * (NW / 4);                                                        \
+    const size_t lds = (size_t)NS * (256 + DTN) * 64;                                              \
     static bool attr_set = false;                                                                  \
     if (!attr_set) {                                                                               \
-      (void)hipFuncSetAttribute((const void*)gemm_i8_dma_kernel<BJ, NS>,                          \
+      (void)hipFuncSetAttribute((const void*)gemm_i8_dma_kernel<BJ, NS, NW>,                      \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);             \
       attr_set = true;                                                                             \
     }                                                                                              \
-    const uint64_t dma_tiles = ((M + 255) / 256) * ((N + 64 * BJ - 1) / (64 * BJ));                \
-    hipLaunchKernelGGL((gemm_i8_dma_kernel<BJ, NS>), dim3((unsigned)dma_tiles), dim3(256), lds, s, \
-                       f->k, (uint32_t)M, (uint32_t)N, (uint32_t)K, (const int8_t*)A,              \
+    const uint64_t dma_tiles = ((M + 255) / 256) * ((N + DTN - 1) / DTN);                          \
+    hipLaunchKernelGGL((gemm_i8_dma_kernel<BJ, NS, NW>), dim3((unsigned)dma_tiles), dim3(64 * NW),  \
+                       lds, s, f->k, (uint32_t)M, (uint32_t)N, (uint32_t)K, (const int8_t*)A,      \
                        (uint64_t)lda, (const int8_t*)bt, (uint64_t)K, (int8_t*)C, (uint64_t)ldc); \
   }
-      if (shape == 5) FD_I8_DMA(2, 3) else FD_I8_DMA(4, 4)
+      if (shape == 5) FD_I8_DMA(2, 3, 4) else if (shape == 6) FD_I8_DMA(4, 4, 4) else FD_I8_DMA(2, 4, 8)
 #undef FD_I8_DMA
-    } else if (shape == 3 || shape == 4 || shape == 5 || shape == 6) {
+    } else if (shape >= 3 && shape <= 7) {
       // 3: 256 x 256 tile, one wavefront per SIMD; 4: 256 x 128, two
-      const int64_t bkt = (shape == 4 || shape == 5) ? 64 : (fd_tune("gemm.i8.big.ktile", 128) == 64 ? 64 : 128);
+      const int64_t bkt = (shape == 4 || shape == 5 || shape == 7) ? 64 : (fd_tune("gemm.i8.big.ktile", 128) == 64 ? 64 : 128);
       const uint32_t big_fold = (uint32_t)(lam / (uint64_t)bkt);
 #define FD_I8_BIG(KT, BJ)                                                                          \
   {                                                                                                \
@@ -802,7 +832,7 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
                        (const int8_t*)A, (uint64_t)lda, (const int8_t*)bt, (uint64_t)K,            \
                        (int8_t*)C, (uint64_t)ldc, big_fold);                                       \
   }
-      if (shape == 4 || shape == 5) FD_I8_BIG(64, 2) else if (bkt == 64) FD_I8_BIG(64, 4) else FD_I8_BIG(128, 4)
+      if (shape == 4 || shape == 5 || shape == 7) FD_I8_BIG(64, 2) else if (bkt == 64) FD_I8_BIG(64, 4) else FD_I8_BIG(128, 4)
 #undef FD_I8_BIG
     } else if (kt == 64) { FD_I8_SHAPE(64) } else { FD_I8_SHAPE(128) }
 #undef FD_I8_SHAPE
