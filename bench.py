@@ -255,6 +255,21 @@ def extras_gemm(fd):
         tops = 2.0 * M * N * K / t / 1e12
         out[label] = {"ms": round(t * 1e3, 3), "TOPS": round(tops, 1),
                       "frac_of_peak": round(tops / peak, 4), "peak_TOPS": peak}
+        # The vendor library's plain product of the same operands (int8 with
+        # int32 output, or doubles), timed only as the achievable rate of the
+        # matrix cores at this shape; it is not exact modular arithmetic.
+        try:
+            if dt == torch.int8:
+                ref = lambda: torch._int_mm(A, B)
+            else:
+                ref = lambda: torch.matmul(A, B)
+            ref()
+            tr = time_events(ref, 3)
+            out[label]["library_plain_product"] = {
+                "ms": round(tr * 1e3, 3), "TOPS": round(2.0 * M * N * K / tr / 1e12, 1),
+                "call": "torch._int_mm" if dt == torch.int8 else "torch.matmul (float64)"}
+        except Exception as ex:  # the reference is optional
+            out[label]["library_plain_product"] = {"error": str(ex)[:120]}
         del A, B, C
         torch.cuda.empty_cache()
     return out
