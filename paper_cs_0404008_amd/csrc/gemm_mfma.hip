@@ -22,6 +22,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <set>
@@ -282,11 +283,27 @@ __device__ __forceinline__ int32_t centred_mod(int32_t v, const FieldK& F) {
 // distinct banks) and consumed in MFMA steps of 32; the next K-tile is
 // fetched into registers while the current one is multiplied.  Accumulators
 // are folded (to centred residues) after every fold_steps stagings.
-template <int BI, int BJ, int IK, bool VEC>
+// Output of one int8 product.  Centred residues: the int8 result.  SPLIT
+// (digit products of larger residues): Cu += (acc mod p) w, mod p, for the
+// digit pair's weight w < p (each output is owned by one lane of one launch,
+// and the launches of a product run in order on one stream).
+template <bool SPLIT>
+__device__ __forceinline__ void i8_store(int8_t* C, uint32_t* Cu, uint64_t w, uint64_t o,
+                                         int32_t acc, const FieldK& F) {
+  if constexpr (SPLIT) {
+    const uint64_t r = mod_i64((int64_t)acc, F);
+    Cu[o] = mod_u64((uint64_t)Cu[o] + r * w, F);
+  } else {
+    C[o] = (int8_t)centred_mod(acc, F);
+  }
+}
+
+template <int BI, int BJ, int IK, bool VEC, bool SPLIT = false>
 __global__ __launch_bounds__(256) void gemm_i8_kernel(const FieldK F, uint32_t M, uint32_t N,
                                                       uint32_t K, const int8_t* A, uint64_t lda,
                                                       const int8_t* Bt, uint64_t ldbt, int8_t* C,
-                                                      uint64_t ldc, uint32_t fold_steps) {
+                                                      uint64_t ldc, uint32_t fold_steps,
+                                                      uint32_t* Cu = nullptr, uint64_t wgt = 0) {
   constexpr int TM = 64 * BI, TN = 64 * BJ;
   constexpr int NA = TM * IK / 16 / 256, NB = TN * IK / 16 / 256;  // 16-byte vectors per thread
   __shared__ __attribute__((aligned(16))) int8_t As[TM][IK + IPAD];
@@ -375,7 +392,7 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(const FieldK F, uint32_t M
       for (int r = 0; r < 16; ++r) {
         const uint32_t gm = m0 + wm + 32 * i + 8 * (r / 4) + 4 * (lane / 32) + r % 4;
         const uint32_t gn = n0 + wn + 32 * j + lane % 32;
-        if (gm < M && gn < N) C[(uint64_t)gm * ldc + gn] = (int8_t)centred_mod(acc[i][j][r], F);
+        if (gm < M && gn < N) i8_store<SPLIT>(C, Cu, wgt, (uint64_t)gm * ldc + gn, acc[i][j][r], F);
       }
 }
 
@@ -561,10 +578,11 @@ __device__ __forceinline__ void lds_barrier() {
 // (no zero fill is possible on this path) and 16-byte rows; rows of A and
 // B^T past M and N are read from the last row and only reach outputs that
 // are not stored.
-template <int BJ, int NS, int NW>
+template <int BJ, int NS, int NW, bool SPLIT = false>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(BJ == 4 ? 1 : 2, BJ == 4 ? 1 : 2)))
 void gemm_i8_dma_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, const int8_t* A,
-                        uint64_t lda, const int8_t* Bt, uint64_t ldbt, int8_t* C, uint64_t ldc) {
+                        uint64_t lda, const int8_t* Bt, uint64_t ldbt, int8_t* C, uint64_t ldc,
+                        uint32_t* Cu = nullptr, uint64_t wgt = 0) {
   // NW = 4 wavefronts as 2 x 2, or 8 as 2 x 4 (the workgroup tile twice as
   // wide); each wavefront a 128 x (32 BJ) sub-tile.
   constexpr int IK = 64, TM = 256, TN = 64 * BJ * (NW / 4), WC = NW / 2;
@@ -659,7 +677,7 @@ void gemm_i8_dma_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, cons
       for (int r = 0; r < 16; ++r) {
         const uint32_t gm = m0 + wm + 32 * i + 8 * (r / 4) + 4 * (lane / 32) + r % 4;
         const uint32_t gn = n0 + wn + 32 * j + lane % 32;
-        if (gm < M && gn < N) C[(uint64_t)gm * ldc + gn] = (int8_t)centred_mod(acc[i][j][r], F);
+        if (gm < M && gn < N) i8_store<SPLIT>(C, Cu, wgt, (uint64_t)gm * ldc + gn, acc[i][j][r], F);
       }
 }
 
@@ -740,6 +758,157 @@ uint64_t lambda_carried(uint64_t limit, uint64_t h, uint64_t carry) {
   if (limit < carry) return 0;
   const unsigned __int128 l = (limit - carry) / hh;
   return l > 0xFFFFFFFFull ? 0xFFFFFFFFull : (uint64_t)l;
+}
+
+// ------------------------------------------------- large primes on int8 cores
+// A residue below p < 2^32 is centred (|c| <= (p-1)/2) and written with four
+// balanced base-256 digits in [-128, 127]: c = d0 + 256 d1 + 2^16 d2 + 2^24 d3,
+// which covers |c| <= 2139062143.  Then A B = sum over digit pairs (i, j) of
+// 256^(i+j) A_i B_j, sixteen exact int8 products with int32 accumulation
+// (|d d'| <= 2^14, so up to 131071 terms need no fold), each reduced mod p
+// and added with its weight 256^(i+j) mod p (times B^-1 for Montgomery
+// residues, whose products carry B^2) -- the operand-splitting counterpart of
+// the delayed reduction of Sec. 3.1 on matrix cores.
+constexpr uint64_t kSplitMaxHalf = 2139062143ull;  // 127 (1 + 2^8 + 2^16 + 2^24)
+constexpr uint32_t kSplitMaxK = 131071;            // (2^31 - 1) / 2^14
+
+__device__ __forceinline__ void balanced_digits(uint32_t v, const FieldK& F, int8_t d[4]) {
+  int64_t c = v > (uint32_t)F.half ? (int64_t)v - (int64_t)F.p : (int64_t)v;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int64_t t = c & 255;
+    if (t >= 128) t -= 256;
+    d[i] = (int8_t)t;
+    c = (c - t) / 256;
+  }
+}
+
+// A (M x K residues, row stride lda) to four digit planes, each M x ldk with
+// zeros in columns K .. ldk-1.
+__global__ __launch_bounds__(256) void digits_rows_kernel(const uint32_t* A, uint64_t lda,
+                                                          uint32_t M, uint32_t K, uint32_t ldk,
+                                                          int8_t* D, const FieldK F) {
+  const uint64_t plane = (uint64_t)M * ldk;
+  const uint64_t total = (uint64_t)M * (ldk / 4);
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t row = e / (ldk / 4);
+    const uint32_t k = (uint32_t)(e % (ldk / 4)) * 4;
+    int8_t d[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (k + q < K) {
+        balanced_digits(A[row * lda + k + q], F, d[q]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) d[q][i] = 0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t packed = (uint32_t)(uint8_t)d[0][i] | (uint32_t)(uint8_t)d[1][i] << 8 |
+                              (uint32_t)(uint8_t)d[2][i] << 16 | (uint32_t)(uint8_t)d[3][i] << 24;
+      *(uint32_t*)(D + i * plane + row * ldk + k) = packed;
+    }
+  }
+}
+
+// B (K x N residues, row stride ldb) to four digit planes of B^T, each N x
+// ldk (zeros in columns K .. ldk-1), 64 x 64 tiles through LDS.
+__global__ __launch_bounds__(256) void digits_cols_kernel(const uint32_t* B, uint64_t ldb,
+                                                          uint32_t K, uint32_t N, uint32_t ldk,
+                                                          int8_t* D, const FieldK F) {
+  __shared__ uint32_t t[64][65];
+  const uint32_t k0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  for (uint32_t e = threadIdx.x; e < 64 * 64; e += 256) {
+    const uint32_t r = e / 64, c = e % 64;  // r: k, c: n
+    t[r][c] = (k0 + r < K && n0 + c < N) ? B[(uint64_t)(k0 + r) * ldb + n0 + c] : 0u;
+  }
+  __syncthreads();
+  const uint64_t plane = (uint64_t)N * ldk;
+  const uint32_t r = threadIdx.x / 4, c = (threadIdx.x % 4) * 16;  // r: n, c: first k
+  if (n0 + r >= N || k0 + c >= ldk) return;
+  int8_t d[16][4];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) balanced_digits(t[c + q][r], F, d[q]);  // zero residue: zero digits
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int8_t row[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) row[q] = d[q][i];
+    v4i v;
+    __builtin_memcpy(&v, row, 16);
+    *(v4i*)(D + i * plane + (uint64_t)(n0 + r) * ldk + k0 + c) = v;
+  }
+}
+
+// C (M x N residues, row stride ldc) = 0.
+__global__ __launch_bounds__(256) void zero_rows_kernel(uint32_t* C, uint64_t ldc, uint32_t M,
+                                                        uint32_t N) {
+  const uint64_t total = (uint64_t)M * N;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * blockDim.x)
+    C[(e / N) * ldc + e % N] = 0u;
+}
+
+fdot_status_t gemm_split(const fdot_field_s* f, size_t M, size_t N, size_t K, const void* A,
+                         size_t lda, const void* B, size_t ldb, void* C, size_t ldc,
+                         hipStream_t s) {
+  const fdot_field_info_t& I = f->info;
+  const uint32_t ldk = (uint32_t)((K + 63) / 64 * 64);
+  const size_t bytes = (size_t)4 * ((size_t)M + N) * ldk + 256;
+  void* scr = nullptr;
+  fdot_status_t st = scratch_for(s, bytes, &scr);
+  if (st != FDOT_OK) return st;
+  int8_t* Ad = (int8_t*)scr;
+  int8_t* Bd = Ad + (size_t)4 * M * ldk;
+  const uint64_t cells = (uint64_t)M * N;
+  const unsigned zg = (unsigned)std::min<uint64_t>((cells + 255) / 256, 65536);
+  hipLaunchKernelGGL(zero_rows_kernel, dim3(zg), dim3(256), 0, s, (uint32_t*)C, (uint64_t)ldc,
+                     (uint32_t)M, (uint32_t)N);
+  const uint64_t ag = std::min<uint64_t>(((uint64_t)M * (ldk / 4) + 255) / 256, 65536);
+  hipLaunchKernelGGL(digits_rows_kernel, dim3((unsigned)ag), dim3(256), 0, s, (const uint32_t*)A,
+                     (uint64_t)lda, (uint32_t)M, (uint32_t)K, ldk, Ad, f->k);
+  hipLaunchKernelGGL(digits_cols_kernel, dim3((unsigned)((N + 63) / 64), (unsigned)(ldk / 64)),
+                     dim3(256), 0, s, (const uint32_t*)B, (uint64_t)ldb, (uint32_t)K, (uint32_t)N,
+                     ldk, Bd, f->k);
+  if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
+  const unsigned __int128 p = I.p;
+  uint64_t base = I.rep == FDOT_REP_MONT_U32 ? I.binv_mod_p : 1;  // Montgomery: one factor B^-1
+  const bool big = M >= 256 && N >= 256 && fd_tune("gemm.split.small", 0) == 0;
+  const size_t lds = (size_t)4 * (256 + 256) * 64;
+  if (big) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      (void)hipFuncSetAttribute((const void*)gemm_i8_dma_kernel<2, 4, 8, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      attr_set = true;
+    }
+  }
+  for (int e = 0; e <= 6; ++e) {
+    const uint64_t w = base;  // 256^e (B^-1) mod p
+    for (int i = 0; i <= 3; ++i) {
+      const int j = e - i;
+      if (j < 0 || j > 3) continue;
+      const int8_t* Ai = Ad + (size_t)i * M * ldk;
+      const int8_t* Bj = Bd + (size_t)j * N * ldk;
+      if (big) {
+        const uint64_t tiles = ((M + 255) / 256) * ((N + 255) / 256);
+        hipLaunchKernelGGL((gemm_i8_dma_kernel<2, 4, 8, true>), dim3((unsigned)tiles), dim3(512),
+                           lds, s, f->k, (uint32_t)M, (uint32_t)N, ldk, Ai, (uint64_t)ldk, Bj,
+                           (uint64_t)ldk, (int8_t*)nullptr, (uint64_t)ldc, (uint32_t*)C, w);
+      } else {
+        const uint64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
+        hipLaunchKernelGGL((gemm_i8_kernel<2, 2, 64, true, true>), dim3((unsigned)tiles),
+                           dim3(256), 0, s, f->k, (uint32_t)M, (uint32_t)N, ldk, Ai,
+                           (uint64_t)ldk, Bj, (uint64_t)ldk, (int8_t*)nullptr, (uint64_t)ldc,
+                           0xFFFFFFFFu, (uint32_t*)C, w);
+      }
+      if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
+    }
+    base = (uint64_t)(((unsigned __int128)base * 256u) % p);
+  }
+  return FDOT_OK;
 }
 
 }  // namespace
@@ -856,7 +1025,15 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
     centre = true;
     lam = lam_centre;
   }
-  if (lam < 4) return FDOT_E_UNSUPPORTED;
+  if (lam < 4) {
+    // larger primes: digit products on the int8 matrix cores
+    if ((I.rep == FDOT_REP_ZPZ_U32 || I.rep == FDOT_REP_MONT_U32) && h <= kSplitMaxHalf &&
+        K >= 1 && K <= kSplitMaxK - 63 && M > 0 && N > 0 && fd_tune("gemm.split.disable", 0) == 0) {
+      *handled = true;
+      return gemm_split(f, M, N, K, A, lda, B, ldb, C, ldc, s);
+    }
+    return FDOT_E_UNSUPPORTED;
+  }
   *handled = true;
   const uint64_t tiles = ((M + FM - 1) / FM) * ((N + FN - 1) / FN);
   if (tiles > 0x7FFFFFFFull) return FDOT_E_INVALID_ARG;

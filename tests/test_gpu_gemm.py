@@ -24,7 +24,8 @@ FIELDS = [
     (65521, "zpz"),          # FP64 MFMA from uint32 residues
     (32749, "mont"),         # FP64 MFMA on Montgomery residues, one REDC at the end
     (251, "centred"),        # int8 MFMA
-    (2147483647, "zpz"),     # vector-ALU kernel
+    (2147483647, "zpz"),     # int8 MFMA on four balanced base-256 digits
+    (4278124237, "zpz"),     # largest prime the digit split covers
     (4294967291, "mont"),    # vector-ALU kernel
     (32749, "zech"),         # vector-ALU kernel
 ]
@@ -177,3 +178,24 @@ def test_gemm_fp64_wave_layouts(waves):
             assert same(got, oracle.gemm(p, "fp64", A, B)), (waves, p, K)
     finally:
         fd.tune_set("gemm.f64.waves", None)
+
+
+@pytest.mark.parametrize("p,rep", [(2147483647, "zpz"), (2147483647, "mont"), (4278124237, "zpz"),
+                                   (2654435761, "mont")])
+@pytest.mark.parametrize("M,N,K", [(300, 260, 700), (1030, 1100, 1000), (40, 36, 131008)])
+def test_gemm_digit_split(p, rep, M, N, K):
+    """Large primes on the int8 matrix cores through sixteen digit products:
+    ragged shapes, K not a multiple of 64, the largest K without folds, the
+    large-tile kernel (M, N >= 256) and the small one; sampled entries against
+    the oracle, maximal products included."""
+    F = field(p, rep)
+    for pattern in ("random", "maxprod"):
+        A = mat(p, rep, M, K, 73, 0, pattern)
+        B = mat(p, rep, K, N, 73, 1, pattern)
+        got = to_host(F.gemm(to_dev(A), to_dev(B)))
+        rows = synth.uniform_int(74, 0, 160, M)
+        cols = synth.uniform_int(74, 1, 160, N)
+        rows[:2] = [0, M - 1]
+        cols[:2] = [0, N - 1]
+        want = oracle.gemm_entries(p, rep, A, B, rows, cols)
+        assert same(got[rows, cols], want), (p, rep, M, N, K, pattern)
