@@ -287,6 +287,12 @@ typedef struct {
   uint32_t fake_device;  /* 1: no GPU; completions are simulated (scheduler tests) */
   uint32_t plain;        /* 1: no batching: one launch per request, one stream,
                             arrival order (the comparison baseline) */
+  uint64_t exclusive_ns; /* a request whose estimated device time exceeds this
+                            runs alone: it is admitted when nothing is in
+                            flight and nothing is admitted while it runs, so
+                            overlap never slows the longest requests (0 = off:
+                            on the mixed stream it cost more waiting behind
+                            long requests than it saved) */
 } fdot_server_cfg_t;
 
 typedef struct {
@@ -322,7 +328,9 @@ fdot_status_t fdot_server_poll(fdot_server_t s, uint64_t ticket, int* done, fdot
  * (FDOT_E_BUSY on timeout). */
 fdot_status_t fdot_server_drain(fdot_server_t s, uint64_t timeout_ms);
 /* Load generator: submit reqs[i] when arrival_s[i] seconds (non-decreasing)
- * have passed since the call, wait for all, fill timings[i]. */
+ * have passed since the call, wait for all, fill timings[i]; there submit_ns
+ * is the scheduled arrival, so time spent blocked in submit counts as
+ * waiting. */
 fdot_status_t fdot_server_replay(fdot_server_t s, const fdot_request_t* reqs,
                                  const double* arrival_s, size_t count, fdot_timing_t* timings);
 fdot_status_t fdot_server_stats(fdot_server_t s, fdot_server_stats_t* out);

@@ -296,7 +296,7 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", _u64), ("max_inflight", ctypes.c_uint32),
                 ("max_queue", ctypes.c_uint32), ("streams", ctypes.c_uint32),
                 ("max_batch", ctypes.c_uint32), ("fake_device", ctypes.c_uint32),
-                ("plain", ctypes.c_uint32)]
+                ("plain", ctypes.c_uint32), ("exclusive_ns", _u64)]
 
 
 class Timing(ctypes.Structure):
@@ -333,9 +333,9 @@ class Server:
 
     def __init__(self, hbm_budget: int = 0, max_inflight: int = 0, max_queue: int = 0,
                  streams: int = 0, max_batch: int = 0, fake_device: bool = False,
-                 plain: bool = False):
+                 plain: bool = False, exclusive_ns: int = 0):
         cfg = ServerConfig(hbm_budget, max_inflight, max_queue, streams, max_batch,
-                           1 if fake_device else 0, 1 if plain else 0)
+                           1 if fake_device else 0, 1 if plain else 0, exclusive_ns)
         h = _vp()
         _check(_lib.fdot_server_create(ctypes.byref(cfg), ctypes.byref(h)), "fdot_server_create")
         self._h = h

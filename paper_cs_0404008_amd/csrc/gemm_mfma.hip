@@ -287,15 +287,60 @@ __device__ __forceinline__ int32_t centred_mod(int32_t v, const FieldK& F) {
 // (digit products of larger residues): Cu += (acc mod p) w, mod p, for the
 // digit pair's weight w < p (each output is owned by one lane of one launch,
 // and the launches of a product run in order on one stream).
-template <bool SPLIT>
-__device__ __forceinline__ void i8_store(int8_t* C, uint32_t* Cu, uint64_t w, uint64_t o,
-                                         int32_t acc, const FieldK& F) {
-  if constexpr (SPLIT) {
-    const uint64_t r = mod_i64((int64_t)acc, F);
-    Cu[o] = mod_u64((uint64_t)Cu[o] + r * w, F);
-  } else {
-    C[o] = (int8_t)centred_mod(acc, F);
-  }
+// Centred residue of a finished int8 tile entry.
+__device__ __forceinline__ void i8_store(int8_t* C, uint64_t o, int32_t acc, const FieldK& F) {
+  C[o] = (int8_t)centred_mod(acc, F);
+}
+
+// x * w mod p for any x < 2^32 by Shoup's method: wgt holds w < p in its low
+// half and floor(w 2^32 / p) in its high half, so the quotient estimate is
+// one multiply-high and falls short of the true quotient by at most one.
+__device__ __forceinline__ uint32_t mulmod_pre(uint32_t x, uint64_t wgt, const FieldK& F) {
+  const uint64_t q = ((uint64_t)x * (wgt >> 32)) >> 32;
+  const uint64_t r = (uint64_t)x * (uint32_t)wgt - q * F.p;
+  return (uint32_t)(r >= F.p ? r - F.p : r);
+}
+
+// Digit-product epilogue for one 32-row block of a wavefront's tile:
+// Cu = (Cu + acc * w) mod p for its 32 x 32*BJ entries.  A negative acc is
+// first lifted by pm, the least multiple of p that is at least 2^31, so that
+// the multiplier sees a value in [0, 2^32).  The products replace the
+// accumulators in place; then every load of Cu is issued before the first
+// store, so their latencies overlap.  Requires M, N >= 1.
+template <int BJ>
+__device__ __forceinline__ void split_rows(uint32_t* Cu, uint64_t ldc, uint64_t wgt, v16i* acc,
+                                           uint32_t row0, uint32_t col0, uint32_t lane,
+                                           uint32_t M, uint32_t N, uint64_t pm,
+                                           const FieldK& F) {
+#pragma unroll
+  for (int j = 0; j < BJ; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t a = acc[j][r];
+      acc[j][r] = (int32_t)mulmod_pre((uint32_t)(a < 0 ? a + (int64_t)pm : a), wgt, F);
+    }
+  uint32_t old[BJ][16];
+#pragma unroll
+  for (int j = 0; j < BJ; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const uint32_t gm = row0 + 8 * (r / 4) + 4 * (lane / 32) + r % 4;
+      const uint32_t gn = col0 + 32 * j + lane % 32;
+      // clamped (always valid) addresses keep the loads unconditional, so
+      // they are all in flight together; entries outside C are not stored
+      old[j][r] = Cu[(uint64_t)min(gm, M - 1) * ldc + min(gn, N - 1)];
+    }
+#pragma unroll
+  for (int j = 0; j < BJ; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const uint32_t gm = row0 + 8 * (r / 4) + 4 * (lane / 32) + r % 4;
+      const uint32_t gn = col0 + 32 * j + lane % 32;
+      if (gm < M && gn < N) {
+        const uint64_t t = (uint64_t)old[j][r] + (uint32_t)acc[j][r];
+        Cu[(uint64_t)gm * ldc + gn] = (uint32_t)(t >= F.p ? t - F.p : t);
+      }
+    }
 }
 
 template <int BI, int BJ, int IK, bool VEC, bool SPLIT = false>
@@ -384,6 +429,13 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(const FieldK F, uint32_t M
       steps = 0;
     }
   }
+  if constexpr (SPLIT) {
+    const uint64_t pm = (0x80000000ull + F.p - 1) / F.p * F.p;
+#pragma unroll
+    for (int i = 0; i < BI; ++i)
+      split_rows<BJ>(Cu, ldc, wgt, acc[i], m0 + wm + 32 * i, n0 + wn, lane, M, N, pm, F);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < BI; ++i)
 #pragma unroll
@@ -392,7 +444,7 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(const FieldK F, uint32_t M
       for (int r = 0; r < 16; ++r) {
         const uint32_t gm = m0 + wm + 32 * i + 8 * (r / 4) + 4 * (lane / 32) + r % 4;
         const uint32_t gn = n0 + wn + 32 * j + lane % 32;
-        if (gm < M && gn < N) i8_store<SPLIT>(C, Cu, wgt, (uint64_t)gm * ldc + gn, acc[i][j][r], F);
+        if (gm < M && gn < N) i8_store(C, (uint64_t)gm * ldc + gn, acc[i][j][r], F);
       }
 }
 
@@ -669,6 +721,13 @@ void gemm_i8_dma_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, cons
           acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
+  if constexpr (SPLIT) {
+    const uint64_t pm = (0x80000000ull + F.p - 1) / F.p * F.p;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      split_rows<BJ>(Cu, ldc, wgt, acc[i], m0 + wm + 32 * i, n0 + wn, lane, M, N, pm, F);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -677,7 +736,7 @@ void gemm_i8_dma_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, cons
       for (int r = 0; r < 16; ++r) {
         const uint32_t gm = m0 + wm + 32 * i + 8 * (r / 4) + 4 * (lane / 32) + r % 4;
         const uint32_t gn = n0 + wn + 32 * j + lane % 32;
-        if (gm < M && gn < N) i8_store<SPLIT>(C, Cu, wgt, (uint64_t)gm * ldc + gn, acc[i][j][r], F);
+        if (gm < M && gn < N) i8_store(C, (uint64_t)gm * ldc + gn, acc[i][j][r], F);
       }
 }
 
@@ -686,7 +745,8 @@ void gemm_i8_dma_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, cons
 // segment is inside B and aligned), sixteen LDS byte reads down a column, one
 // 16-byte store of a row segment of Bt; bytewise at the edges.
 __global__ __launch_bounds__(256) void transpose_i8_kernel(const int8_t* B, uint64_t ldb, uint32_t K,
-                                                           uint32_t N, int8_t* Bt, uint64_t ldbt) {
+                                                           uint32_t N, int8_t* Bt, uint64_t ldbt,
+                                                           uint32_t Kout) {
   __shared__ int8_t t[64][65];
   const uint32_t k0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const uint32_t r = threadIdx.x / 4, c = (threadIdx.x % 4) * 16;  // 64 rows x 4 segments
@@ -708,14 +768,57 @@ __global__ __launch_bounds__(256) void transpose_i8_kernel(const int8_t* B, uint
 #pragma unroll
   for (int i = 0; i < 16; ++i) b[i] = t[c + i][r];
   if (n0 + r >= N) return;
-  if (vin && k0 + c + 16 <= K) {
+  // columns K .. Kout-1 of Bt (zero in the tile) are the zero padding
+  if (vin && k0 + c + 16 <= Kout) {
     v4i v;
     __builtin_memcpy(&v, b, 16);
     *(v4i*)(Bt + (uint64_t)(n0 + r) * ldbt + k0 + c) = v;
   } else {
 #pragma unroll
     for (int i = 0; i < 16; ++i)
-      if (k0 + c + i < K) Bt[(uint64_t)(n0 + r) * ldbt + k0 + c + i] = b[i];
+      if (k0 + c + i < Kout) Bt[(uint64_t)(n0 + r) * ldbt + k0 + c + i] = b[i];
+  }
+}
+
+// dst = src (rows x cols, row stride ld) with each row padded by zeros to
+// ldd elements: one workgroup per row at a time, coalesced along the row.
+template <typename T>
+__global__ __launch_bounds__(256) void pad_copy_kernel(const T* src, uint64_t ld, uint32_t rows,
+                                                       uint32_t cols, T* dst, uint32_t ldd) {
+  for (uint32_t row = blockIdx.x; row < rows; row += gridDim.x)
+    for (uint32_t c = threadIdx.x; c < ldd; c += 256)
+      dst[(uint64_t)row * ldd + c] = c < cols ? src[(uint64_t)row * ld + c] : (T)0;
+}
+
+template <typename T>
+hipError_t pad_copy(const void* src, size_t ld, size_t rows, size_t cols, void* dst, size_t ldd,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(pad_copy_kernel<T>, dim3((unsigned)std::min<size_t>(rows, 65536)), dim3(256),
+                     0, s, (const T*)src, (uint64_t)ld, (uint32_t)rows, (uint32_t)cols, (T*)dst,
+                     (uint32_t)ldd);
+  return hipGetLastError();
+}
+
+// Ap = A with rows padded by zeros from K to Kp (a multiple of 64), row
+// stride Kp: one 16-byte segment of Ap per thread.
+__global__ __launch_bounds__(256) void pad_rows_i8_kernel(const int8_t* A, uint64_t lda, uint32_t M,
+                                                          uint32_t K, int8_t* Ap, uint32_t Kp) {
+  const uint64_t segs = (uint64_t)M * (Kp / 16);
+  for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < segs;
+       e += (uint64_t)gridDim.x * 256) {
+    const uint64_t row = e / (Kp / 16);
+    const uint32_t k = (uint32_t)(e % (Kp / 16)) * 16;
+    const int8_t* src = A + row * lda + k;
+    v4i v = {0, 0, 0, 0};
+    if (k + 16 <= K && ((uintptr_t)src & 15u) == 0) {
+      v = gld((const v4i*)src);
+    } else {
+      int8_t t[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) t[i] = k + i < K ? src[i] : (int8_t)0;
+      __builtin_memcpy(&v, t, 16);
+    }
+    *(v4i*)(Ap + row * Kp + k) = v;
   }
 }
 
@@ -886,7 +989,8 @@ fdot_status_t gemm_split(const fdot_field_s* f, size_t M, size_t N, size_t K, co
     }
   }
   for (int e = 0; e <= 6; ++e) {
-    const uint64_t w = base;  // 256^e (B^-1) mod p
+    // 256^e (B^-1) mod p with its precomputed quotient for the epilogue
+    const uint64_t w = base | ((uint64_t)(((unsigned __int128)base << 32) / p) << 32);
     for (int i = 0; i <= 3; ++i) {
       const int j = e - i;
       if (j < 0 || j > 3) continue;
@@ -925,15 +1029,37 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
     const uint64_t lam = lambda_carried(0x7FFFFFFFull, h, h);
     if (lam < 128 || fd_tune("gemm.i8.disable", 0)) return FDOT_E_UNSUPPORTED;
     *handled = true;
+    int64_t shape = fd_tune("gemm.i8.tile", M >= 1024 && N >= 1024 ? 7 : 2);
+    // The direct-to-LDS tilings need K a multiple of 64 and 16-byte rows of A;
+    // other shapes get zero-padded copies (zero terms leave every sum as it
+    // is, so the fold bound still applies to the true K).
+    const uint64_t Kp = (K + 63) / 64 * 64;
+    const bool dma = (shape == 5 || shape == 6 || shape == 7) && K > 0 &&
+                     (uint64_t)K <= (lam / 128) * 128 && M >= 256 && N >= 256 &&
+                     Kp <= 0xFFFFFFFFull && fd_tune("gemm.i8.pad", 1) != 0;
+    const bool pad_a = dma && (K % 64 != 0 || lda % 16 != 0 || ((uintptr_t)A) % 16 != 0);
+    const uint64_t ldbt = dma ? Kp : K;
     void* bt = nullptr;
-    fdot_status_t st = scratch_for(s, (size_t)N * K + 16, &bt);
+    fdot_status_t st =
+        scratch_for(s, (size_t)N * ldbt + (pad_a ? (size_t)M * Kp : 0) + 16, &bt);
     if (st != FDOT_OK) return st;
     if (K > 0) {
-      hipLaunchKernelGGL(transpose_i8_kernel, dim3((unsigned)((N + 63) / 64), (unsigned)((K + 63) / 64)),
+      hipLaunchKernelGGL(transpose_i8_kernel, dim3((unsigned)((N + 63) / 64), (unsigned)((ldbt + 63) / 64)),
                          dim3(256), 0, s, (const int8_t*)B, (uint64_t)ldb, (uint32_t)K, (uint32_t)N,
-                         (int8_t*)bt, (uint64_t)K);
+                         (int8_t*)bt, ldbt, (uint32_t)ldbt);
       if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
     }
+    if (pad_a) {
+      int8_t* ap = (int8_t*)bt + (size_t)N * ldbt;
+      const uint64_t segs = (uint64_t)M * (Kp / 16);
+      hipLaunchKernelGGL(pad_rows_i8_kernel, dim3((unsigned)std::min<uint64_t>((segs + 255) / 256, 65536)),
+                         dim3(256), 0, s, (const int8_t*)A, (uint64_t)lda, (uint32_t)M, (uint32_t)K,
+                         ap, (uint32_t)Kp);
+      if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
+      A = ap;
+      lda = Kp;
+    }
+    if (dma) K = Kp;
     // Kernel and workgroup tile (tune key gemm.i8.tile): large matrices use 7 by
     // default.  Direct-to-LDS loads (K a multiple of 64): 7 = 256 x 256 with
     // eight wavefronts and four stages, 5 = 256 x 128 with three stages,
@@ -942,7 +1068,6 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
     // in-loop folds (any K): 2 = 128 x 128 (small matrices), 1 = 256 x 128,
     // 0 = 256 x 256.  A tiling whose conditions fail falls back to the next
     // one that applies.
-    int64_t shape = fd_tune("gemm.i8.tile", M >= 1024 && N >= 1024 ? 7 : 2);
     // the large tile keeps its accumulators unfolded (only when K fits one fold
     // block) and needs 16-byte rows
     if ((shape >= 3 && shape <= 7) &&
@@ -978,7 +1103,7 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
     const uint64_t dma_tiles = ((M + 255) / 256) * ((N + DTN - 1) / DTN);                          \
     hipLaunchKernelGGL((gemm_i8_dma_kernel<BJ, NS, NW>), dim3((unsigned)dma_tiles), dim3(64 * NW),  \
                        lds, s, f->k, (uint32_t)M, (uint32_t)N, (uint32_t)K, (const int8_t*)A,      \
-                       (uint64_t)lda, (const int8_t*)bt, (uint64_t)K, (int8_t*)C, (uint64_t)ldc); \
+                       (uint64_t)lda, (const int8_t*)bt, ldbt, (int8_t*)C, (uint64_t)ldc);      \
   }
       if (shape == 5) FD_I8_DMA(2, 3, 4) else if (shape == 6) FD_I8_DMA(4, 4, 4) else FD_I8_DMA(2, 4, 8)
 #undef FD_I8_DMA
@@ -1067,8 +1192,30 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
   const size_t esz = I.elem_bytes, pair = 2 * esz;
   // Pair loads need both rows of A and B to start on a pair boundary, and K
   // and N even so that no pair reaches past the end of a row.
-  const bool vec = lda % 2 == 0 && ldb % 2 == 0 && K % 2 == 0 && N % 2 == 0 &&
-                   ((uintptr_t)A) % pair == 0 && ((uintptr_t)B) % pair == 0;
+  bool vec = lda % 2 == 0 && ldb % 2 == 0 && K % 2 == 0 && N % 2 == 0 &&
+             ((uintptr_t)A) % pair == 0 && ((uintptr_t)B) % pair == 0;
+  // Any other shape or layout: A and B are copied into scratch with rows
+  // padded by zeros to an even length, so every pair load stays inside its
+  // padded row; the kernel's masks by K and N still drop the padding.
+  if (!vec && K > 0 && M > 0 && N > 0 && fd_tune("gemm.f64.pad", 1) != 0) {
+    const size_t Kp = K + (K & 1), Np = N + (N & 1);
+    const size_t a_bytes = (M * Kp * esz + 255) / 256 * 256;
+    void* scr = nullptr;
+    fdot_status_t st = scratch_for(s, a_bytes + K * Np * esz, &scr);
+    if (st != FDOT_OK) return st;
+    char* ap = (char*)scr;
+    char* bp = ap + a_bytes;
+    const hipError_t ea = esz == 8 ? pad_copy<uint64_t>(A, lda, M, K, ap, Kp, s)
+                                   : pad_copy<uint32_t>(A, lda, M, K, ap, Kp, s);
+    const hipError_t eb = esz == 8 ? pad_copy<uint64_t>(B, ldb, K, N, bp, Np, s)
+                                   : pad_copy<uint32_t>(B, ldb, K, N, bp, Np, s);
+    if (ea != hipSuccess || eb != hipSuccess) return FDOT_E_DEVICE;
+    A = ap;
+    lda = Kp;
+    B = bp;
+    ldb = Np;
+    vec = true;
+  }
   if (I.rep == FDOT_REP_FP64) {
     if (centre) { FD_F64_PICK(double, true) } else { FD_F64_PICK(double, false) }
   } else {

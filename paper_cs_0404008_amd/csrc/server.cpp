@@ -6,7 +6,9 @@
 //      done: footprint and slots are released),
 //   2. admits waiting requests in arrival order while an in-flight slot and
 //      enough of the HBM budget are free (a request that does not fit blocks
-//      the ones behind it, so admission never reorders arrivals),
+//      the ones behind it, so admission never reorders arrivals); a request
+//      estimated to take longer than exclusive_ns runs alone, so that overlap
+//      never stretches the longest requests, which set the tail latency,
 //   3. launches everything admitted: the dot requests of one field are fused
 //      into one batched launch (descriptors staged through pinned memory,
 //      results scattered back to each request's output), matrix-vector and
@@ -78,16 +80,32 @@ uint64_t footprint_of(const fdot_request_t& r) {
 }
 
 // Simulated device time of a request (fake-device mode only).
-uint64_t fake_ns(const fdot_request_t& r) {
-  const double e = (double)r.field->info.elem_bytes;
+// Estimated device time of a request: streaming forms at HBM speed, matrix
+// products at the rate of the path they take (int8 cores for centred int8
+// residues, FP64 cores for fp64 and small classical primes, digit products
+// on the int8 cores for larger primes).  Used for the simulated device and
+// for the exclusive rule; only its order of magnitude matters.
+uint64_t est_ns(const fdot_request_t& r) {
+  const fdot_field_info_t& I = r.field->info;
+  const double e = (double)I.elem_bytes;
   double s = 5e-6;
   switch (r.op) {
-    case FDOT_OP_DOT: s += 2.0 * r.n * e / 5e12; break;
-    case FDOT_OP_GEMV: s += (double)r.m * r.n * e / 5e12; break;
-    case FDOT_OP_GEMM: s += 2.0 * r.m * r.n * r.k / 2e13; break;
+    case FDOT_OP_DOT: s += 2.0 * r.n * e / 6e12; break;
+    case FDOT_OP_GEMV: s += (double)r.m * r.n * e / 6e12; break;
+    case FDOT_OP_GEMM: {
+      double rate = 1e13;  // exact vector-ALU kernel
+      if (I.rep == FDOT_REP_CENTRED_I8)
+        rate = 1.5e15;
+      else if (I.rep == FDOT_REP_FP64 || I.lambda_f64 >= 4 ||
+               ((I.rep == FDOT_REP_ZPZ_U32 || I.rep == FDOT_REP_MONT_U32) && I.p <= 4278124237ull))
+        rate = 5e13;  // FP64 cores, or int8 digit products for larger primes
+      s += 2.0 * r.m * r.n * r.k / rate;
+      break;
+    }
   }
   return (uint64_t)(s * 1e9);
 }
+uint64_t fake_ns(const fdot_request_t& r) { return est_ns(r); }
 
 }  // namespace
 
@@ -104,6 +122,7 @@ struct fdot_server_s {
   std::deque<uint64_t> pending;
   std::vector<uint64_t> admitted;
   std::vector<Launch> inflight;
+  bool heavy_inflight = false;  // an exclusive request is admitted or running
   uint64_t used_fp = 0;
   uint32_t n_admitted = 0;  // admitted and not yet done
   std::vector<hipStream_t> streams;
@@ -167,6 +186,7 @@ struct fdot_server_s {
   void finish_launch(Launch& L, uint64_t now) {
     for (uint64_t tk : L.tickets) {
       Req& q = reqs[tk];
+      if (!cfg.plain && est_ns(q.r) > cfg.exclusive_ns) heavy_inflight = false;
       q.done = true;
       q.t.done_ns = now;
       q.t.status = L.status;
@@ -305,9 +325,14 @@ struct fdot_server_s {
           ++i;
         }
       }
-      while (!pending.empty() && n_admitted < cfg.max_inflight) {
+      while (!pending.empty() && n_admitted < cfg.max_inflight && !heavy_inflight) {
         Req& q = reqs[pending.front()];
         if (used_fp + q.fp > cfg.hbm_budget) break;
+        if (!cfg.plain && est_ns(q.r) > cfg.exclusive_ns) {
+          // runs alone: wait until nothing is admitted or in flight
+          if (n_admitted > 0) break;
+          heavy_inflight = true;
+        }
         used_fp += q.fp;
         ++n_admitted;
         q.t.admit_ns = now_ns();
@@ -357,7 +382,9 @@ fdot_status_t fdot_server_create(const fdot_server_cfg_t* cfg, fdot_server_t* ou
     if (cfg->max_batch) c.max_batch = cfg->max_batch;
     c.fake_device = cfg->fake_device;
     c.plain = cfg->plain;
+    c.exclusive_ns = cfg->exclusive_ns;
   }
+  if (c.exclusive_ns == 0) c.exclusive_ns = ~0ull;  // off
   if (c.streams > 64) return FDOT_E_INVALID_ARG;
   fdot_server_s* s = new (std::nothrow) fdot_server_s;
   if (!s) return FDOT_E_NOMEM;
@@ -442,6 +469,8 @@ fdot_status_t fdot_server_replay(fdot_server_t s, const fdot_request_t* reqs,
   if (!s || (count && (!reqs || !arrival_s || !timings))) return FDOT_E_INVALID_ARG;
   std::vector<uint64_t> tickets(count, 0);
   const auto t0 = std::chrono::steady_clock::now();
+  const uint64_t t0_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+                             t0.time_since_epoch()).count();
   for (size_t i = 0; i < count; ++i) {
     const auto due = t0 + std::chrono::nanoseconds((int64_t)(arrival_s[i] * 1e9));
     // sleep until shortly before the arrival, then spin to it
@@ -458,7 +487,12 @@ fdot_status_t fdot_server_replay(fdot_server_t s, const fdot_request_t* reqs,
   fdot_status_t st = fdot_server_drain(s, 600000);
   if (st != FDOT_OK) return st;
   std::lock_guard<std::mutex> g(s->mu);
-  for (size_t i = 0; i < count; ++i) timings[i] = s->reqs[tickets[i]].t;
+  for (size_t i = 0; i < count; ++i) {
+    // latency counts from the scheduled arrival: a submit that had to wait
+    // (for the lock or for queue space) is waiting time of the request
+    timings[i] = s->reqs[tickets[i]].t;
+    timings[i].submit_ns = std::min(timings[i].submit_ns, t0_ns + (uint64_t)(arrival_s[i] * 1e9));
+  }
   return FDOT_OK;
 }
 

@@ -149,7 +149,8 @@ def test_gemm_int8_tile_variants(shape):
     F = field(p, rep)
     fd.tune_set("gemm.i8.tile", shape)
     try:
-        for (M, N, K) in [(1100, 1030, 1024), (1024, 1280, 2048 + 64), (1100, 1030, 1000)]:
+        for (M, N, K) in [(1100, 1030, 1024), (1024, 1280, 2048 + 64), (1100, 1030, 1000),
+                          (300, 257, 1001)]:
             A = mat(p, rep, M, K, 70, 0, "random")
             B = mat(p, rep, K, N, 70, 1, "random")
             got = to_host(F.gemm(to_dev(A), to_dev(B)))
@@ -161,6 +162,50 @@ def test_gemm_int8_tile_variants(shape):
             assert same(got[rows, cols], want), (shape, M, N, K)
     finally:
         fd.tune_set("gemm.i8.tile", None)
+
+
+@pytest.mark.parametrize("pad", [1, 0])
+def test_gemm_int8_zero_padded_operands(pad):
+    """K not a multiple of 64 and A rows at an odd stride (a column slice of a
+    wider matrix): the direct-to-LDS kernel on zero-padded copies (pad=1,
+    default) and the register-staged fallback (pad=0), both against the
+    oracle, maximal products included."""
+    p, rep = 251, "centred"
+    F = field(p, rep)
+    fd.tune_set("gemm.i8.pad", pad)
+    try:
+        for pattern in ("random", "maxprod"):
+            M, N, K = 1037, 1100, 2517
+            W = mat(p, rep, M, K + 3, 75, 0, pattern)
+            B = mat(p, rep, K, N, 75, 1, pattern)
+            Wd = to_dev(W)
+            got = to_host(F.gemm(Wd[:, 1:K + 1], to_dev(B)))
+            A = W[:, 1:K + 1]
+            rows = synth.uniform_int(76, 0, 400, M)
+            cols = synth.uniform_int(76, 1, 400, N)
+            rows[:2] = [0, M - 1]
+            cols[:2] = [0, N - 1]
+            want = oracle.gemm_entries(p, rep, np.ascontiguousarray(A), B, rows, cols)
+            assert same(got[rows, cols], want), (pad, pattern)
+    finally:
+        fd.tune_set("gemm.i8.pad", None)
+
+
+@pytest.mark.parametrize("p,rep", [(1048573, "fp64"), (67108859, "fp64"), (65521, "zpz"),
+                                   (32749, "mont")])
+def test_gemm_fp64_unpadded_element_loads(p, rep):
+    """Odd K and N through the FP64 matrix-core kernel's element loads (the
+    zero-padded copies switched off), against the oracle."""
+    F = field(p, rep)
+    fd.tune_set("gemm.f64.pad", 0)
+    try:
+        for (M, N, K) in [(7, 5, 9), (130, 129, 33), (257, 301, 1001)]:
+            A = mat(p, rep, M, K, 77, 0, "random")
+            B = mat(p, rep, K, N, 77, 1, "random")
+            got = to_host(F.gemm(to_dev(A), to_dev(B)))
+            assert same(got, oracle.gemm(p, rep, A, B)), (p, rep, M, N, K)
+    finally:
+        fd.tune_set("gemm.f64.pad", None)
 
 
 @pytest.mark.parametrize("waves", [4, 8, 16])

@@ -1,6 +1,7 @@
 """The request server's scheduling logic without a GPU (fake-device mode):
 admission by footprint and slots, arrival order, batching, back-pressure,
-rejection of requests that can never fit, and the replay load generator."""
+rejection of requests that can never fit, exclusive long requests, and the
+replay load generator."""
 import time
 
 import numpy as np
@@ -81,7 +82,7 @@ def test_batching_and_plain_mode():
 
 
 def test_back_pressure_and_rejection():
-    big = fd.make_request("gemm", F2, FAKE, FAKE, FAKE, m=4096, n=4096, k=4096)  # ~7 ms simulated
+    big = fd.make_request("gemm", F2, FAKE, FAKE, FAKE, m=4096, n=4096, k=4096)  # ~3 ms simulated
     srv = fd.Server(fake_device=True, hbm_budget=big.footprint or 3 * 4096 * 4096 * 8,
                     max_inflight=1, max_queue=4)
     srv.submit(big)
@@ -109,3 +110,27 @@ def test_replay_honours_arrivals():
     assert (offs + 1e-4 >= arrivals - arrivals[0]).all()
     assert (tm["done_ns"] >= tm["submit_ns"]).all()
     assert tm["submit_ns"].min() >= t0
+
+
+def test_long_requests_run_alone():
+    """A request estimated above exclusive_ns is admitted only once nothing
+    else is in flight, and nothing is admitted while it runs."""
+    heavy = lambda: fd.make_request("gemm", F2, FAKE, FAKE, FAKE, m=2000, n=2000, k=2000)
+    light = lambda: dot(F1, 1000)
+    order = ["l", "l", "l", "h", "l", "l", "h", "h", "l", "l", "l"]
+    srv = fd.Server(fake_device=True, exclusive_ns=100_000, max_inflight=64)
+    ts = [srv.submit(heavy() if k == "h" else light()) for k in order]
+    srv.drain(20000)
+    tm = [srv.poll(t)[1] for t in ts]
+    for i, k in enumerate(order):
+        if k != "h":
+            continue
+        assert tm[i].batch_size == 1
+        assert all(tm[i].admit_ns >= tm[j].done_ns for j in range(i))
+        assert all(tm[j].admit_ns >= tm[i].done_ns for j in range(i + 1, len(order)))
+    # without the rule the light requests behind a long one overlap it
+    srv2 = fd.Server(fake_device=True, max_inflight=64)  # rule off by default
+    ts = [srv2.submit(heavy() if k == "h" else light()) for k in order]
+    srv2.drain(20000)
+    tm = [srv2.poll(t)[1] for t in ts]
+    assert tm[4].admit_ns < tm[3].done_ns
