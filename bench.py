@@ -238,12 +238,25 @@ def extras_config3(fd):
 
 def extras_gemm(fd):
     """fgemm_modp at 8192 x 8192 times 8192 x 4096: p = 251 centred int8 on
-    int8 matrix cores, p = 2^20-3 residues in doubles on FP64 matrix cores."""
+    int8 matrix cores; p = 2^20-3 residues in doubles on the FP64 matrix cores
+    (digit products switched off) and as nine int8 digit products (the
+    default at this size); p = 2^26-5 (doubles) and 2^31-1 (Montgomery) as
+    sixteen digit products; p = 32749 (classical) as four.  A digit path's
+    matrix-core work is D^2 times the product's, which its fraction of peak
+    counts."""
     import synth
     M, K, N = 8192, 8192, 4096
     out = {}
-    for p, rep, dt, lo, peak, label in [(251, "centred", torch.int8, -125, 5000.0, "int8 p=251"),
-                                        (1048573, "fp64", torch.float64, 0, 78.6, "fp64 p=2^20-3")]:
+    for p, rep, dt, lo, peak, label, work, tune in [
+            (251, "centred", torch.int8, -125, 5000.0, "int8 p=251", 1, {}),
+            (1048573, "fp64", torch.float64, 0, 78.6, "fp64 p=2^20-3 FP64 matrix cores", 1,
+             {"gemm.split.disable": 1}),
+            (1048573, "fp64", torch.float64, 0, 5000.0, "fp64 p=2^20-3 digit products", 9, {}),
+            (67108859, "fp64", torch.float64, 0, 5000.0, "fp64 p=2^26-5 digit products", 16, {}),
+            (2147483647, "mont", torch.uint32, 0, 5000.0, "mont p=2^31-1 digit products", 16, {}),
+            (32749, "zpz", torch.uint32, 0, 5000.0, "zpz p=32749 digit products", 4, {})]:
+        for k, v in tune.items():
+            fd.tune_set(k, v)
         F = fd.Field(p, rep)
         A = torch.empty((M, K), dtype=dt, device="cuda")
         B = torch.empty((K, N), dtype=dt, device="cuda")
@@ -253,8 +266,14 @@ def extras_gemm(fd):
         F.gemm(A, B, out=C)
         t = time_events(lambda: F.gemm(A, B, out=C), 3)
         tops = 2.0 * M * N * K / t / 1e12
+        for k in tune:
+            fd.tune_set(k, None)
         out[label] = {"ms": round(t * 1e3, 3), "TOPS": round(tops, 1),
-                      "frac_of_peak": round(tops / peak, 4), "peak_TOPS": peak}
+                      "frac_of_peak": round(work * tops / peak, 4), "peak_TOPS": peak}
+        if dt == torch.uint32 or "digit" in label:
+            del A, B, C
+            torch.cuda.empty_cache()
+            continue
         # The vendor library's plain product of the same operands (int8 with
         # int32 output, or doubles), timed only as the achievable rate of the
         # matrix cores at this shape; it is not exact modular arithmetic.

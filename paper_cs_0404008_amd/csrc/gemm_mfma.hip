@@ -864,15 +864,24 @@ uint64_t lambda_carried(uint64_t limit, uint64_t h, uint64_t carry) {
 }
 
 // ------------------------------------------------- large primes on int8 cores
-// A residue below p < 2^32 is centred (|c| <= (p-1)/2) and written with four
+// A residue below p < 2^32 is centred (|c| <= (p-1)/2) and written with D <= 4
 // balanced base-256 digits in [-128, 127]: c = d0 + 256 d1 + 2^16 d2 + 2^24 d3,
-// which covers |c| <= 2139062143.  Then A B = sum over digit pairs (i, j) of
-// 256^(i+j) A_i B_j, sixteen exact int8 products with int32 accumulation
-// (|d d'| <= 2^14, so up to 131071 terms need no fold), each reduced mod p
-// and added with its weight 256^(i+j) mod p (times B^-1 for Montgomery
-// residues, whose products carry B^2) -- the operand-splitting counterpart of
-// the delayed reduction of Sec. 3.1 on matrix cores.
+// four of which cover |c| <= 2139062143.  Then A B = sum over digit pairs
+// (i, j) of 256^(i+j) A_i B_j, D^2 exact int8 products with int32
+// accumulation (|d d'| <= 2^14, so up to 131071 terms need no fold), each
+// reduced mod p and added with its weight 256^(i+j) mod p (times B^-1 for
+// Montgomery residues, whose products carry B^2) -- the operand-splitting
+// counterpart of the delayed reduction of Sec. 3.1 on matrix cores.
 constexpr uint64_t kSplitMaxHalf = 2139062143ull;  // 127 (1 + 2^8 + 2^16 + 2^24)
+
+// Balanced base-256 digits needed for centred residues |c| <= h: D digits
+// in [-128, 127] reach 127 (256^D - 1) / 255.
+int split_digits(uint64_t h) {
+  if (h <= 127ull) return 1;
+  if (h <= 32639ull) return 2;
+  if (h <= 8355711ull) return 3;
+  return 4;
+}
 constexpr uint32_t kSplitMaxK = 131071;            // (2^31 - 1) / 2^14
 
 __device__ __forceinline__ void balanced_digits(uint32_t v, const FieldK& F, int8_t d[4]) {
@@ -886,11 +895,12 @@ __device__ __forceinline__ void balanced_digits(uint32_t v, const FieldK& F, int
   }
 }
 
-// A (M x K residues, row stride lda) to four digit planes, each M x ldk with
-// zeros in columns K .. ldk-1.
-__global__ __launch_bounds__(256) void digits_rows_kernel(const uint32_t* A, uint64_t lda,
+// A (M x K residues, row stride lda; uint32 or integral doubles) to nd
+// digit planes, each M x ldk with zeros in columns K .. ldk-1.
+template <typename E>
+__global__ __launch_bounds__(256) void digits_rows_kernel(const E* A, uint64_t lda,
                                                           uint32_t M, uint32_t K, uint32_t ldk,
-                                                          int8_t* D, const FieldK F) {
+                                                          int8_t* D, int nd, const FieldK F) {
   const uint64_t plane = (uint64_t)M * ldk;
   const uint64_t total = (uint64_t)M * (ldk / 4);
   for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -901,7 +911,7 @@ __global__ __launch_bounds__(256) void digits_rows_kernel(const uint32_t* A, uin
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (k + q < K) {
-        balanced_digits(A[row * lda + k + q], F, d[q]);
+        balanced_digits((uint32_t)A[row * lda + k + q], F, d[q]);
       } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) d[q][i] = 0;
@@ -909,6 +919,7 @@ __global__ __launch_bounds__(256) void digits_rows_kernel(const uint32_t* A, uin
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
+      if (i >= nd) break;  // the digits above nd are zero for |c| <= h
       const uint32_t packed = (uint32_t)(uint8_t)d[0][i] | (uint32_t)(uint8_t)d[1][i] << 8 |
                               (uint32_t)(uint8_t)d[2][i] << 16 | (uint32_t)(uint8_t)d[3][i] << 24;
       *(uint32_t*)(D + i * plane + row * ldk + k) = packed;
@@ -916,16 +927,17 @@ __global__ __launch_bounds__(256) void digits_rows_kernel(const uint32_t* A, uin
   }
 }
 
-// B (K x N residues, row stride ldb) to four digit planes of B^T, each N x
+// B (K x N residues, row stride ldb) to nd digit planes of B^T, each N x
 // ldk (zeros in columns K .. ldk-1), 64 x 64 tiles through LDS.
-__global__ __launch_bounds__(256) void digits_cols_kernel(const uint32_t* B, uint64_t ldb,
+template <typename E>
+__global__ __launch_bounds__(256) void digits_cols_kernel(const E* B, uint64_t ldb,
                                                           uint32_t K, uint32_t N, uint32_t ldk,
-                                                          int8_t* D, const FieldK F) {
+                                                          int8_t* D, int nd, const FieldK F) {
   __shared__ uint32_t t[64][65];
   const uint32_t k0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   for (uint32_t e = threadIdx.x; e < 64 * 64; e += 256) {
     const uint32_t r = e / 64, c = e % 64;  // r: k, c: n
-    t[r][c] = (k0 + r < K && n0 + c < N) ? B[(uint64_t)(k0 + r) * ldb + n0 + c] : 0u;
+    t[r][c] = (k0 + r < K && n0 + c < N) ? (uint32_t)B[(uint64_t)(k0 + r) * ldb + n0 + c] : 0u;
   }
   __syncthreads();
   const uint64_t plane = (uint64_t)N * ldk;
@@ -936,6 +948,7 @@ __global__ __launch_bounds__(256) void digits_cols_kernel(const uint32_t* B, uin
   for (int q = 0; q < 16; ++q) balanced_digits(t[c + q][r], F, d[q]);  // zero residue: zero digits
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
+    if (i >= nd) break;
     int8_t row[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) row[q] = d[q][i];
@@ -954,31 +967,59 @@ __global__ __launch_bounds__(256) void zero_rows_kernel(uint32_t* C, uint64_t ld
     C[(e / N) * ldc + e % N] = 0u;
 }
 
+// C (M x N integral doubles, row stride ldc) = Cu (M x N residues, dense).
+__global__ __launch_bounds__(256) void residues_to_f64_kernel(const uint32_t* Cu, uint32_t M,
+                                                              uint32_t N, double* C, uint64_t ldc) {
+  const uint64_t total = (uint64_t)M * N;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * blockDim.x)
+    C[(e / N) * ldc + e % N] = (double)Cu[e];
+}
+
 fdot_status_t gemm_split(const fdot_field_s* f, size_t M, size_t N, size_t K, const void* A,
                          size_t lda, const void* B, size_t ldb, void* C, size_t ldc,
                          hipStream_t s) {
   const fdot_field_info_t& I = f->info;
+  const bool f64 = I.rep == FDOT_REP_FP64;  // doubles in and out; residues summed in scratch
   const uint32_t ldk = (uint32_t)((K + 63) / 64 * 64);
-  const size_t bytes = (size_t)4 * ((size_t)M + N) * ldk + 256;
+  const int nd = split_digits((I.p - 1) / 2);
+  const size_t planes = (size_t)nd * ((size_t)M + N) * ldk + 256;
+  const size_t bytes = planes + (f64 ? (size_t)4 * M * N : 0);
   void* scr = nullptr;
   fdot_status_t st = scratch_for(s, bytes, &scr);
   if (st != FDOT_OK) return st;
   int8_t* Ad = (int8_t*)scr;
-  int8_t* Bd = Ad + (size_t)4 * M * ldk;
+  int8_t* Bd = Ad + (size_t)nd * M * ldk;
+  void* Cf = C;
+  const size_t ldcf = ldc;
+  if (f64) {
+    C = (char*)scr + planes;
+    ldc = N;
+  }
   const uint64_t cells = (uint64_t)M * N;
   const unsigned zg = (unsigned)std::min<uint64_t>((cells + 255) / 256, 65536);
   hipLaunchKernelGGL(zero_rows_kernel, dim3(zg), dim3(256), 0, s, (uint32_t*)C, (uint64_t)ldc,
                      (uint32_t)M, (uint32_t)N);
   const uint64_t ag = std::min<uint64_t>(((uint64_t)M * (ldk / 4) + 255) / 256, 65536);
-  hipLaunchKernelGGL(digits_rows_kernel, dim3((unsigned)ag), dim3(256), 0, s, (const uint32_t*)A,
-                     (uint64_t)lda, (uint32_t)M, (uint32_t)K, ldk, Ad, f->k);
-  hipLaunchKernelGGL(digits_cols_kernel, dim3((unsigned)((N + 63) / 64), (unsigned)(ldk / 64)),
-                     dim3(256), 0, s, (const uint32_t*)B, (uint64_t)ldb, (uint32_t)K, (uint32_t)N,
-                     ldk, Bd, f->k);
+  const dim3 cg((unsigned)((N + 63) / 64), (unsigned)(ldk / 64));
+  if (f64) {
+    hipLaunchKernelGGL(digits_rows_kernel<double>, dim3((unsigned)ag), dim3(256), 0, s,
+                       (const double*)A, (uint64_t)lda, (uint32_t)M, (uint32_t)K, ldk, Ad, nd, f->k);
+    hipLaunchKernelGGL(digits_cols_kernel<double>, cg, dim3(256), 0, s, (const double*)B,
+                       (uint64_t)ldb, (uint32_t)K, (uint32_t)N, ldk, Bd, nd, f->k);
+  } else {
+    hipLaunchKernelGGL(digits_rows_kernel<uint32_t>, dim3((unsigned)ag), dim3(256), 0, s,
+                       (const uint32_t*)A, (uint64_t)lda, (uint32_t)M, (uint32_t)K, ldk, Ad, nd, f->k);
+    hipLaunchKernelGGL(digits_cols_kernel<uint32_t>, cg, dim3(256), 0, s, (const uint32_t*)B,
+                       (uint64_t)ldb, (uint32_t)K, (uint32_t)N, ldk, Bd, nd, f->k);
+  }
   if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
   const unsigned __int128 p = I.p;
   uint64_t base = I.rep == FDOT_REP_MONT_U32 ? I.binv_mod_p : 1;  // Montgomery: one factor B^-1
-  const bool big = M >= 256 && N >= 256 && fd_tune("gemm.split.small", 0) == 0;
+  // 256 x 256 direct-to-LDS tiles once they fill half the chip, else 128 x 128
+  const int64_t small = fd_tune("gemm.split.small", -1);
+  const bool big = M >= 256 && N >= 256 &&
+                   (small == 0 || (small < 0 && ((M + 255) / 256) * ((N + 255) / 256) >= 128));
   const size_t lds = (size_t)4 * (256 + 256) * 64;
   if (big) {
     static bool attr_set = false;
@@ -988,12 +1029,12 @@ fdot_status_t gemm_split(const fdot_field_s* f, size_t M, size_t N, size_t K, co
       attr_set = true;
     }
   }
-  for (int e = 0; e <= 6; ++e) {
+  for (int e = 0; e <= 2 * nd - 2; ++e) {
     // 256^e (B^-1) mod p with its precomputed quotient for the epilogue
     const uint64_t w = base | ((uint64_t)(((unsigned __int128)base << 32) / p) << 32);
-    for (int i = 0; i <= 3; ++i) {
+    for (int i = 0; i < nd; ++i) {
       const int j = e - i;
-      if (j < 0 || j > 3) continue;
+      if (j < 0 || j >= nd) continue;
       const int8_t* Ai = Ad + (size_t)i * M * ldk;
       const int8_t* Bj = Bd + (size_t)j * N * ldk;
       if (big) {
@@ -1011,6 +1052,11 @@ fdot_status_t gemm_split(const fdot_field_s* f, size_t M, size_t N, size_t K, co
       if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
     }
     base = (uint64_t)(((unsigned __int128)base * 256u) % p);
+  }
+  if (f64) {
+    hipLaunchKernelGGL(residues_to_f64_kernel, dim3(zg), dim3(256), 0, s, (const uint32_t*)C,
+                       (uint32_t)M, (uint32_t)N, (double*)Cf, (uint64_t)ldcf);
+    if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
   }
   return FDOT_OK;
 }
@@ -1150,15 +1196,26 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
     centre = true;
     lam = lam_centre;
   }
-  if (lam < 4) {
-    // larger primes: digit products on the int8 matrix cores
-    if ((I.rep == FDOT_REP_ZPZ_U32 || I.rep == FDOT_REP_MONT_U32) && h <= kSplitMaxHalf &&
-        K >= 1 && K <= kSplitMaxK - 63 && M > 0 && N > 0 && fd_tune("gemm.split.disable", 0) == 0) {
-      *handled = true;
-      return gemm_split(f, M, N, K, A, lda, B, ldb, C, ldc, s);
-    }
-    return FDOT_E_UNSUPPORTED;
+  // Digit products on the int8 matrix cores: the only matrix-core path for
+  // larger primes (lambda < 4), and faster than the FP64 matrix cores for
+  // every prime once the product is large enough to amortise its D^2
+  // launches (D = 2, 3 or 4 digits by the size of p; tune key
+  // gemm.split.min_work, in M*N*K; gemm.split.disable keeps the FP64 path).
+  const bool split_ok = h <= kSplitMaxHalf && K >= 1 && K <= kSplitMaxK - 63 && M > 0 && N > 0 &&
+                        fd_tune("gemm.split.disable", 0) == 0;
+  // Crossovers measured at square shapes: two digits (4 products) beat the
+  // FP64 cores from about 512^3, four digits (16 products, against FP64
+  // products folded every few terms) from about 1300^3, three digits (9
+  // products, against unfolded FP64 products) from about 2600^3.
+  const int nd = split_digits(h);
+  const int64_t min_work = nd <= 2 ? (1ll << 27) : nd == 3 ? (1ll << 34) : (1ll << 31);
+  const bool split_wins = (double)M * (double)N * (double)K >=
+                          (double)fd_tune("gemm.split.min_work", min_work);
+  if (split_ok && (lam < 4 || split_wins)) {
+    *handled = true;
+    return gemm_split(f, M, N, K, A, lda, B, ldb, C, ldc, s);
   }
+  if (lam < 4) return FDOT_E_UNSUPPORTED;
   *handled = true;
   const uint64_t tiles = ((M + FM - 1) / FM) * ((N + FN - 1) / FN);
   if (tiles > 0x7FFFFFFFull) return FDOT_E_INVALID_ARG;

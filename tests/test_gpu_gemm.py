@@ -106,10 +106,30 @@ def test_gemm_special_cases():
     assert not Z.any()
 
 
-@pytest.mark.parametrize("p,rep,dtype", [(251, "centred", torch.int8),
-                                         (1048573, "fp64", torch.float64)])
-def test_gemm_full_size_sampled(p, rep, dtype):
-    """The 8192 x 8192 times 8192 x 4096 product, checked on 4096 entries."""
+def _matvec_mod(X, v, p):
+    """X v mod p, exact in int64 for |X| < 2^27 and K <= 8192: v is split
+    into 13-bit halves so that no partial sum passes 2^53."""
+    lo = (X @ (v & 8191)) % p
+    hi = (X @ (v >> 13)) % p
+    return (lo + hi * 8192) % p
+
+
+@pytest.mark.parametrize("p,rep,dtype,path", [(251, "centred", torch.int8, "int8"),
+                                              (1048573, "fp64", torch.float64, "fp64"),
+                                              (1048573, "fp64", torch.float64, "digits"),
+                                              (67108859, "fp64", torch.float64, "digits")])
+def test_gemm_full_size_sampled(p, rep, dtype, path):
+    """The 8192 x 8192 times 8192 x 4096 product, checked on 4096 entries
+    and by Freivalds' test, on the FP64 matrix cores and on the int8 digit
+    products (the default at this size for both primes)."""
+    fd.tune_set("gemm.split.disable", 1 if path == "fp64" else None)
+    try:
+        _full_size_case(p, rep, dtype)
+    finally:
+        fd.tune_set("gemm.split.disable", None)
+
+
+def _full_size_case(p, rep, dtype):
     M, K, N = 8192, 8192, 4096
     F = field(p, rep)
     m, lo = (p, 0) if rep != "centred" else (p, -((p - 1) // 2))
@@ -131,12 +151,12 @@ def test_gemm_full_size_sampled(p, rep, dtype):
     want = oracle.gemm_entries(p, rep, Ah, Bh, rows, cols)
     assert same(C[rows, cols], want)
     # Freivalds: A (B r) = C r mod p for random r; a wrong C passes one trial
-    # with probability at most 1/p.  Exact in int64: |sums| < 8192 * p^2 < 2^54.
+    # with probability at most 1/p.
     Ai, Bi, Ci = (v.astype(np.int64) for v in (Ah, Bh, C))
     for t in range(8):
         r = synth.uniform_int(4, 10 + t, N, p).astype(np.int64)
-        lhs = (Ai @ ((Bi @ r) % p)) % p
-        rhs = (Ci @ r) % p
+        lhs = _matvec_mod(Ai, _matvec_mod(Bi, r, p), p)
+        rhs = _matvec_mod(Ci, r, p)
         assert np.array_equal(lhs, rhs), t
 
 
@@ -226,14 +246,29 @@ def test_gemm_fp64_wave_layouts(waves):
 
 
 @pytest.mark.parametrize("p,rep", [(2147483647, "zpz"), (2147483647, "mont"), (4278124237, "zpz"),
-                                   (2654435761, "mont")])
-@pytest.mark.parametrize("M,N,K", [(300, 260, 700), (1030, 1100, 1000), (40, 36, 131008)])
-def test_gemm_digit_split(p, rep, M, N, K):
-    """Large primes on the int8 matrix cores through sixteen digit products:
-    ragged shapes, K not a multiple of 64, the largest K without folds, the
-    large-tile kernel (M, N >= 256) and the small one; sampled entries against
-    the oracle, maximal products included."""
+                                   (2654435761, "mont"), (67108859, "fp64"), (67108859, "zpz"),
+                                   (67108859, "mont"), (1048573, "fp64"), (65521, "zpz"),
+                                   (32749, "mont"), (32749, "zpz"), (251, "zpz")])
+@pytest.mark.parametrize("M,N,K,tiles", [(300, 260, 700, "auto"), (1030, 1100, 1000, "auto"),
+                                         (1030, 1100, 1000, "large"), (40, 36, 131008, "auto")])
+def test_gemm_digit_split(p, rep, M, N, K, tiles):
+    """Primes on the int8 matrix cores through D^2 digit products, D = 4, 3,
+    2 and 1 balanced base-256 digits by the size of p (the size threshold is
+    lowered so that every shape here takes them): ragged shapes, K not a
+    multiple of 64, the largest K without folds, the large-tile kernel and
+    the small one; sampled entries against the oracle, maximal products
+    included."""
     F = field(p, rep)
+    fd.tune_set("gemm.split.min_work", 1)
+    fd.tune_set("gemm.split.small", 0 if tiles == "large" else None)
+    try:
+        _digit_split_case(F, p, rep, M, N, K)
+    finally:
+        fd.tune_set("gemm.split.min_work", None)
+        fd.tune_set("gemm.split.small", None)
+
+
+def _digit_split_case(F, p, rep, M, N, K):
     for pattern in ("random", "maxprod"):
         A = mat(p, rep, M, K, 73, 0, pattern)
         B = mat(p, rep, K, N, 73, 1, pattern)

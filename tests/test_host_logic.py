@@ -124,3 +124,39 @@ def test_tune_table_roundtrip():
     assert fd.tune_get("no.such.key") is None
     fd.tune_set("test.key", 1234)
     assert fd.tune_get("test.key") == 1234
+
+
+def _balanced_digits(c, ndig):
+    """Balanced base-256 digits in [-128, 127], lowest first, and what is
+    left after ndig of them (zero when ndig digits represent c)."""
+    out = []
+    for _ in range(ndig):
+        t = c & 255
+        if t >= 128:
+            t -= 256
+        out.append(t)
+        c = (c - t) // 256
+    return out, c
+
+
+@pytest.mark.parametrize("ndig", [1, 2, 3, 4])
+def test_balanced_digit_ranges(ndig):
+    """The digit-product matrix path writes a centred residue |c| <= h with
+    ndig balanced base-256 digits when h <= 127 (256^ndig - 1) / 255 (127,
+    32639, 8355711, 2139062143): every such c is represented exactly, the
+    next value up is not, and the digit range keeps each product within
+    2^14 so that 131071 of them fit in int32."""
+    top = 127 * (256 ** ndig - 1) // 255
+    assert top == [127, 32639, 8355711, 2139062143][ndig - 1]
+    rng = random.Random(ndig)
+    for c in [0, 1, -1, top, -top, -top - 1] + [rng.randint(-top, top) for _ in range(2000)]:
+        d, rest = _balanced_digits(c, ndig)
+        assert rest == 0 and all(-128 <= x <= 127 for x in d)
+        assert sum(x * 256 ** i for i, x in enumerate(d)) == c
+    assert _balanced_digits(top + 1, ndig)[1] != 0
+    assert 131071 * 128 * 128 <= 2 ** 31 - 1
+    # the primes of the workloads and the digits they take
+    for p, want in [(251, 1), (32749, 2), (65521, 3), (1048573, 3), (67108859, 4),
+                    (2147483647, 4), (4278124237, 4)]:
+        h = (p - 1) // 2
+        assert min(k for k in (1, 2, 3, 4) if h <= 127 * (256 ** k - 1) // 255) == want
