@@ -349,9 +349,15 @@ def served_workload(fd, n_req, seed=5):
     return fields, pools, reqs, outs
 
 
-def extras_served(fd, n_req=400):
-    """Served stream vs one launch per request at the same Poisson load.
-    mu = the plain path's service rate (all requests at once, one stream)."""
+SERVED_P99_SLO_MS = 5.0
+
+
+def extras_served(fd, n_req=2000):
+    """Served stream vs one launch per request at the same Poisson loads.
+    mu = the plain path's service rate (all requests at once, one stream).
+    The sweep runs 0.2 .. 2 mu; "at_p99_slo" is, for each mode, the highest
+    throughput among the sweep points whose p99 stays within the stated
+    SLO."""
     fields, pools, reqs, outs = served_workload(fd, n_req)
     budget = 64 << 30
 
@@ -368,16 +374,25 @@ def extras_served(fd, n_req=400):
                 "throughput_rps": round(len(reqs) / span, 1)}
 
     run(True, np.zeros(len(reqs)))  # warm-up: workspaces, code objects
+    run(False, np.zeros(len(reqs)))
     burst = run(True, np.zeros(len(reqs)))
     mu = burst["throughput_rps"]
     res = {"requests": n_req, "mu_plain_rps": mu, "hbm_budget_GiB": budget >> 30,
            "mix": "60% dot n~10^U(3,7), 30% matvec n~U(2000,20000), 10% fgemm n~U(512,4096); "
-                  "p uniform over {251, 32749, 65521, 2^26-5, 2^31-1}"}
+                  "p uniform over {251, 32749, 65521, 2^26-5, 2^31-1}",
+           "p99_slo_ms": SERVED_P99_SLO_MS}
     rng = np.random.default_rng(55)
     gaps = rng.exponential(1.0, len(reqs))
-    for load in (0.5, 0.8, 2.0):
+    best = {"plain": None, "served": None}
+    for load in (0.2, 0.5, 0.8, 1.0, 1.2, 2.0):
         arrivals = np.cumsum(gaps) / (load * mu)
-        res[f"load_{load}mu"] = {"plain": run(True, arrivals), "served": run(False, arrivals)}
+        row = {"plain": run(True, arrivals), "served": run(False, arrivals)}
+        res[f"load_{load}mu"] = row
+        for mode, r in row.items():
+            if r["p99_ms"] <= SERVED_P99_SLO_MS and (
+                    best[mode] is None or r["throughput_rps"] > best[mode]["throughput_rps"]):
+                best[mode] = dict(r, load_mu=load)
+    res["at_p99_slo"] = best
     return res
 
 

@@ -49,6 +49,13 @@ int fd_zech_build(uint64_t p, uint32_t g, uint16_t* value, uint16_t* index, uint
 
 // Runtime (runtime.cpp).
 fdot_status_t fd_workspace_get(hipStream_t s, size_t count, Workspace** out);
+// Releases (stream-ordered) the workspace and the matrix scratch of stream s;
+// called before a library-owned stream is destroyed.
+void fd_workspace_release(hipStream_t s);
+void fd_scratch_release(hipStream_t s);
+// Stream-ordered device allocation from the default pool, which keeps freed
+// blocks for reuse.
+hipError_t fd_alloc_async(void** p, size_t bytes, hipStream_t s);
 int64_t fd_tune(const char* key, int64_t fallback);
 int fd_cu_count();
 

@@ -842,17 +842,33 @@ fdot_status_t scratch_for(hipStream_t s, size_t bytes, void** out) {
     return FDOT_OK;
   }
   if (capturing) return FDOT_E_BUSY;  // growing allocates
+  // Stream-ordered allocation and release: the old buffer is freed after the
+  // work already queued on s, and the host never waits for the device.
+  // Growth is geometric, so a stream of rising sizes reallocates rarely.
+  bytes = std::max(bytes, e.second + e.second / 2);
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return FDOT_E_NOMEM;
-  if (e.first) {
-    hipStreamSynchronize(s);
-    // a buffer that a captured graph holds stays allocated until the process ends
-    if (!g_scratch_captured.count(e.first)) hipFree(e.first);
-  }
+  if (fd_alloc_async(&p, bytes, s) != hipSuccess) return FDOT_E_NOMEM;
+  // a buffer that a captured graph holds stays allocated until the process ends
+  if (e.first && !g_scratch_captured.count(e.first)) (void)hipFreeAsync(e.first, s);
   e = std::make_pair(p, bytes);
   *out = p;
   return FDOT_OK;
 }
+
+}  // namespace
+
+void fd_scratch_release(hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  std::lock_guard<std::mutex> g(g_mu);
+  auto it = g_scratch.find(std::make_pair(dev, s));
+  if (it == g_scratch.end()) return;
+  if (it->second.first && !g_scratch_captured.count(it->second.first))
+    (void)hipFreeAsync(it->second.first, s);
+  g_scratch.erase(it);
+}
+
+namespace {
 
 // Largest lambda with carry + lambda*h^2 <= limit (h = largest |term|).
 uint64_t lambda_carried(uint64_t limit, uint64_t h, uint64_t carry) {

@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -69,6 +70,39 @@ int fd_cu_count() {
   return cached[dev];
 }
 
+hipError_t fd_alloc_async(void** p, size_t bytes, hipStream_t s) {
+  // Freed blocks stay in the device's default pool for the next growth
+  // instead of going back to the driver at every synchronisation.
+  static bool pool_set[64] = {false};
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64 && !pool_set[dev]) {
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t keep = ~0ull;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    pool_set[dev] = true;
+  }
+  return hipMallocAsync(p, bytes, s);
+}
+
+void fd_workspace_release(hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  std::lock_guard<std::mutex> g(g_ws_mu);
+  auto it = g_ws.find(std::make_pair(dev, s));
+  if (it == g_ws.end()) return;
+  Workspace* w = it->second;
+  if (w) {
+    if (w->captured)
+      g_ws_retired.push_back(w->base);
+    else
+      (void)hipFreeAsync(w->base, s);
+    delete w;
+  }
+  g_ws.erase(it);
+}
+
 fdot_status_t fd_workspace_get(hipStream_t s, size_t count, Workspace** out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return FDOT_E_DEVICE;
@@ -87,21 +121,21 @@ fdot_status_t fd_workspace_get(hipStream_t s, size_t count, Workspace** out) {
   // Growing allocates, which a stream under graph capture cannot do.
   if (capturing) return FDOT_E_BUSY;
   size_t cap = count < 4096 ? 4096 : count;
+  if (w) cap = std::max(cap, w->cap + w->cap / 2);  // geometric growth
   const size_t bytes_acc = cap * 8, bytes_first = cap * 8, bytes_units = (cap * 4 + 7) / 8 * 8,
                bytes_start = (size_t)kMaxRanges * 4;
   const size_t bytes = bytes_acc + bytes_first + bytes_units + bytes_start + 64;
   void* base = nullptr;
-  if (hipMalloc(&base, bytes) != hipSuccess) return FDOT_E_NOMEM;
+  if (fd_alloc_async(&base, bytes, s) != hipSuccess) return FDOT_E_NOMEM;
   if (fd_launch_zero(base, bytes, s) != FDOT_OK) {
-    hipFree(base);
+    (void)hipFreeAsync(base, s);
     return FDOT_E_DEVICE;
   }
-  if (w) {  // the old buffer may still be in use by work queued on s
-    hipStreamSynchronize(s);
+  if (w) {  // freed in stream order, after the work already queued on s
     if (w->captured)
       g_ws_retired.push_back(w->base);  // kept until the process ends
     else
-      hipFree(w->base);
+      (void)hipFreeAsync(w->base, s);
     w->captured = false;
   } else {
     w = new Workspace;

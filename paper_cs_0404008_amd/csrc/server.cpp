@@ -6,14 +6,15 @@
 //      done: footprint and slots are released),
 //   2. admits waiting requests in arrival order while an in-flight slot and
 //      enough of the HBM budget are free (a request that does not fit blocks
-//      the ones behind it, so admission never reorders arrivals); a request
-//      estimated to take longer than exclusive_ns runs alone, so that overlap
-//      never stretches the longest requests, which set the tail latency,
+//      the ones behind it, so admission never reorders arrivals); optionally
+//      a request estimated to take longer than exclusive_ns runs alone,
 //   3. launches everything admitted: the dot requests of one field are fused
 //      into one batched launch (descriptors staged through pinned memory,
 //      results scattered back to each request's output), matrix-vector and
-//      matrix products are launched one by one; launches rotate over the
-//      server's streams so that their work overlaps on the device.
+//      matrix products are launched one by one.  Matrix products, bound by
+//      the matrix cores, go in arrival order to one stream, so two of them
+//      never share the chip; the HBM-bound requests go to the least-loaded
+//      of the other streams (by estimated outstanding work) and overlap them.
 // Requests that arrive while others run are therefore taken into the next
 // launch as soon as capacity frees up.  In "plain" mode every request is one
 // launch on one stream in arrival order: the baseline that serving is
@@ -64,6 +65,8 @@ struct Launch {
   std::vector<uint64_t> tickets;
   hipEvent_t ev = nullptr;
   int slot = -1;
+  int stream = 0;     // index of the stream it was issued on
+  uint64_t est = 0;   // estimated device time, counted in that stream's load
   uint64_t fake_done = 0;
   int32_t status = FDOT_OK;
 };
@@ -82,24 +85,28 @@ uint64_t footprint_of(const fdot_request_t& r) {
 // Simulated device time of a request (fake-device mode only).
 // Estimated device time of a request: streaming forms at HBM speed, matrix
 // products at the rate of the path they take (int8 cores for centred int8
-// residues, FP64 cores for fp64 and small classical primes, digit products
-// on the int8 cores for larger primes).  Used for the simulated device and
-// for the exclusive rule; only its order of magnitude matters.
+// residues; D^2 int8 digit products, D = 1..4 by the size of p, for the
+// other residues up to 4278124237; the vector-ALU kernel beyond).  Used to
+// pick the least-loaded stream, for the exclusive rule and for the simulated
+// device; only its order of magnitude matters.
 uint64_t est_ns(const fdot_request_t& r) {
   const fdot_field_info_t& I = r.field->info;
   const double e = (double)I.elem_bytes;
   double s = 5e-6;
   switch (r.op) {
-    case FDOT_OP_DOT: s += 2.0 * r.n * e / 6e12; break;
-    case FDOT_OP_GEMV: s += (double)r.m * r.n * e / 6e12; break;
+    case FDOT_OP_DOT: s += 2.0 * r.n * e / 5e12; break;
+    case FDOT_OP_GEMV: s += (double)r.m * r.n * e / 5e12; break;
     case FDOT_OP_GEMM: {
-      double rate = 1e13;  // exact vector-ALU kernel
-      if (I.rep == FDOT_REP_CENTRED_I8)
-        rate = 1.5e15;
-      else if (I.rep == FDOT_REP_FP64 || I.lambda_f64 >= 4 ||
-               ((I.rep == FDOT_REP_ZPZ_U32 || I.rep == FDOT_REP_MONT_U32) && I.p <= 4278124237ull))
-        rate = 5e13;  // FP64 cores, or int8 digit products for larger primes
-      s += 2.0 * r.m * r.n * r.k / rate;
+      const double ops = 2.0 * r.m * r.n * r.k;
+      const uint64_t h = (I.p - 1) / 2;
+      if (I.rep == FDOT_REP_CENTRED_I8) {
+        s += ops / 1.5e15;
+      } else if (I.rep != FDOT_REP_ZECH_U16 && I.p <= 4278124237ull) {
+        const double d = h <= 127 ? 1 : h <= 32639 ? 2 : h <= 8355711 ? 3 : 4;
+        s += d * d * (10e-6 + ops / 1.6e15);
+      } else {
+        s += ops / 1e13;
+      }
       break;
     }
   }
@@ -130,11 +137,20 @@ struct fdot_server_s {
   std::vector<Slot> slots;
   size_t slot_bytes = 0;
   uint32_t rr = 0;
+  std::vector<uint64_t> load;  // per stream: estimated ns of work issued and not done
   fdot_server_stats_t st;
 
-  hipStream_t next_stream() {
-    if (cfg.plain) return streams[0];
-    return streams[(rr++) % streams.size()];
+  // Matrix products (bound by the matrix cores) run in arrival order on
+  // stream 0, so two of them never share the chip and stretch each other;
+  // streaming requests (bound by HBM) take the least-loaded of the other
+  // streams and overlap the products.  Plain: everything on the one stream.
+  int pick_stream(const fdot_request_t& r) {
+    if (cfg.plain || streams.size() == 1) return 0;
+    if (r.op == FDOT_OP_GEMM) return 0;
+    int best = 1 + (int)(rr++ % (streams.size() - 1));
+    for (size_t i = 1; i < streams.size(); ++i)
+      if (load[i] < load[best]) best = (int)i;
+    return best;
   }
 
   hipEvent_t get_event() {
@@ -196,12 +212,16 @@ struct fdot_server_s {
     }
     if (L.ev) free_events.push_back(L.ev);
     if (L.slot >= 0) slots[L.slot].busy = false;
+    load[L.stream] -= L.est;
   }
 
-  void issue(std::vector<uint64_t> tickets, hipStream_t s, fdot_status_t stt, int slot) {
+  void issue(std::vector<uint64_t> tickets, int si, uint64_t est, fdot_status_t stt, int slot) {
+    hipStream_t s = streams[si];
     Launch L;
     L.tickets = std::move(tickets);
     L.slot = slot;
+    L.stream = si;
+    L.est = est;
     L.status = stt;
     const uint64_t now = now_ns();
     uint64_t dur = 0;
@@ -232,9 +252,11 @@ struct fdot_server_s {
     if (cfg.plain || cfg.fake_device) {
       if (cfg.plain) {
         for (uint64_t tk : todo) {
-          hipStream_t s = next_stream();
-          const fdot_status_t stt = cfg.fake_device ? FDOT_OK : launch_one(reqs[tk], s);
-          issue({tk}, s, stt, -1);
+          const int si = pick_stream(reqs[tk].r);
+          const uint64_t est = est_ns(reqs[tk].r);
+          load[si] += est;
+          const fdot_status_t stt = cfg.fake_device ? FDOT_OK : launch_one(reqs[tk], streams[si]);
+          issue({tk}, si, est, stt, -1);
         }
         return;
       }
@@ -246,9 +268,11 @@ struct fdot_server_s {
       if (q.r.op == FDOT_OP_DOT) {
         dots[q.r.field].push_back(tk);
       } else {
-        hipStream_t s = next_stream();
-        const fdot_status_t stt = cfg.fake_device ? FDOT_OK : launch_one(q, s);
-        issue({tk}, s, stt, -1);
+        const int si = pick_stream(q.r);
+        const uint64_t est = est_ns(q.r);
+        load[si] += est;
+        const fdot_status_t stt = cfg.fake_device ? FDOT_OK : launch_one(q, streams[si]);
+        issue({tk}, si, est, stt, -1);
       }
     }
     for (auto& kv : dots) {
@@ -256,18 +280,22 @@ struct fdot_server_s {
       for (size_t b = 0; b < v.size(); b += cfg.max_batch) {
         const size_t e = std::min(v.size(), b + (size_t)cfg.max_batch);
         std::vector<uint64_t> group(v.begin() + b, v.begin() + e);
-        hipStream_t s = next_stream();
+        const int si = pick_stream(reqs[group[0]].r);
+        hipStream_t s = streams[si];
+        uint64_t est = 0;
+        for (uint64_t tk : group) est += est_ns(reqs[tk].r);
+        load[si] += est;
         if (cfg.fake_device) {
-          issue(group, s, FDOT_OK, -1);
+          issue(group, si, est, FDOT_OK, -1);
           continue;
         }
         if (group.size() == 1) {
-          issue(group, s, launch_one(reqs[group[0]], s), -1);
+          issue(group, si, est, launch_one(reqs[group[0]], s), -1);
           continue;
         }
         const int slot = get_slot();
         if (slot < 0) {  // no staging buffer free: launch these one by one
-          for (uint64_t tk : group) issue({tk}, s, launch_one(reqs[tk], s), -1);
+          for (uint64_t tk : group) issue({tk}, si, est_ns(reqs[tk].r), launch_one(reqs[tk], s), -1);
           continue;
         }
         const size_t n = group.size();
@@ -293,7 +321,7 @@ struct fdot_server_s {
         if (stt == FDOT_OK)
           stt = fd_launch_scatter(results, (void* const*)(d + n * sizeof(fdot_desc_t)), n,
                                   kv.first->info.elem_bytes, s);
-        issue(group, s, stt, slot);
+        issue(group, si, est, stt, slot);
       }
     }
   }
@@ -409,6 +437,18 @@ fdot_status_t fdot_server_create(const fdot_server_cfg_t* cfg, fdot_server_t* ou
   } else {
     s->streams.assign(c.plain ? 1 : c.streams, nullptr);
   }
+  s->load.assign(s->streams.size(), 0);
+  if (!c.fake_device) {
+    // pinned descriptor slots for the first batches, so that the measured
+    // stream does not pay for pinned allocations
+    std::vector<int> pre;
+    for (uint32_t i = 0; i < std::min<uint32_t>(64, 2 * (uint32_t)s->streams.size()); ++i) {
+      const int k = s->get_slot();
+      if (k < 0) break;
+      pre.push_back(k);
+    }
+    for (int k : pre) s->slots[k].busy = false;
+  }
   s->thread = std::thread([s] { s->run(); });
   *out = s;
   return FDOT_OK;
@@ -513,6 +553,8 @@ fdot_status_t fdot_server_destroy(fdot_server_t s) {
   s->thread.join();
   if (!s->cfg.fake_device) {
     for (hipStream_t x : s->streams) {
+      fd_workspace_release(x);
+      fd_scratch_release(x);
       hipStreamSynchronize(x);
       hipStreamDestroy(x);
     }

@@ -82,7 +82,7 @@ def test_batching_and_plain_mode():
 
 
 def test_back_pressure_and_rejection():
-    big = fd.make_request("gemm", F2, FAKE, FAKE, FAKE, m=4096, n=4096, k=4096)  # ~3 ms simulated
+    big = fd.make_request("gemm", F2, FAKE, FAKE, FAKE, m=4096, n=4096, k=4096)  # ~1.5 ms simulated
     srv = fd.Server(fake_device=True, hbm_budget=big.footprint or 3 * 4096 * 4096 * 8,
                     max_inflight=1, max_queue=4)
     srv.submit(big)
