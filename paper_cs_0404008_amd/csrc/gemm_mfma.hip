@@ -911,13 +911,13 @@ __device__ __forceinline__ void balanced_digits(uint32_t v, const FieldK& F, int
   }
 }
 
-// A (M x K residues, row stride lda; uint32 or integral doubles) to nd
-// digit planes, each M x ldk with zeros in columns K .. ldk-1.
+// A (M x K residues, row stride lda; uint32 or integral doubles) to its nd
+// digits: row r of the result is digit 0 of row r of A, then digit 1, ...,
+// each ldk long with zeros in columns K .. ldk-1.
 template <typename E>
 __global__ __launch_bounds__(256) void digits_rows_kernel(const E* A, uint64_t lda,
                                                           uint32_t M, uint32_t K, uint32_t ldk,
                                                           int8_t* D, int nd, const FieldK F) {
-  const uint64_t plane = (uint64_t)M * ldk;
   const uint64_t total = (uint64_t)M * (ldk / 4);
   for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (uint64_t)gridDim.x * blockDim.x) {
@@ -938,13 +938,16 @@ __global__ __launch_bounds__(256) void digits_rows_kernel(const E* A, uint64_t l
       if (i >= nd) break;  // the digits above nd are zero for |c| <= h
       const uint32_t packed = (uint32_t)(uint8_t)d[0][i] | (uint32_t)(uint8_t)d[1][i] << 8 |
                               (uint32_t)(uint8_t)d[2][i] << 16 | (uint32_t)(uint8_t)d[3][i] << 24;
-      *(uint32_t*)(D + i * plane + row * ldk + k) = packed;
+      *(uint32_t*)(D + row * (nd * (uint64_t)ldk) + i * (uint64_t)ldk + k) = packed;
     }
   }
 }
 
-// B (K x N residues, row stride ldb) to nd digit planes of B^T, each N x
-// ldk (zeros in columns K .. ldk-1), 64 x 64 tiles through LDS.
+// B (K x N residues, row stride ldb) to the digits of B^T: row n of the
+// result is digit nd-1 of column n of B, then digit nd-2, ..., digit 0, each
+// ldk long (zeros in columns K .. ldk-1); 64 x 64 tiles through LDS.  With
+// A's digits in rising and B's in falling order, the pairs (i, e - i) of one
+// weight 256^e sit side by side along k in both.
 template <typename E>
 __global__ __launch_bounds__(256) void digits_cols_kernel(const E* B, uint64_t ldb,
                                                           uint32_t K, uint32_t N, uint32_t ldk,
@@ -956,7 +959,6 @@ __global__ __launch_bounds__(256) void digits_cols_kernel(const E* B, uint64_t l
     t[r][c] = (k0 + r < K && n0 + c < N) ? (uint32_t)B[(uint64_t)(k0 + r) * ldb + n0 + c] : 0u;
   }
   __syncthreads();
-  const uint64_t plane = (uint64_t)N * ldk;
   const uint32_t r = threadIdx.x / 4, c = (threadIdx.x % 4) * 16;  // r: n, c: first k
   if (n0 + r >= N || k0 + c >= ldk) return;
   int8_t d[16][4];
@@ -970,7 +972,7 @@ __global__ __launch_bounds__(256) void digits_cols_kernel(const E* B, uint64_t l
     for (int q = 0; q < 16; ++q) row[q] = d[q][i];
     v4i v;
     __builtin_memcpy(&v, row, 16);
-    *(v4i*)(D + i * plane + (uint64_t)(n0 + r) * ldk + k0 + c) = v;
+    *(v4i*)(D + (uint64_t)(n0 + r) * (nd * (uint64_t)ldk) + (uint64_t)(nd - 1 - i) * ldk + k0 + c) = v;
   }
 }
 
@@ -1045,25 +1047,31 @@ fdot_status_t gemm_split(const fdot_field_s* f, size_t M, size_t N, size_t K, co
       attr_set = true;
     }
   }
+  // One product per weight: the pairs (i, e - i) of weight 256^e are adjacent
+  // along k in both digit layouts, so they form one int8 product of length
+  // (pairs) * ldk, in as few launches as the int32 bound allows (at most
+  // 131071 terms of |d d'| <= 2^14 each): 2D - 1 epilogues instead of D^2.
+  const uint64_t ld_all = (uint64_t)nd * ldk;
+  const int per_launch = (int)std::max<uint64_t>(1, (uint64_t)kSplitMaxK / ldk);
   for (int e = 0; e <= 2 * nd - 2; ++e) {
     // 256^e (B^-1) mod p with its precomputed quotient for the epilogue
     const uint64_t w = base | ((uint64_t)(((unsigned __int128)base << 32) / p) << 32);
-    for (int i = 0; i < nd; ++i) {
-      const int j = e - i;
-      if (j < 0 || j >= nd) continue;
-      const int8_t* Ai = Ad + (size_t)i * M * ldk;
-      const int8_t* Bj = Bd + (size_t)j * N * ldk;
+    const int i_lo = std::max(0, e - nd + 1), i_hi = std::min(e, nd - 1);
+    for (int c = i_lo; c <= i_hi; c += per_launch) {
+      const int cnt = std::min(per_launch, i_hi - c + 1);
+      const int8_t* Ai = Ad + (size_t)c * ldk;                    // digits c .. c+cnt-1 of A
+      const int8_t* Bj = Bd + (size_t)(nd - 1 - (e - c)) * ldk;   // digits e-c .. down of B
+      const uint32_t Kx = (uint32_t)cnt * ldk;
       if (big) {
         const uint64_t tiles = ((M + 255) / 256) * ((N + 255) / 256);
         hipLaunchKernelGGL((gemm_i8_dma_kernel<2, 4, 8, true>), dim3((unsigned)tiles), dim3(512),
-                           lds, s, f->k, (uint32_t)M, (uint32_t)N, ldk, Ai, (uint64_t)ldk, Bj,
-                           (uint64_t)ldk, (int8_t*)nullptr, (uint64_t)ldc, (uint32_t*)C, w);
+                           lds, s, f->k, (uint32_t)M, (uint32_t)N, Kx, Ai, ld_all, Bj, ld_all,
+                           (int8_t*)nullptr, (uint64_t)ldc, (uint32_t*)C, w);
       } else {
         const uint64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
         hipLaunchKernelGGL((gemm_i8_kernel<2, 2, 64, true, true>), dim3((unsigned)tiles),
-                           dim3(256), 0, s, f->k, (uint32_t)M, (uint32_t)N, ldk, Ai,
-                           (uint64_t)ldk, Bj, (uint64_t)ldk, (int8_t*)nullptr, (uint64_t)ldc,
-                           0xFFFFFFFFu, (uint32_t*)C, w);
+                           dim3(256), 0, s, f->k, (uint32_t)M, (uint32_t)N, Kx, Ai, ld_all, Bj,
+                           ld_all, (int8_t*)nullptr, (uint64_t)ldc, 0xFFFFFFFFu, (uint32_t*)C, w);
       }
       if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
     }
