@@ -349,6 +349,25 @@ def served_workload(fd, n_req, seed=5):
     return fields, pools, reqs, outs
 
 
+SWEEP_PRIMES = (251, 4093, 32749, 65521, 1048573, 16777213, 67108859, 2147483647, 4294967291)
+
+
+def extras_prime_sweep(fd):
+    """Throughput against p: the single streaming dot in every
+    representation that admits each prime (largest primes below 2^8, 2^12,
+    2^15, 2^16, 2^20, 2^24, 2^26, 2^31, 2^32), 1 GiB of operands per call, and
+    the representation fdot_choose_rep picks for that prime."""
+    from paper_cs_0404008_amd import autotune
+    rows = autotune.rep_sweep(SWEEP_PRIMES)
+    out = {}
+    for p in SWEEP_PRIMES:
+        out[str(p)] = {"choose_rep": fd.choose_rep(p),
+                       **{r["rep"]: {"gelem_per_s": round(r["gelem_per_s"], 1),
+                                     "GBps": round(r["GBps"], 1), "n": r["n"]}
+                          for r in rows if r["p"] == p}}
+    return out
+
+
 SERVED_P99_SLO_MS = 5.0
 
 
@@ -489,6 +508,9 @@ def main():
         torch.cuda.empty_cache()
         log("extras: served stream ...")
         extras["served_config5"] = extras_served(fd)
+        torch.cuda.empty_cache()
+        log("extras: prime sweep ...")
+        extras["prime_sweep"] = extras_prime_sweep(fd)
         result["extras"] = extras
     print(json.dumps(result), flush=True)
 

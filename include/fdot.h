@@ -168,6 +168,19 @@ fdot_status_t fdot_lambda(uint64_t p, fdot_acc_t acc, uint64_t* lambda);
  * 2.4); bits in [8, 64]. */
 fdot_status_t fdot_max_prime(fdot_bound_t kind, uint32_t bits, uint64_t* p);
 
+/* The representation to hold GF(p) vectors in for dot products of length
+ * about n on this device: the switch between representations by prime size,
+ * vector size and architecture that the Conclusion calls for.  A measured
+ * choice written by the autotuner at install time (tune keys
+ * auto.rep.b<bits>.n<decade>, then auto.rep.b<bits>, bits = bit length of p,
+ * decade = floor(log10 n)) wins when that representation admits p.
+ * Otherwise the model for a device where the streaming dot is bound by HBM
+ * bandwidth: the admissible representation with the fewest bytes per element
+ * (centred int8, then discrete logarithms in 16 bits, then classical 32-bit
+ * residues, then doubles).  Host only; FDOT_E_BOUND if no representation
+ * admits p, FDOT_E_NOT_PRIME if p is not prime. */
+fdot_status_t fdot_choose_rep(uint64_t p, uint64_t n, fdot_rep_t* rep);
+
 /* Evaluate one fold primitive on the host with the field's constants, with
  * the same code the kernels run.  Returns FDOT_E_INVALID_ARG when T is
  * outside the primitive's input range. */

@@ -63,6 +63,7 @@ _sig("fdot_version", [])
 _sig("fdot_field_params", [_u64, _i32, ctypes.POINTER(FieldInfo)])
 _sig("fdot_lambda", [_u64, _i32, ctypes.POINTER(_u64)])
 _sig("fdot_max_prime", [_i32, ctypes.c_uint32, ctypes.POINTER(_u64)])
+_sig("fdot_choose_rep", [_u64, _u64, ctypes.POINTER(_i32)])
 _sig("fdot_host_fold", [ctypes.POINTER(FieldInfo), _i32, _u64, ctypes.POINTER(_u64)])
 _sig("fdot_zech_tables", [_u64, _vp, _vp, _vp])
 _sig("fdot_field_create", [_u64, _i32, ctypes.POINTER(_vp)])
@@ -133,6 +134,15 @@ def max_prime(kind: str, bits: int) -> int:
     out = _u64()
     _check(_lib.fdot_max_prime(BOUNDS[kind], bits, ctypes.byref(out)), "fdot_max_prime")
     return out.value
+
+
+def choose_rep(p: int, n: int = 0) -> str:
+    """The representation for dot products of length about n over GF(p) on
+    this device (fdot_choose_rep): a measured choice from the tuning table,
+    else the admissible one with the fewest bytes per element."""
+    out = ctypes.c_int32()
+    _check(_lib.fdot_choose_rep(p, n, ctypes.byref(out)), "fdot_choose_rep")
+    return {v: k for k, v in REPS.items()}[out.value]
 
 
 def host_fold(p: int, rep: str, kind: str, T: int) -> int:

@@ -21,7 +21,12 @@ What is tuned:
   (Sec. 3.2.1, 3.3, 3.4), value table against Zech addition for discrete
   logarithms (Sec. 2.4);
 * the matrix-core tiling of ``fgemm_modp`` (``gemm.i8.tile``,
-  ``gemm.f64.waves``).
+  ``gemm.f64.waves``);
+* the representation that ``fdot_choose_rep`` returns for each prime size
+  (``auto.rep.b<bits>``): the Conclusion's install-time choice of the
+  switching thresholds between representations, made here by timing the
+  streaming dot in every representation that admits the largest prime of
+  each bit length (``rep_sweep``).
 
 Command line: ``python -m paper_cs_0404008_amd.autotune --out tune.txt``
 tunes on synthetic inputs of the benchmark's shapes (``--small`` for a quick
@@ -37,7 +42,7 @@ import sys
 import numpy as np
 import torch
 
-from . import ALGOS, Field, tune_get, tune_set
+from . import ALGOS, REPS as ALGOS_REP, Field, tune_get, tune_set
 
 REP_KEYS = ("zpz", "mont", "fp64", "zech", "centred")
 
@@ -148,6 +153,77 @@ def tune_gemm(field: Field, A: torch.Tensor, B: torch.Tensor, reps: int = 3):
     return _search(lambda: field.gemm(A, B, out=C), lambda: C.cpu().numpy().copy(), cands, reps)
 
 
+def _is_prime(n: int) -> bool:
+    if n < 2:
+        return False
+    for q in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37):
+        if n % q == 0:
+            return n == q
+    d, r = n - 1, 0
+    while d % 2 == 0:
+        d, r = d // 2, r + 1
+    for a in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37):  # deterministic below 3.3e24
+        x = pow(a, d, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(r - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def largest_prime_below(x: int) -> int:
+    q = x - 1
+    while not _is_prime(q):
+        q -= 1
+    return q
+
+
+def rep_sweep(primes, bytes_per_call: int = 1 << 30, reps: int = 3):
+    """Streaming dot throughput of every representation that admits each
+    prime: rows (p, rep, n, seconds per call, Gelem/s, GB/s).  Each call
+    reads bytes_per_call bytes (n = bytes_per_call / (2 * element size)), so
+    the operands do not stay in the last-level cache between calls."""
+    from synth import fill_device
+    rows = []
+    for p in primes:
+        for rep in REP_KEYS:
+            try:
+                F = Field(p, rep)
+            except Exception:  # the representation does not admit p
+                continue
+            n = bytes_per_call // (2 * F.info["elem_bytes"])
+            m, lo = (p, 0) if rep != "centred" else (p, -((p - 1) // 2))
+            x = torch.empty(n, dtype=F.dtype, device="cuda")
+            y = torch.empty(n, dtype=F.dtype, device="cuda")
+            fill_device(x, 9, 0, m, lo)
+            fill_device(y, 9, 1, m, lo)
+            out = torch.empty(1, dtype=F.dtype, device="cuda")
+            t = _time(lambda: F.dot(x, y, out=out), reps)
+            rows.append({"p": p, "rep": rep, "n": n, "s": t, "gelem_per_s": n / t / 1e9,
+                         "GBps": 2 * n * F.info["elem_bytes"] / t / 1e9})
+            del x, y, out, F
+            torch.cuda.empty_cache()
+    return rows
+
+
+def tune_representation(bits=range(8, 33), bytes_per_call: int = 1 << 30, reps: int = 3):
+    """auto.rep.b<bits> for each bit length: the fastest representation
+    (elements per second) for the largest prime of that length."""
+    primes = [largest_prime_below(1 << b) for b in bits]
+    rows = rep_sweep(primes, bytes_per_call, reps)
+    settings = {}
+    for b, p in zip(bits, primes):
+        mine = [r for r in rows if r["p"] == p]
+        if mine:
+            best = max(mine, key=lambda r: r["gelem_per_s"])
+            settings[f"auto.rep.b{b}"] = ALGOS_REP[best["rep"]]
+    return settings, rows
+
+
 def apply(settings: dict) -> None:
     for k, v in settings.items():
         tune_set(k, v)
@@ -195,6 +271,7 @@ def main(argv=None) -> int:
     ap.add_argument("--out", required=True, help="tuning file to write (key=value lines)")
     ap.add_argument("--small", action="store_true", help="small shapes (quick check)")
     ap.add_argument("--no-gemm", action="store_true")
+    ap.add_argument("--no-rep", action="store_true", help="skip the representation sweep")
     args = ap.parse_args(argv)
     import synth
     torch.cuda.set_device(0)
@@ -233,6 +310,12 @@ def main(argv=None) -> int:
                 f"{c} {t * 1e3:.3f} ms" for c, t in sorted(table, key=lambda x: x[1])))
             del A, B
             torch.cuda.empty_cache()
+    if not args.no_rep:
+        bits = range(8, 33, 4) if args.small else range(8, 33)
+        rsettings, rows = tune_representation(bits, (1 << 26) if args.small else (1 << 30))
+        settings.update(rsettings)
+        for r in rows:
+            log.append(f"rep p={r['p']} {r['rep']}: {r['gelem_per_s']:.1f} Gelem/s")
     write(args.out, settings, "\n".join(log))
     print("\n".join(log))
     print(f"wrote {len(settings)} settings to {args.out}")

@@ -1,6 +1,7 @@
 // Field set-up on the host: primality, representation bounds (Sec. 2), block
 // lengths (Sec. 3.1 Eq. 1 and its variants), reduction constants and the Zech
 // tables (Sec. 2.4).  Nothing here runs per element.
+#include <stdio.h>
 #include <string.h>
 
 #include <new>
@@ -249,6 +250,36 @@ fdot_status_t fdot_max_prime(fdot_bound_t kind, uint32_t bits, uint64_t* out) {
   for (u128 x = lo; x >= 2; --x)
     if (x < ((u128)1 << 64) && fd_is_prime_u64((uint64_t)x)) { *out = (uint64_t)x; return FDOT_OK; }
   return FDOT_E_NOT_FOUND;
+}
+
+fdot_status_t fdot_choose_rep(uint64_t p, uint64_t n, fdot_rep_t* rep) {
+  if (!rep) return FDOT_E_INVALID_ARG;
+  if (p < 2 || !fd_is_prime_u64(p)) return FDOT_E_NOT_PRIME;
+  fdot_field_info_t info;
+  int bits = 0;
+  while (bits < 64 && (p >> bits) != 0) ++bits;
+  int decade = 0;
+  for (uint64_t t = n; t >= 10; t /= 10) ++decade;
+  char key[64];
+  snprintf(key, sizeof key, "auto.rep.b%d.n%d", bits, decade);
+  int64_t tuned = fd_tune(key, -1);
+  if (tuned < 0) {
+    snprintf(key, sizeof key, "auto.rep.b%d", bits);
+    tuned = fd_tune(key, -1);
+  }
+  if (tuned >= FDOT_REP_ZPZ_U32 && tuned <= FDOT_REP_CENTRED_I8 &&
+      fd_fill_params(p, (fdot_rep_t)tuned, &info) == FDOT_OK) {
+    *rep = (fdot_rep_t)tuned;
+    return FDOT_OK;
+  }
+  static const fdot_rep_t by_bytes[] = {FDOT_REP_CENTRED_I8, FDOT_REP_ZECH_U16, FDOT_REP_ZPZ_U32,
+                                        FDOT_REP_FP64};
+  for (fdot_rep_t r : by_bytes)
+    if (fd_fill_params(p, r, &info) == FDOT_OK) {
+      *rep = r;
+      return FDOT_OK;
+    }
+  return FDOT_E_BOUND;
 }
 
 fdot_status_t fdot_host_fold(const fdot_field_info_t* info, fdot_fold_t kind, uint64_t T,

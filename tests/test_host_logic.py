@@ -160,3 +160,31 @@ def test_balanced_digit_ranges(ndig):
                     (2147483647, 4), (4278124237, 4)]:
         h = (p - 1) // 2
         assert min(k for k in (1, 2, 3, 4) if h <= 127 * (256 ** k - 1) // 255) == want
+
+
+def test_choose_rep_model_and_tuned_override():
+    """Representation choice: the fewest bytes per element among the
+    representations that admit p, unless the tuning table holds a measured
+    choice for p's bit length (and n's decade) that admits p."""
+    want = {3: "centred", 251: "centred", 257: "zech", 32749: "zech", 65521: "zech",
+            65537: "zpz", 67108859: "zpz", 2147483647: "zpz", 4294967291: "zpz"}
+    for p, rep in want.items():
+        assert fd.choose_rep(p) == rep, p
+        assert fd.field_params_status(p, rep) == 0
+    with pytest.raises(fd.FdotError):
+        fd.choose_rep(65535)                     # not prime
+    with pytest.raises(fd.FdotError):
+        fd.choose_rep(2 ** 61 - 1)               # no representation admits it
+    try:
+        fd.tune_set("auto.rep.b8", fd.REPS["fp64"])
+        fd.tune_set("auto.rep.b8.n6", fd.REPS["mont"])
+        fd.tune_set("auto.rep.b17", fd.REPS["centred"])  # does not admit 65537
+        assert fd.choose_rep(251) == "fp64"
+        assert fd.choose_rep(251, 10 ** 6) == "mont"
+        assert fd.choose_rep(251, 9 * 10 ** 6) == "mont"
+        assert fd.choose_rep(251, 10 ** 7) == "fp64"
+        assert fd.choose_rep(65537) == "zpz"
+    finally:
+        for k in ("auto.rep.b8", "auto.rep.b8.n6", "auto.rep.b17"):
+            fd.tune_set(k, None)
+    assert fd.choose_rep(251) == "centred"
