@@ -55,6 +55,7 @@ def lib():
         L.orc_gemm.argtypes = [u64, i32, sz, sz, sz, vp, sz, vp, sz, vp, sz]
         L.orc_gemm_entries.argtypes = [u64, i32, sz, vp, sz, vp, sz, sz, vp, vp, vp]
         L.orc_gemv.argtypes = [u64, i32, sz, sz, vp, sz, vp, vp]
+        L.orc_elementwise.argtypes = [u64, i32, i32, sz, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -160,3 +161,21 @@ def gemv(p: int, rep: str, A, x) -> np.ndarray:
     y = np.zeros(m, dtype=DTYPES[rep])
     _check(lib().orc_gemv(p, REPS[rep], m, n, _ptr(A), n, _ptr(x), _ptr(y)), "gemv")
     return y
+
+
+EW_OPS = {"add": 0, "sub": 1, "neg": 2, "mul": 3, "div": 4, "axpy": 5, "axpyin": 6}
+
+
+def elementwise(p: int, rep: str, op: str, x, y=None, alpha=None, r=None) -> np.ndarray:
+    """The elementwise operation op (Sec. 2) on stored values of rep:
+    add/sub/mul/div (x, y), neg (x), axpy (alpha * x + y), axpyin
+    (alpha * x + r); returns a new array."""
+    xa = _arr(x, rep)
+    ya = _arr(y, rep) if y is not None else np.zeros_like(xa)
+    out = _arr(r, rep).copy() if r is not None else np.zeros_like(xa)
+    al = _arr([alpha if alpha is not None else 0], rep)
+    if ya.size != xa.size or out.size != xa.size:
+        raise ValueError("length mismatch")
+    _check(lib().orc_elementwise(p, REPS[rep], EW_OPS[op], xa.size, _ptr(al), _ptr(xa),
+                                 _ptr(ya), _ptr(out)), "elementwise")
+    return out

@@ -351,4 +351,50 @@ int orc_gemv(uint64_t p, int rep, size_t m, size_t n, const void* A, size_t lda,
   return bad ? ORC_E_NONCANON : ORC_OK;
 }
 
+/* ------------------------------------------------- elementwise operations */
+
+/* The seven basic operations of Sec. 2 (opening), on every element i, by
+ * their plain definitions on residues in [0,p):
+ *   0 ADD    r = x + y          1 SUB    r = x - y        2 NEG  r = -x
+ *   3 MUL    r = x * y          4 DIV    r = x * y^-1 (inverse by the
+ *            extended Euclidean algorithm, as Sec. 2.1 does it; y = 0 gives
+ *            the zero element, a convention: the paper leaves it undefined)
+ *   5 AXPY   r = a * x + y      6 AXPYIN r = a * x + r (r read, then written)
+ * each reduced mod p in 128-bit arithmetic, decoded from and encoded to the
+ * representation as for the dot product.  a is one element of the
+ * representation (read for AXPY and AXPYIN only). */
+int orc_elementwise(uint64_t p, int rep, int op, size_t n, const void* a, const void* x,
+                    const void* y, void* r) {
+  if (op < 0 || op > 6) return ORC_E_ARG;
+  orc_field f;
+  int rc = field_init(&f, p, rep);
+  if (rc) { field_free(&f); return rc; }
+  int64_t av = 0;
+  if (op == 5 || op == 6) {
+    av = decode(&f, a, 0);
+    if (av < 0) { field_free(&f); return ORC_E_NONCANON; }
+  }
+  for (size_t i = 0; i < n; ++i) {
+    const int64_t xv = decode(&f, x, i);
+    int64_t yv = 0;
+    if (op == 0 || op == 1 || op == 3 || op == 4 || op == 5) yv = decode(&f, y, i);
+    if (op == 6) yv = decode(&f, r, i);
+    if (xv < 0 || yv < 0) { field_free(&f); return ORC_E_NONCANON; }
+    const uint64_t u = (uint64_t)xv, v = (uint64_t)yv;
+    uint64_t out = 0;
+    switch (op) {
+      case 0: out = (uint64_t)(((u128)u + v) % p); break;
+      case 1: out = (uint64_t)(((u128)u + p - v) % p); break;
+      case 2: out = (p - u) % p; break;
+      case 3: out = mulmod(u, v, p); break;
+      case 4: out = v == 0 ? 0 : mulmod(u, orc_inv_mod(v, p), p); break;
+      case 5:
+      case 6: out = (uint64_t)(((u128)(uint64_t)av * u + v) % p); break;
+    }
+    encode(&f, out, r, i);
+  }
+  field_free(&f);
+  return ORC_OK;
+}
+
 int orc_version(void) { return 1; }

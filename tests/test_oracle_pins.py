@@ -355,3 +355,118 @@ def test_gemm_special_cases(p, rep):
         r = synth.uniform_int(40, t, N, p).astype(object)
         Br = (Bc.astype(object) @ r) % p
         assert np.array_equal((Ac.astype(object) @ Br) % p, (Cc.astype(object) @ r) % p)
+
+
+# ------------------------------------------------ elementwise operations (Sec. 2)
+EW_BINARY = ("add", "sub", "mul", "div")
+
+
+def _py_ew(p, op, a, u, v, r_old):
+    """The seven operations on residues, in Python integers; the inverse from
+    Python's own modular exponent -1 (division by zero gives zero)."""
+    if op == "add":
+        return (u + v) % p
+    if op == "sub":
+        return (u - v) % p
+    if op == "neg":
+        return (-u) % p
+    if op == "mul":
+        return u * v % p
+    if op == "div":
+        return 0 if v == 0 else u * pow(v, -1, p) % p
+    if op == "axpy":
+        return (a * u + v) % p
+    if op == "axpyin":
+        return (a * u + r_old) % p
+    raise AssertionError(op)
+
+
+class _Codec:
+    """Python encode/decode with a log table (Zech at large p)."""
+
+    def __init__(self, p, rep):
+        self.p, self.rep = p, rep
+        self.g = oracle.primitive_root(p) if rep == "zech" else None
+        if rep == "zech":
+            self.log = {}
+            v = 1
+            for i in range(1, p):
+                v = v * self.g % p
+                self.log[v] = i
+
+    def dec(self, v):
+        return py_decode(self.p, self.rep, v, self.g)
+
+    def enc(self, r):
+        if self.rep == "zech":
+            return 0 if r == 0 else self.log[r]
+        return py_encode(self.p, self.rep, r, self.g)
+
+
+def _check_ew(p, rep, op, x, y, alpha, r_old):
+    c = _Codec(p, rep)
+    got = oracle.elementwise(p, rep, op, x, y if op not in ("neg", "axpyin") else None,
+                             alpha if op in ("axpy", "axpyin") else None,
+                             r_old if op == "axpyin" else None)
+    a = c.dec(alpha) if alpha is not None else 0
+    for i in range(len(x)):
+        want = c.enc(_py_ew(p, op, a, c.dec(x[i]), c.dec(y[i]), c.dec(r_old[i])))
+        g = float(got[i]) if rep == "fp64" else int(got[i])
+        assert g == want, (p, rep, op, i, x[i], y[i], alpha)
+
+
+@pytest.mark.parametrize("p", [3, 5, 7, 11])
+def test_elementwise_exhaustive_tiny_fields(p):
+    """Every operation on every pair of stored values (and every a for the
+    AXPY forms) of every representation of GF(p)."""
+    for rep in reps_for(p):
+        vals = stored_range(p, rep)
+        pairs = list(itertools.product(vals, repeat=2))
+        x = np.array([u for u, _ in pairs])
+        y = np.array([v for _, v in pairs])
+        for op in EW_BINARY + ("neg",):
+            _check_ew(p, rep, op, x, y, None, y)
+        for a in vals:
+            _check_ew(p, rep, "axpy", x, y, a, y)
+            _check_ew(p, rep, "axpyin", x, y, a, y)
+
+
+@pytest.mark.parametrize("p", CONFIG_PRIMES)
+def test_elementwise_random_against_bigint(p):
+    for rep in reps_for(p):
+        n = 3000
+        x = random_stored(p, rep, n, 12, 0)
+        y = random_stored(p, rep, n, 12, 1)
+        r = random_stored(p, rep, n, 12, 2)
+        alpha = random_stored(p, rep, 1, 12, 3)[0]
+        for op in EW_BINARY + ("neg", "axpy", "axpyin"):
+            _check_ew(p, rep, op, x, y, alpha, r)
+
+
+def test_elementwise_invariants():
+    """x - x = 0, x + (-x) = 0, (x y) / y = x for y != 0, x (1 / x) = 1,
+    axpy with a = 1 is addition and with a = 0 returns y, and every
+    representation gives the same residues for the same field elements."""
+    p = 32749
+    x = synth.uniform_int(13, 0, 5000, p)
+    y = synth.uniform_int(13, 1, 5000, p)
+    y[:10] = 0
+    ew = oracle.elementwise
+    assert (ew(p, "zpz", "sub", x, x) == 0).all()
+    assert (ew(p, "zpz", "add", x, ew(p, "zpz", "neg", x)) == 0).all()
+    q = ew(p, "zpz", "div", ew(p, "zpz", "mul", x, y), y)
+    assert (q[y != 0] == x[y != 0]).all() and (q[y == 0] == 0).all()
+    ones = np.ones(5000, dtype=np.uint64)
+    nz = x != 0
+    assert (ew(p, "zpz", "mul", x, ew(p, "zpz", "div", ones, x))[nz] == 1).all()
+    assert (ew(p, "zpz", "axpy", x, y, alpha=1) == ew(p, "zpz", "add", x, y)).all()
+    assert (ew(p, "zpz", "axpy", x, y, alpha=0) == y).all()
+    for op in ("add", "sub", "neg", "mul", "div", "axpy", "axpyin"):
+        res = set()
+        for rep in ("zpz", "mont", "fp64", "zech"):
+            xs, ys = oracle.encode(p, rep, x), oracle.encode(p, rep, y)
+            a = oracle.encode(p, rep, [12345])[0]
+            out = ew(p, rep, op, xs, ys if op not in ("neg", "axpyin") else None,
+                     a if op in ("axpy", "axpyin") else None, ys if op == "axpyin" else None)
+            res.add(tuple(oracle.decode(p, rep, out).tolist()))
+        assert len(res) == 1, op
