@@ -349,6 +349,43 @@ def served_workload(fd, n_req, seed=5):
     return fields, pools, reqs, outs
 
 
+def extras_elementwise(fd):
+    """The elementwise operations (Sec. 2) over 2^27 elements per operand:
+    algorithmic bytes (operands read plus the result written) over the
+    call's device time; division is ALU-bound (about 2 log2 p products per
+    element)."""
+    import synth
+    n = 1 << 27
+    out = {}
+    for p, rep in [(32749, "zpz"), (2147483647, "mont"), (67108859, "fp64"), (32749, "zech"),
+                   (251, "centred")]:
+        F = fd.Field(p, rep)
+        m, lo = (p, 0) if rep != "centred" else (p, -((p - 1) // 2))
+        x = torch.empty(n, dtype=F.dtype, device="cuda")
+        y = torch.empty(n, dtype=F.dtype, device="cuda")
+        r = torch.empty(n, dtype=F.dtype, device="cuda")
+        synth.fill_device(x, 10, 0, m, lo)
+        synth.fill_device(y, 10, 1, m, lo)
+        synth.fill_device(r, 10, 2, m, lo)
+        alpha = 3 if rep != "mont" else (3 << 32) % p
+        es = F.info["elem_bytes"]
+        row = {}
+        for op, arrays in [("add", 3), ("neg", 2), ("mul", 3), ("axpy", 3), ("axpyin", 3),
+                           ("div", 3)]:
+            kw = {"alpha": alpha} if op in ("axpy", "axpyin") else {}
+            yy = y if op in ("add", "mul", "div", "axpy") else None
+            oo = r if op == "axpyin" else torch.empty_like(x)
+            F.elementwise(op, x, yy, out=oo, **kw)  # first call: code objects
+            t = time_events(lambda: F.elementwise(op, x, yy, out=oo, **kw), 3)
+            gbps = arrays * n * es / t / 1e9
+            row[op] = {"ms": round(t * 1e3, 3), "GBps": round(gbps, 1),
+                       "gelem_per_s": round(n / t / 1e9, 1), "frac_of_hbm": round(gbps / 8000, 3)}
+        out[f"{rep} p={p}"] = row
+        del x, y, r
+        torch.cuda.empty_cache()
+    return out
+
+
 SWEEP_PRIMES = (251, 4093, 32749, 65521, 1048573, 16777213, 67108859, 2147483647, 4294967291)
 
 
@@ -511,6 +548,9 @@ def main():
         torch.cuda.empty_cache()
         log("extras: prime sweep ...")
         extras["prime_sweep"] = extras_prime_sweep(fd)
+        torch.cuda.empty_cache()
+        log("extras: elementwise ...")
+        extras["elementwise"] = extras_elementwise(fd)
         result["extras"] = extras
     print(json.dumps(result), flush=True)
 

@@ -218,6 +218,30 @@ fdot_status_t fdot_encode(fdot_field_t f, const uint32_t* canon, void* rep,
 fdot_status_t fdot_decode(fdot_field_t f, const void* rep, uint32_t* canon,
                           size_t n, void* stream);
 
+/* --------------------------------------------------- elementwise operations */
+
+/* The seven basic operations of Sec. 2 (opening) on vectors, elementwise. */
+typedef enum {
+  FDOT_EW_ADD = 0,    /* r = x + y */
+  FDOT_EW_SUB = 1,    /* r = x - y */
+  FDOT_EW_NEG = 2,    /* r = -x */
+  FDOT_EW_MUL = 3,    /* r = x * y */
+  FDOT_EW_DIV = 4,    /* r = x / y; a zero divisor gives the zero element */
+  FDOT_EW_AXPY = 5,   /* r = a * x + y */
+  FDOT_EW_AXPYIN = 6  /* r = a * x + r */
+} fdot_ew_op_t;
+
+/* r[i] = op(x[i], y[i]) for i < n over GF(p) in the field's representation
+ * (Sec. 2.1-2.4 give each operation per representation).  x, y and r are
+ * device arrays of the representation's element type, aligned to its size;
+ * y is read by ADD, SUB, MUL, DIV and AXPY (NULL allowed otherwise); r may be
+ * the same array as x or y (not a partial overlap).  alpha points to one
+ * element of the representation in host memory, read at the call, for AXPY
+ * and AXPYIN (NULL allowed otherwise).  Inputs must be canonical.  n = 0
+ * does nothing.  Enqueued on the stream. */
+fdot_status_t fdot_elementwise(fdot_field_t f, fdot_ew_op_t op, size_t n, const void* alpha,
+                               const void* x, const void* y, void* r, void* stream);
+
 /* ------------------------------------------------------------ dot products */
 
 /* result[0] = sum_{i<n} x_i*y_i over GF(p) (Sec. 1, Sec. 3), x, y, result on

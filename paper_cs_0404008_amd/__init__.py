@@ -29,6 +29,9 @@ ACCS = {"u64": 0, "u32": 1, "f64": 2, "i32_centred": 3, "f64_centred": 4, "mont_
         "u64_hybrid": 6}
 BOUNDS = {"axpy_signed": 0, "axpy_unsigned": 1, "montgomery": 2, "zech_index": 3}
 FOLDS = {"remainder": 0, "redc": 1, "fp64": 2}
+EW_OPS = {"add": 0, "sub": 1, "neg": 2, "mul": 3, "div": 4, "axpy": 5, "axpyin": 6}
+NP_DTYPES = {"zpz": "uint32", "mont": "uint32", "fp64": "float64", "zech": "uint16",
+             "centred": "int8"}
 TORCH_DTYPES = {"zpz": torch.uint32, "mont": torch.uint32, "fp64": torch.float64,
                 "zech": torch.uint16, "centred": torch.int8}
 
@@ -74,6 +77,7 @@ _sig("fdot_encode", [_vp, _vp, _vp, _sz, _vp])
 _sig("fdot_decode", [_vp, _vp, _vp, _sz, _vp])
 _sig("fdot_modp", [_vp, _vp, _vp, _sz, _vp, _vp])
 _sig("fdot_modp_algo", [_vp, _i32, _vp, _vp, _sz, _vp, _vp])
+_sig("fdot_elementwise", [_vp, _i32, _sz, _vp, _vp, _vp, _vp, _vp])
 _sig("fdot_modp_many", [_vp, _sz, _vp, _vp, _vp])
 _sig("fdot_modp_many_algo", [_vp, _i32, _sz, _vp, _vp, _vp])
 _sig("fgemv_modp", [_vp, _sz, _sz, _vp, _sz, _vp, _vp, _vp])
@@ -228,6 +232,37 @@ class Field:
             out = torch.empty(rep.shape, dtype=torch.uint32, device=rep.device)
         _check(_lib.fdot_decode(self._h, _ptr(rep), _ptr(out), rep.numel(), _stream(stream)),
                "fdot_decode")
+        return out
+
+    def elementwise(self, op: str, x: torch.Tensor, y: torch.Tensor | None = None,
+                    alpha=None, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """fdot_elementwise: op in EW_OPS; y for add/sub/mul/div/axpy, alpha (a
+        stored value of this representation) for axpy/axpyin; axpyin updates
+        out in place (out is required)."""
+        import numpy as np
+        code = EW_OPS[op]
+        self._need(x, "x")
+        if not x.is_contiguous():
+            raise ValueError("x must be contiguous")
+        if op in ("add", "sub", "mul", "div", "axpy"):
+            self._need(y, "y")
+            if y.numel() != x.numel() or not y.is_contiguous():
+                raise ValueError("y must be contiguous and as long as x")
+        if op == "axpyin" and out is None:
+            raise ValueError("axpyin updates out in place")
+        if out is None:
+            out = torch.empty_like(x)
+        self._need(out, "out")
+        if out.numel() != x.numel() or not out.is_contiguous():
+            raise ValueError("out must be contiguous and as long as x")
+        a = None
+        if op in ("axpy", "axpyin"):
+            if alpha is None:
+                raise ValueError(f"{op} needs alpha")
+            a = np.array([alpha], dtype=NP_DTYPES[self.rep])
+        _check(_lib.fdot_elementwise(self._h, code, x.numel(), a.ctypes.data if a is not None else None,
+                                     _ptr(x), _ptr(y) if y is not None else None, _ptr(out),
+                                     _stream(stream)), "fdot_elementwise")
         return out
 
     def dot(self, x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None,

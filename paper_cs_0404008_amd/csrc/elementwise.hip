@@ -1,0 +1,317 @@
+// Elementwise field operations (Sec. 2, opening): addition, subtraction,
+// negation, multiplication, division, AXPY (r = a x + y) and AXPYIN
+// (r = a x + r) on vectors of n stored values, in each representation:
+//
+//   classical residues (Sec. 2.1): one conditional correction for the sums,
+//     one remainder for a product or for a whole AXPY (a x + y < p 2^32);
+//   Montgomery residues (Sec. 2.2): sums as classical, products by REDC;
+//   integral doubles (Sec. 2.3): sums with one correction, products and
+//     AXPY by the floating-point remainder (exact: a x + y <= 2^53 is the
+//     field's admission bound);
+//   discrete logarithms (Sec. 2.4, Table 1): products and quotients are index
+//     sums and differences modulo q-1, negation adds the index of -1,
+//     addition goes through the plus-one table, g^i + g^j = g^i (1 + g^(j-i));
+//   centred residues (Sec. 3.2.2): sums with one correction each way,
+//     products by a signed remainder.
+//
+// Division multiplies by the inverse.  Except for discrete logarithms, the
+// inverse is b^(p-2) (Fermat), by square-and-multiply with the
+// representation's own product: the same instruction stream for every lane,
+// where the extended Euclidean algorithm of Sec. 2.1 would branch per lane.
+// A zero divisor gives the zero element.
+//
+// Every lane handles 16 bytes of each operand (one vector load) when all
+// pointers are 16-byte aligned, else one element; the loop strides over the
+// whole grid.  The kernels are bound by HBM except division (ALU-bound: about
+// 2 log2 p products per element).
+#include <string.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "fdot_internal.h"
+
+namespace {
+
+struct RZpz {
+  using E = uint32_t;
+  static __device__ E zero() { return 0; }
+  static __device__ E one(const FieldK&) { return 1; }
+  static __device__ E add(E a, E b, const FieldK& F) {
+    const uint64_t s = (uint64_t)a + b;
+    return (E)(s >= F.p ? s - F.p : s);
+  }
+  static __device__ E sub(E a, E b, const FieldK& F) {
+    return a >= b ? a - b : (E)((uint64_t)a + F.p - b);
+  }
+  static __device__ E neg(E a, const FieldK& F) { return a == 0 ? 0u : (E)(F.p - a); }
+  static __device__ E mul(E a, E b, const FieldK& F) { return mod_small((uint64_t)a * b, F); }
+  // one remainder for the whole a x + y (< p^2 < p 2^32)
+  static __device__ E axpy(E a, E x, E y, const FieldK& F) {
+    return mod_small((uint64_t)a * x + y, F);
+  }
+  static __device__ bool is_zero(E a) { return a == 0; }
+};
+
+struct RMont : RZpz {
+  // Montgomery form of 1 is B mod p
+  static __device__ E one(const FieldK& F) { return mod_u64(1ull << 32, F); }
+  static __device__ E mul(E a, E b, const FieldK& F) { return redc((uint64_t)a * b, F); }
+  static __device__ E axpy(E a, E x, E y, const FieldK& F) { return add(mul(a, x, F), y, F); }
+};
+
+struct RF64 {
+  using E = double;
+  static __device__ E zero() { return 0.0; }
+  static __device__ E one(const FieldK&) { return 1.0; }
+  static __device__ E add(E a, E b, const FieldK& F) {
+    const double s = a + b;
+    return s >= F.P ? s - F.P : s;
+  }
+  static __device__ E sub(E a, E b, const FieldK& F) { return a >= b ? a - b : (a - b) + F.P; }
+  static __device__ E neg(E a, const FieldK& F) { return a == 0.0 ? 0.0 : F.P - a; }
+  static __device__ E mul(E a, E b, const FieldK& F) { return fold_f64(a * b, F); }
+  static __device__ E axpy(E a, E x, E y, const FieldK& F) { return fold_f64(fma(a, x, y), F); }
+  static __device__ bool is_zero(E a) { return a == 0.0; }
+};
+
+// Codes: 0 is the zero element, i in [1, q-1] is g^i (q-1 codes the element 1).
+struct RZech {
+  using E = uint16_t;
+  static __device__ E zero() { return 0; }
+  static __device__ E one(const FieldK& F) { return (E)F.qbar; }
+  static __device__ E idx_add(uint32_t i, uint32_t j, const FieldK& F) {
+    const uint32_t k = i + j;
+    return (E)(k > F.qbar ? k - F.qbar : k);
+  }
+  static __device__ E idx_sub(uint32_t i, uint32_t j, const FieldK& F) {
+    return (E)(i > j ? i - j : i + F.qbar - j);
+  }
+  static __device__ E mul(E a, E b, const FieldK& F) {
+    return (a == 0 || b == 0) ? (E)0 : idx_add(a, b, F);
+  }
+  static __device__ E div(E a, E b, const FieldK& F) {
+    return (a == 0 || b == 0) ? (E)0 : idx_sub(a, b, F);
+  }
+  // -1 = g^((q-1)/2)
+  static __device__ E neg(E a, const FieldK& F) {
+    return a == 0 ? (E)0 : idx_add(a, F.qbar / 2, F);
+  }
+  static __device__ E add(E a, E b, const FieldK& F) {
+    if (a == 0) return b;
+    if (b == 0) return a;
+    const E t = F.zplus1[idx_sub(b, a, F)];  // code of 1 + g^(j - i)
+    return t == 0 ? (E)0 : idx_add(a, t, F);
+  }
+  static __device__ E sub(E a, E b, const FieldK& F) { return add(a, neg(b, F), F); }
+  static __device__ E axpy(E a, E x, E y, const FieldK& F) { return add(mul(a, x, F), y, F); }
+  static __device__ bool is_zero(E a) { return a == 0; }
+};
+
+struct RCentred {
+  using E = int8_t;
+  static __device__ E zero() { return 0; }
+  static __device__ E one(const FieldK&) { return 1; }
+  static __device__ E centre(int32_t s, const FieldK& F) {
+    s = s > F.half ? s - (int32_t)F.p32 : s;
+    return (E)(s < -F.half ? s + (int32_t)F.p32 : s);
+  }
+  static __device__ E add(E a, E b, const FieldK& F) { return centre((int32_t)a + b, F); }
+  static __device__ E sub(E a, E b, const FieldK& F) { return centre((int32_t)a - b, F); }
+  static __device__ E neg(E a, const FieldK&) { return (E)-a; }
+  // |v| <= h^2 + h, so v + p (h + 1) is positive and below p^2 < p 2^32:
+  // one 2-by-1 remainder
+  static __device__ E signed_rem(int32_t v, const FieldK& F) {
+    const uint32_t t = (uint32_t)(v + (int32_t)F.p32 * (F.half + 1));
+    const int32_t r = (int32_t)mod_small(t, F);
+    return (E)(r > F.half ? r - (int32_t)F.p32 : r);
+  }
+  static __device__ E mul(E a, E b, const FieldK& F) { return signed_rem((int32_t)a * b, F); }
+  static __device__ E axpy(E a, E x, E y, const FieldK& F) {
+    return signed_rem((int32_t)a * x + y, F);
+  }
+  static __device__ bool is_zero(E a) { return a == 0; }
+};
+
+// 16-byte global accesses, marked nontemporal: every element is touched once.
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const v4u gv4_t;
+typedef __attribute__((address_space(1))) v4u gv4w_t;
+
+template <class V>
+__device__ __forceinline__ V load16(const V* p) {
+  const v4u raw = __builtin_nontemporal_load((gv4_t*)p);
+  V v;
+  __builtin_memcpy(&v, &raw, 16);
+  return v;
+}
+template <class V>
+__device__ __forceinline__ void store16(V* p, const V& v) {
+  v4u raw;
+  __builtin_memcpy(&raw, &v, 16);
+  __builtin_nontemporal_store(raw, (gv4w_t*)p);
+}
+
+// Discrete-logarithm additions read the plus-one table at random; it is
+// staged in LDS (2p bytes, at most 128 KiB) by workgroups that stay resident
+// for the whole vector.
+template <class R, int OP>
+constexpr bool table_in_lds() {
+  return std::is_same<R, RZech>::value &&
+         (OP == FDOT_EW_ADD || OP == FDOT_EW_SUB || OP == FDOT_EW_AXPY);
+}
+
+// b^(p-2) by square-and-multiply from the top bit of p-2.
+template <class R>
+__device__ typename R::E inverse(typename R::E b, const FieldK& F) {
+  using E = typename R::E;
+  const uint64_t e = F.p - 2;
+  E r = R::one(F);
+  for (int bit = 63 - __builtin_clzll(e | 1); bit >= 0; --bit) {
+    r = R::mul(r, r, F);
+    if ((e >> bit) & 1) r = R::mul(r, b, F);
+  }
+  return r;
+}
+
+template <class R>
+__device__ typename R::E divide(typename R::E a, typename R::E b, const FieldK& F) {
+  if constexpr (std::is_same<R, RZech>::value) {
+    return R::div(a, b, F);
+  } else {
+    if (R::is_zero(b)) return R::zero();
+    if (F.p == 2) return a;  // the only nonzero divisor is 1
+    return R::mul(a, inverse<R>(b, F), F);
+  }
+}
+
+template <class R, int OP>
+__device__ __forceinline__ typename R::E apply(typename R::E a, typename R::E x,
+                                               typename R::E y, const FieldK& F) {
+  switch (OP) {
+    case FDOT_EW_ADD: return R::add(x, y, F);
+    case FDOT_EW_SUB: return R::sub(x, y, F);
+    case FDOT_EW_NEG: return R::neg(x, F);
+    case FDOT_EW_MUL: return R::mul(x, y, F);
+    case FDOT_EW_DIV: return divide<R>(x, y, F);
+    default: return R::axpy(a, x, y, F);  // AXPY, and AXPYIN with y = r
+  }
+}
+
+// y is read for the binary operations and AXPY; for AXPYIN it is r itself.
+template <int OP>
+constexpr bool reads_y() {
+  return OP != FDOT_EW_NEG;
+}
+
+template <class R, int OP, bool VEC, int NT>
+__global__ __launch_bounds__(NT) void ew_kernel(const FieldK Fin, uint64_t n,
+                                                const typename R::E* x,
+                                                const typename R::E* y, typename R::E* r,
+                                                typename R::E a) {
+  using E = typename R::E;
+  FieldK F = Fin;
+  if constexpr (table_in_lds<R, OP>()) {
+    extern __shared__ uint16_t s_plus1[];
+    for (uint32_t i = threadIdx.x; i < (uint32_t)Fin.p; i += NT) s_plus1[i] = Fin.zplus1[i];
+    __syncthreads();
+    F.zplus1 = s_plus1;
+  }
+  const uint64_t tid = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * NT;
+  if constexpr (VEC) {
+    constexpr int W = 16 / (int)sizeof(E);
+    struct alignas(16) V { E e[W]; };
+    const uint64_t nv = n / W;
+    uint64_t v = tid;
+    for (; v < nv; v += stride) {
+      const V xv = load16((const V*)x + v);
+      V yv = {};
+      if constexpr (reads_y<OP>()) yv = load16((const V*)y + v);
+      V out;
+#pragma unroll
+      for (int k = 0; k < W; ++k) out.e[k] = apply<R, OP>(a, xv.e[k], yv.e[k], F);
+      store16((V*)r + v, out);
+    }
+    for (uint64_t i = nv * W + tid; i < n; i += stride)
+      r[i] = apply<R, OP>(a, x[i], reads_y<OP>() ? y[i] : E(0), F);
+  } else {
+    for (uint64_t i = tid; i < n; i += stride)
+      r[i] = apply<R, OP>(a, x[i], reads_y<OP>() ? y[i] : E(0), F);
+  }
+}
+
+template <class R, int OP>
+fdot_status_t launch_op(const fdot_field_s* f, uint64_t n, const void* alpha, const void* x,
+                        const void* y, void* r, hipStream_t s) {
+  using E = typename R::E;
+  E a{};
+  if (alpha) memcpy(&a, alpha, sizeof(E));
+  const uintptr_t bits = (uintptr_t)x | (uintptr_t)r | (reads_y<OP>() ? (uintptr_t)y : 0);
+  const bool vec = (bits & 15u) == 0;
+  const uint64_t per = vec ? 16 / sizeof(E) : 1;
+  const uint64_t work = (n + per - 1) / per;
+  if constexpr (table_in_lds<R, OP>()) {
+    // 1024 threads per workgroup, as many resident workgroups as the LDS
+    // holds tables (160 KiB per CU), and no more than the work needs
+    constexpr int NT = 1024;
+    const size_t lds = (size_t)f->info.p * sizeof(uint16_t);
+    const uint64_t per_cu = std::max<uint64_t>(1, (160u * 1024u) / lds);
+    const unsigned grid = (unsigned)std::max<uint64_t>(
+        1, std::min<uint64_t>((work + NT - 1) / NT, (uint64_t)fd_cu_count() * per_cu));
+    static bool attr_set[2] = {false, false};
+    if (!attr_set[vec]) {
+      (void)hipFuncSetAttribute(vec ? (const void*)ew_kernel<R, OP, true, NT>
+                                    : (const void*)ew_kernel<R, OP, false, NT>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+      attr_set[vec] = true;
+    }
+    if (vec)
+      hipLaunchKernelGGL((ew_kernel<R, OP, true, NT>), dim3(grid), dim3(NT), lds, s, f->k, n,
+                         (const E*)x, (const E*)y, (E*)r, a);
+    else
+      hipLaunchKernelGGL((ew_kernel<R, OP, false, NT>), dim3(grid), dim3(NT), lds, s, f->k, n,
+                         (const E*)x, (const E*)y, (E*)r, a);
+  } else {
+    const unsigned grid = (unsigned)std::max<uint64_t>(
+        1, std::min<uint64_t>((work + 255) / 256, (uint64_t)fd_cu_count() * 16));
+    if (vec)
+      hipLaunchKernelGGL((ew_kernel<R, OP, true, 256>), dim3(grid), dim3(256), 0, s, f->k, n,
+                         (const E*)x, (const E*)y, (E*)r, a);
+    else
+      hipLaunchKernelGGL((ew_kernel<R, OP, false, 256>), dim3(grid), dim3(256), 0, s, f->k, n,
+                         (const E*)x, (const E*)y, (E*)r, a);
+  }
+  return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
+}
+
+template <class R>
+fdot_status_t launch_rep(const fdot_field_s* f, fdot_ew_op_t op, uint64_t n, const void* alpha,
+                         const void* x, const void* y, void* r, hipStream_t s) {
+  switch (op) {
+    case FDOT_EW_ADD: return launch_op<R, FDOT_EW_ADD>(f, n, alpha, x, y, r, s);
+    case FDOT_EW_SUB: return launch_op<R, FDOT_EW_SUB>(f, n, alpha, x, y, r, s);
+    case FDOT_EW_NEG: return launch_op<R, FDOT_EW_NEG>(f, n, alpha, x, y, r, s);
+    case FDOT_EW_MUL: return launch_op<R, FDOT_EW_MUL>(f, n, alpha, x, y, r, s);
+    case FDOT_EW_DIV: return launch_op<R, FDOT_EW_DIV>(f, n, alpha, x, y, r, s);
+    case FDOT_EW_AXPY: return launch_op<R, FDOT_EW_AXPY>(f, n, alpha, x, y, r, s);
+    case FDOT_EW_AXPYIN: return launch_op<R, FDOT_EW_AXPY>(f, n, alpha, x, r, r, s);
+  }
+  return FDOT_E_INVALID_ARG;
+}
+
+}  // namespace
+
+fdot_status_t fd_launch_elementwise(const fdot_field_s* f, fdot_ew_op_t op, uint64_t n,
+                                    const void* alpha, const void* x, const void* y, void* r,
+                                    hipStream_t s) {
+  if (n == 0) return FDOT_OK;
+  switch (f->info.rep) {
+    case FDOT_REP_ZPZ_U32: return launch_rep<RZpz>(f, op, n, alpha, x, y, r, s);
+    case FDOT_REP_MONT_U32: return launch_rep<RMont>(f, op, n, alpha, x, y, r, s);
+    case FDOT_REP_FP64: return launch_rep<RF64>(f, op, n, alpha, x, y, r, s);
+    case FDOT_REP_ZECH_U16: return launch_rep<RZech>(f, op, n, alpha, x, y, r, s);
+    case FDOT_REP_CENTRED_I8: return launch_rep<RCentred>(f, op, n, alpha, x, y, r, s);
+  }
+  return FDOT_E_UNSUPPORTED;
+}

@@ -77,4 +77,7 @@ fdot_status_t fd_launch_gemm(const fdot_field_s* f, size_t M, size_t N, size_t K
                              const void* A, size_t lda, const void* B, size_t ldb,
                              void* C, size_t ldc, hipStream_t s);
 fdot_status_t fd_launch_zero(void* ptr, size_t bytes, hipStream_t s);
+fdot_status_t fd_launch_elementwise(const fdot_field_s* f, fdot_ew_op_t op, uint64_t n,
+                                    const void* alpha, const void* x, const void* y, void* r,
+                                    hipStream_t s);
 fdot_algo_t fd_default_algo(const fdot_field_s* f, uint64_t n);

@@ -214,6 +214,22 @@ fdot_status_t fdot_decode(fdot_field_t f, const void* rep, uint32_t* canon, size
   return fd_launch_decode(f, rep, canon, n, (hipStream_t)stream);
 }
 
+fdot_status_t fdot_elementwise(fdot_field_t f, fdot_ew_op_t op, size_t n, const void* alpha,
+                               const void* x, const void* y, void* r, void* stream) {
+  if (!f) return FDOT_E_INVALID_ARG;
+  if (f->host_only) return FDOT_E_UNSUPPORTED;
+  if ((int)op < FDOT_EW_ADD || (int)op > FDOT_EW_AXPYIN) return FDOT_E_INVALID_ARG;
+  if (n == 0) return FDOT_OK;
+  const size_t es = f->info.elem_bytes;
+  const bool needs_y = op != FDOT_EW_NEG && op != FDOT_EW_AXPYIN;
+  const bool needs_a = op == FDOT_EW_AXPY || op == FDOT_EW_AXPYIN;
+  if (!x || !r || !aligned_to(x, es) || !aligned_to(r, es)) return FDOT_E_INVALID_ARG;
+  if (needs_y && (!y || !aligned_to(y, es))) return FDOT_E_INVALID_ARG;
+  if (needs_a && !alpha) return FDOT_E_INVALID_ARG;
+  return fd_launch_elementwise(f, op, n, needs_a ? alpha : nullptr, x, needs_y ? y : nullptr, r,
+                               (hipStream_t)stream);
+}
+
 fdot_status_t fdot_modp_algo(fdot_field_t f, fdot_algo_t algo, const void* x, const void* y,
                              size_t n, void* result, void* stream) {
   if (!f || !result) return FDOT_E_INVALID_ARG;

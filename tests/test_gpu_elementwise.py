@@ -1,0 +1,120 @@
+"""GPU parity of the elementwise field operations (fdot_elementwise) against
+the oracle, bit for bit: the seven operations of Sec. 2 in every
+representation, lengths that leave ragged tails of the 16-byte vector path,
+misaligned operands (element-wise path), in-place results, zero divisors and
+the edge elements 0, 1 and p-1."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.gpu_helpers import ELEM_BYTES, TORCH_DTYPES, same, stored, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+fd = pytest.importorskip("paper_cs_0404008_amd")
+
+OPS = ("add", "sub", "neg", "mul", "div", "axpy", "axpyin")
+FIELDS = [(32749, "zpz"), (65521, "zpz"), (2147483647, "zpz"), (4294967291, "zpz"), (2, "zpz"),
+          (2147483647, "mont"), (65521, "mont"), (2654435761, "mont"),
+          (67108859, "fp64"), (1048573, "fp64"), (2, "fp64"),
+          (32749, "zech"), (65521, "zech"), (3, "zech"),
+          (251, "centred"), (3, "centred")]
+
+_fields = {}
+
+
+def field(p, rep):
+    if (p, rep) not in _fields:
+        _fields[(p, rep)] = fd.Field(p, rep)
+    return _fields[(p, rep)]
+
+
+def inputs(p, rep, n, seed):
+    x = stored(p, rep, n, seed, 0)
+    y = stored(p, rep, n, seed, 1)
+    r = stored(p, rep, n, seed, 2)
+    edge = oracle.encode(p, rep, [0, 1 % p, p - 1, 0, 1 % p, p - 1])
+    k = min(n, 6)
+    x[:k] = edge[:k]
+    y[:k] = edge[::-1][:k]       # zero divisors among them
+    alpha = stored(p, rep, 1, seed, 3)[0]
+    return x, y, r, alpha
+
+
+def run(F, op, x, y, r, alpha, offset=0):
+    """op on device copies; offset > 0 shifts every operand by that many
+    elements inside a larger buffer (misaligned for the vector path)."""
+    def dev(a):
+        buf = torch.zeros(a.size + offset, dtype=F.dtype, device="cuda")
+        buf[offset:] = to_dev(a)
+        return buf[offset:]
+    xd, yd, rd = dev(x), dev(y), dev(r)
+    out = rd if op == "axpyin" else None
+    got = F.elementwise(op, xd, yd if op in ("add", "sub", "mul", "div", "axpy") else None,
+                        alpha=alpha if op in ("axpy", "axpyin") else None, out=out)
+    return to_host(got)
+
+
+def want(p, rep, op, x, y, r, alpha):
+    return oracle.elementwise(p, rep, op, x, y if op in ("add", "sub", "mul", "div", "axpy") else None,
+                              alpha if op in ("axpy", "axpyin") else None,
+                              r if op == "axpyin" else None)
+
+
+@pytest.mark.parametrize("p,rep", FIELDS, ids=lambda v: str(v))
+def test_elementwise_matches_oracle(p, rep):
+    F = field(p, rep)
+    for n in (0, 1, 5, 15, 17, 4099, 100003):
+        x, y, r, alpha = inputs(p, rep, n, 80 + n % 7)
+        for op in OPS:
+            got = run(F, op, x, y, r, alpha)
+            assert same(got, want(p, rep, op, x, y, r, alpha)), (p, rep, op, n)
+
+
+@pytest.mark.parametrize("p,rep", [(65521, "zpz"), (2147483647, "mont"), (67108859, "fp64"),
+                                   (32749, "zech"), (251, "centred")])
+def test_elementwise_misaligned_and_in_place(p, rep):
+    F = field(p, rep)
+    n = 10007
+    x, y, r, alpha = inputs(p, rep, n, 90)
+    for op in OPS:
+        got = run(F, op, x, y, r, alpha, offset=1)
+        assert same(got, want(p, rep, op, x, y, r, alpha)), (p, rep, op)
+    # r = x in place, and r = y
+    xd, yd = to_dev(x), to_dev(y)
+    F.elementwise("mul", xd, yd, out=xd)
+    assert same(to_host(xd), oracle.elementwise(p, rep, "mul", x, y))
+    xd = to_dev(x)
+    F.elementwise("sub", xd, yd, out=yd)
+    assert same(to_host(yd), oracle.elementwise(p, rep, "sub", x, y))
+
+
+@pytest.mark.parametrize("p,rep", [(32749, "zpz"), (67108859, "fp64"), (32749, "zech")])
+def test_elementwise_large(p, rep):
+    """A length of 2^24 + 3 (many grid strides, ragged tail)."""
+    F = field(p, rep)
+    n = (1 << 24) + 3
+    x, y, r, alpha = inputs(p, rep, n, 91)
+    for op in ("add", "mul", "axpy"):
+        got = run(F, op, x, y, r, alpha)
+        assert same(got, want(p, rep, op, x, y, r, alpha)), (p, rep, op)
+
+
+def test_elementwise_argument_errors():
+    F = field(65521, "zpz")
+    x = torch.zeros(8, dtype=torch.uint32, device="cuda")
+    with pytest.raises(ValueError):
+        F.elementwise("axpy", x, x)            # no alpha
+    with pytest.raises(ValueError):
+        F.elementwise("axpyin", x, alpha=1)    # no out
+    with pytest.raises(TypeError):
+        F.elementwise("add", x, torch.zeros(8, dtype=torch.float64, device="cuda"))
+    import ctypes
+    L = fd.lib()
+    assert L.fdot_elementwise(F.handle, 9, 8, None, ctypes.c_void_p(x.data_ptr()),
+                              ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                              None) == -1      # unknown operation
+    assert L.fdot_elementwise(F.handle, 0, 8, None, ctypes.c_void_p(x.data_ptr()), None,
+                              ctypes.c_void_p(x.data_ptr()), None) == -1  # add without y
+    assert ELEM_BYTES["zpz"] == 4 and TORCH_DTYPES["zpz"] == torch.uint32
