@@ -56,6 +56,11 @@ def lib():
         L.orc_gemm_entries.argtypes = [u64, i32, sz, vp, sz, vp, sz, sz, vp, vp, vp]
         L.orc_gemv.argtypes = [u64, i32, sz, sz, vp, sz, vp, vp]
         L.orc_elementwise.argtypes = [u64, i32, i32, sz, vp, vp, vp, vp]
+        L.orc_ext_modulus.argtypes = [u64, i32, vp]
+        L.orc_ext_encode.argtypes = [u64, i32, vp, vp, sz]
+        L.orc_ext_decode.argtypes = [u64, i32, vp, vp, sz]
+        L.orc_ext_dot.argtypes = [u64, i32, vp, vp, sz, vp]
+        L.orc_ext_elementwise.argtypes = [u64, i32, i32, sz, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -178,4 +183,46 @@ def elementwise(p: int, rep: str, op: str, x, y=None, alpha=None, r=None) -> np.
         raise ValueError("length mismatch")
     _check(lib().orc_elementwise(p, REPS[rep], EW_OPS[op], xa.size, _ptr(al), _ptr(xa),
                                  _ptr(ya), _ptr(out)), "elementwise")
+    return out
+
+
+# ------------------------------------------------- extension fields GF(p^d)
+def ext_modulus(p: int, d: int) -> int:
+    """The modulus polynomial f of GF(p^d) as the integer f(p)."""
+    out = np.zeros(1, dtype=np.uint64)
+    _check(lib().orc_ext_modulus(p, d, _ptr(out)), "ext_modulus")
+    return int(out[0])
+
+
+def ext_encode(p: int, d: int, values) -> np.ndarray:
+    v = np.ascontiguousarray(np.asarray(values, dtype=np.uint32))
+    out = np.empty(v.shape, dtype=np.uint16)
+    _check(lib().orc_ext_encode(p, d, _ptr(v), _ptr(out), v.size), "ext_encode")
+    return out
+
+
+def ext_decode(p: int, d: int, codes) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(codes, dtype=np.uint16))
+    out = np.empty(c.shape, dtype=np.uint32)
+    _check(lib().orc_ext_decode(p, d, _ptr(c), _ptr(out), c.size), "ext_decode")
+    return out
+
+
+def ext_dot(p: int, d: int, x, y) -> int:
+    xa = np.ascontiguousarray(np.asarray(x, dtype=np.uint16))
+    ya = np.ascontiguousarray(np.asarray(y, dtype=np.uint16))
+    if xa.size != ya.size:
+        raise ValueError("length mismatch")
+    out = np.zeros(1, dtype=np.uint16)
+    _check(lib().orc_ext_dot(p, d, _ptr(xa), _ptr(ya), xa.size, _ptr(out)), "ext_dot")
+    return int(out[0])
+
+
+def ext_elementwise(p: int, d: int, op: str, x, y=None, alpha=None, r=None) -> np.ndarray:
+    xa = np.ascontiguousarray(np.asarray(x, dtype=np.uint16))
+    ya = np.ascontiguousarray(np.asarray(y if y is not None else np.zeros_like(xa), dtype=np.uint16))
+    out = np.ascontiguousarray(np.asarray(r, dtype=np.uint16)).copy() if r is not None else np.zeros_like(xa)
+    al = np.array([alpha if alpha is not None else 0], dtype=np.uint16)
+    _check(lib().orc_ext_elementwise(p, d, EW_OPS[op], xa.size, _ptr(al), _ptr(xa), _ptr(ya),
+                                     _ptr(out)), "ext_elementwise")
     return out

@@ -397,4 +397,192 @@ int orc_elementwise(uint64_t p, int rep, int op, size_t n, const void* a, const 
   return ORC_OK;
 }
 
+/* ------------------------------------------- extension fields GF(p^d) */
+
+/* Sec. 2.4.2: the discrete-logarithm representation is the same for a field
+ * extension GF(q), q = p^d.  Here an element is a polynomial of degree < d
+ * over GF(p), written as the integer c_0 + c_1 p + ... + c_{d-1} p^{d-1}
+ * (its "value"), and arithmetic is polynomial arithmetic modulo a monic
+ * primitive polynomial f of degree d: the one whose lower coefficients,
+ * read as the same kind of integer, are smallest.  The generator is the
+ * class of X; code 0 is the zero element, code i (1 <= i <= q-1) is X^i (so
+ * q-1 codes 1), as for prime fields.  All arithmetic below works on
+ * coefficient arrays; nothing is tabulated except the code <-> value maps,
+ * which are built by repeated multiplication by X. */
+
+#define EXT_MAXD 16
+
+typedef struct {
+  uint64_t p, q;
+  int d;
+  uint64_t f[EXT_MAXD + 1];  /* modulus coefficients, f[d] = 1 */
+  uint32_t* exp;             /* code -> value (exp[0] = 0) */
+  uint32_t* log;             /* value -> code */
+} orc_ext;
+
+static void ext_to_coef(const orc_ext* E, uint64_t v, uint64_t* c) {
+  for (int i = 0; i < E->d; ++i) { c[i] = v % E->p; v /= E->p; }
+}
+static uint64_t ext_from_coef(const orc_ext* E, const uint64_t* c) {
+  uint64_t v = 0;
+  for (int i = E->d - 1; i >= 0; --i) v = v * E->p + c[i];
+  return v;
+}
+static uint64_t ext_add(const orc_ext* E, uint64_t a, uint64_t b) {
+  uint64_t ca[EXT_MAXD], cb[EXT_MAXD];
+  ext_to_coef(E, a, ca); ext_to_coef(E, b, cb);
+  for (int i = 0; i < E->d; ++i) ca[i] = (ca[i] + cb[i]) % E->p;
+  return ext_from_coef(E, ca);
+}
+static uint64_t ext_neg(const orc_ext* E, uint64_t a) {
+  uint64_t ca[EXT_MAXD];
+  ext_to_coef(E, a, ca);
+  for (int i = 0; i < E->d; ++i) ca[i] = (E->p - ca[i]) % E->p;
+  return ext_from_coef(E, ca);
+}
+/* schoolbook product, then reduction by the monic modulus from the top */
+static uint64_t ext_mul(const orc_ext* E, uint64_t a, uint64_t b) {
+  uint64_t ca[EXT_MAXD], cb[EXT_MAXD], t[2 * EXT_MAXD] = {0};
+  ext_to_coef(E, a, ca); ext_to_coef(E, b, cb);
+  const int d = E->d;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) t[i + j] = (t[i + j] + ca[i] * cb[j]) % E->p;
+  for (int k = 2 * d - 2; k >= d; --k) {
+    const uint64_t c = t[k];
+    if (!c) continue;
+    for (int i = 0; i <= d; ++i) t[k - d + i] = (t[k - d + i] + (E->p - c) * E->f[i]) % E->p;
+  }
+  return ext_from_coef(E, t);
+}
+static uint64_t ext_pow(const orc_ext* E, uint64_t a, uint64_t e) {
+  uint64_t r = 1;
+  while (e) {
+    if (e & 1) r = ext_mul(E, r, a);
+    a = ext_mul(E, a, a);
+    e >>= 1;
+  }
+  return r;
+}
+
+static void ext_free(orc_ext* E) {
+  free(E->exp); free(E->log);
+  E->exp = E->log = NULL;
+}
+
+/* Find the modulus: candidates in increasing order of their lower
+ * coefficients; f is primitive exactly when X, multiplied by itself, first
+ * returns to 1 after q-1 steps (X has order q-1). */
+static int ext_init(orc_ext* E, uint64_t p, int d) {
+  memset(E, 0, sizeof(*E));
+  if (d < 2 || d > EXT_MAXD || !orc_is_prime(p)) return ORC_E_PRIME;
+  uint64_t q = 1;
+  for (int i = 0; i < d; ++i) { q *= p; if (q > 65536) return ORC_E_PRIME; }
+  E->p = p; E->q = q; E->d = d;
+  E->exp = (uint32_t*)malloc(sizeof(uint32_t) * q);
+  E->log = (uint32_t*)malloc(sizeof(uint32_t) * q);
+  if (!E->exp || !E->log) { ext_free(E); return ORC_E_NOMEM; }
+  const uint64_t x = p;  /* the value of the polynomial X */
+  for (uint64_t low = 0; low < q; ++low) {
+    uint64_t c[EXT_MAXD];
+    ext_to_coef(E, low, c);
+    if (c[0] == 0) continue;  /* X divides f */
+    for (int i = 0; i < d; ++i) E->f[i] = c[i];
+    E->f[d] = 1;
+    uint64_t v = 1, k = 0;
+    do { v = ext_mul(E, v, x); ++k; } while (v != 1 && k < q);
+    if (k != q - 1) continue;
+    E->exp[0] = 0; E->log[0] = 0;
+    v = 1;
+    for (uint64_t i = 1; i <= q - 1; ++i) {
+      v = ext_mul(E, v, x);
+      E->exp[i] = (uint32_t)v;
+      E->log[v] = (uint32_t)i;
+    }
+    return ORC_OK;
+  }
+  ext_free(E);
+  return ORC_E_PRIME;
+}
+
+/* The modulus as an integer: f(p) = sum f_i p^i, including p^d. */
+int orc_ext_modulus(uint64_t p, int d, uint64_t* modulus) {
+  orc_ext E;
+  int rc = ext_init(&E, p, d);
+  if (rc == ORC_OK) {
+    uint64_t v = 0;
+    for (int i = d; i >= 0; --i) v = v * p + E.f[i];
+    *modulus = v;
+  }
+  ext_free(&E);
+  return rc;
+}
+
+/* Codes <-> values (uint16 codes, uint32 values). */
+int orc_ext_encode(uint64_t p, int d, const uint32_t* values, uint16_t* codes, size_t n) {
+  orc_ext E;
+  int rc = ext_init(&E, p, d);
+  for (size_t i = 0; rc == ORC_OK && i < n; ++i) {
+    if (values[i] >= E.q) rc = ORC_E_NONCANON;
+    else codes[i] = (uint16_t)E.log[values[i]];
+  }
+  ext_free(&E);
+  return rc;
+}
+int orc_ext_decode(uint64_t p, int d, const uint16_t* codes, uint32_t* values, size_t n) {
+  orc_ext E;
+  int rc = ext_init(&E, p, d);
+  for (size_t i = 0; rc == ORC_OK && i < n; ++i) {
+    if (codes[i] >= E.q) rc = ORC_E_NONCANON;
+    else values[i] = E.exp[codes[i]];
+  }
+  ext_free(&E);
+  return rc;
+}
+
+/* sum x_i y_i in GF(q), on codes: every product and sum in polynomial
+ * arithmetic, the result encoded to its code. */
+int orc_ext_dot(uint64_t p, int d, const uint16_t* x, const uint16_t* y, size_t n,
+                uint16_t* out) {
+  orc_ext E;
+  int rc = ext_init(&E, p, d);
+  uint64_t acc = 0;
+  for (size_t i = 0; rc == ORC_OK && i < n; ++i) {
+    if (x[i] >= E.q || y[i] >= E.q) { rc = ORC_E_NONCANON; break; }
+    acc = ext_add(&E, acc, ext_mul(&E, E.exp[x[i]], E.exp[y[i]]));
+  }
+  if (rc == ORC_OK) *out = (uint16_t)E.log[acc];
+  ext_free(&E);
+  return rc;
+}
+
+/* The seven elementwise operations of Sec. 2 in GF(q) on codes, numbered as
+ * for prime fields; the inverse is a^(q-2); a zero divisor gives zero. */
+int orc_ext_elementwise(uint64_t p, int d, int op, size_t n, const uint16_t* a,
+                        const uint16_t* x, const uint16_t* y, uint16_t* r) {
+  if (op < 0 || op > 6) return ORC_E_ARG;
+  orc_ext E;
+  int rc = ext_init(&E, p, d);
+  if (rc) { ext_free(&E); return rc; }
+  const uint64_t av = (op == 5 || op == 6) ? E.exp[a[0] < E.q ? a[0] : 0] : 0;
+  for (size_t i = 0; i < n; ++i) {
+    const uint64_t u = E.exp[x[i]];
+    uint64_t v = 0;
+    if (op == 0 || op == 1 || op == 3 || op == 4 || op == 5) v = E.exp[y[i]];
+    if (op == 6) v = E.exp[r[i]];
+    uint64_t out = 0;
+    switch (op) {
+      case 0: out = ext_add(&E, u, v); break;
+      case 1: out = ext_add(&E, u, ext_neg(&E, v)); break;
+      case 2: out = ext_neg(&E, u); break;
+      case 3: out = ext_mul(&E, u, v); break;
+      case 4: out = v == 0 ? 0 : ext_mul(&E, u, ext_pow(&E, v, E.q - 2)); break;
+      case 5:
+      case 6: out = ext_add(&E, ext_mul(&E, av, u), v); break;
+    }
+    r[i] = (uint16_t)E.log[out];
+  }
+  ext_free(&E);
+  return ORC_OK;
+}
+
 int orc_version(void) { return 1; }

@@ -470,3 +470,87 @@ def test_elementwise_invariants():
                      a if op in ("axpy", "axpyin") else None, ys if op == "axpyin" else None)
             res.add(tuple(oracle.decode(p, rep, out).tolist()))
         assert len(res) == 1, op
+
+
+# ------------------------------------------------ extension fields (Sec. 2.4.2)
+def test_ext_moduli_match_published_primitive_polynomials():
+    """The smallest primitive polynomials over GF(2) of degrees 2..8 and 16,
+    as tabulated in the coding literature (x^2+x+1, x^3+x+1, x^4+x+1,
+    x^5+x^2+1, x^6+x+1, x^7+x+1, x^8+x^4+x^3+x^2+1, x^16+x^5+x^3+x^2+1), and
+    x^2+x+2 for GF(9) and GF(25)."""
+    want = {(2, 2): 0x7, (2, 3): 0xB, (2, 4): 0x13, (2, 5): 0x25, (2, 6): 0x43, (2, 7): 0x83,
+            (2, 8): 0x11D, (2, 16): 0x1002D, (3, 2): 9 + 3 + 2, (5, 2): 25 + 5 + 2}
+    for (p, d), f in want.items():
+        assert oracle.ext_modulus(p, d) == f, (p, d)
+
+
+def test_ext_gf4_multiplication_table():
+    """GF(4) = GF(2)[X]/(X^2+X+1), values 0, 1, X = 2, X+1 = 3: the
+    multiplication table every textbook prints."""
+    table = {(2, 2): 3, (2, 3): 1, (3, 3): 2, (3, 2): 1}
+    vals = [0, 1, 2, 3]
+    for a in vals:
+        for b in vals:
+            ca, cb = oracle.ext_encode(2, 2, [a, b])
+            got = oracle.ext_decode(2, 2, oracle.ext_elementwise(2, 2, "mul", [ca], [cb]))[0]
+            want = 0 if 0 in (a, b) else (b if a == 1 else a if b == 1 else table[(a, b)])
+            assert got == want, (a, b)
+            # addition in characteristic 2 is XOR of the coefficient bits
+            s = oracle.ext_decode(2, 2, oracle.ext_elementwise(2, 2, "add", [ca], [cb]))[0]
+            assert s == a ^ b
+
+
+@pytest.mark.parametrize("p,d", [(2, 3), (3, 2), (3, 3), (5, 2), (2, 5), (7, 2)])
+def test_ext_field_axioms(p, d):
+    """Over every element of small extension fields: codes round-trip, the
+    code q-1 is 1 and code 1 is X; every nonzero element times its inverse
+    is 1; a(b + c) = ab + ac and (a + b)^p = a^p + b^p (Frobenius) on all
+    triples / pairs; x - x = 0 and x + (-x) = 0."""
+    q = p ** d
+    codes = np.arange(q, dtype=np.uint16)
+    vals = oracle.ext_decode(p, d, codes)
+    assert sorted(vals.tolist()) == list(range(q))
+    assert (oracle.ext_encode(p, d, vals) == codes).all()
+    assert vals[q - 1] == 1 and vals[1] == p
+    ew = lambda op, x, y=None: oracle.ext_elementwise(p, d, op, x, y)
+    one = np.full(q - 1, q - 1, dtype=np.uint16)
+    nz = codes[1:]
+    assert (ew("mul", nz, ew("div", one, nz)) == q - 1).all()
+    assert (ew("sub", codes, codes) == 0).all()
+    assert (ew("add", codes, ew("neg", codes)) == 0).all()
+    A, B, C = np.meshgrid(codes, codes, codes, indexing="ij") if q <= 27 else \
+        (synth.uniform_int(14, k, 4000, q).astype(np.uint16) for k in range(3))
+    A, B, C = (np.ascontiguousarray(t.reshape(-1).astype(np.uint16)) for t in (A, B, C))
+    assert (ew("mul", A, ew("add", B, C)) == ew("add", ew("mul", A, B), ew("mul", A, C))).all()
+
+    def pw(x, e):
+        r = np.full(x.size, q - 1, dtype=np.uint16)
+        for _ in range(e):
+            r = ew("mul", r, x)
+        return r
+    assert (pw(ew("add", A, B), p) == ew("add", pw(A, p), pw(B, p))).all()
+
+
+def test_ext_dot_against_elementwise_and_bruteforce():
+    """The dot product equals the sum of elementwise products, and over GF(4)
+    it matches a Python sum of the multiplication table, for every pair of
+    vectors of length 2."""
+    p, d = 3, 4
+    q = p ** d
+    x = synth.uniform_int(15, 0, 777, q).astype(np.uint16)
+    y = synth.uniform_int(15, 1, 777, q).astype(np.uint16)
+    prods = oracle.ext_elementwise(p, d, "mul", x, y)
+    acc = np.zeros(1, dtype=np.uint16)
+    for c in prods:
+        acc = oracle.ext_elementwise(p, d, "add", acc, [c])
+    assert oracle.ext_dot(p, d, x, y) == acc[0]
+    assert oracle.ext_dot(p, d, [], []) == 0
+    mul4 = {(2, 2): 3, (2, 3): 1, (3, 3): 2, (3, 2): 1}
+
+    def m(a, b):
+        return 0 if 0 in (a, b) else (b if a == 1 else a if b == 1 else mul4[(a, b)])
+    for x0, x1, y0, y1 in itertools.product(range(4), repeat=4):
+        want = m(x0, y0) ^ m(x1, y1)
+        cx = oracle.ext_encode(2, 2, [x0, x1])
+        cy = oracle.ext_encode(2, 2, [y0, y1])
+        assert oracle.ext_decode(2, 2, [oracle.ext_dot(2, 2, cx, cy)])[0] == want
