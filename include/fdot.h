@@ -138,6 +138,10 @@ typedef struct {
   uint32_t reserved;
   double inv_p;              /* 1.0/p rounded to nearest */
   uint64_t table_bytes;      /* device bytes held by the field's tables */
+  uint32_t degree;           /* d: the field has q = p^d elements (1: prime field) */
+  uint32_t reserved2;
+  uint64_t q;                /* p^d */
+  uint64_t modulus;          /* d > 1: the modulus polynomial f as f(p) */
 } fdot_field_info_t;
 
 /* One instance of a batched dot product (device-resident array). */
@@ -209,6 +213,21 @@ fdot_status_t fdot_field_create(uint64_t p, fdot_rep_t rep, fdot_field_t* out);
  * FDOT_E_UNSUPPORTED. */
 fdot_status_t fdot_field_create_host(uint64_t p, fdot_rep_t rep, fdot_field_t* out);
 fdot_status_t fdot_field_destroy(fdot_field_t f);
+
+/* GF(q), q = p^d with d >= 2 and q <= 65536, in the discrete-logarithm
+ * representation (Sec. 2.4.2: the representation is unchanged for field
+ * extensions, where the classical one would need polynomial arithmetic).
+ * An element is a polynomial c_0 + c_1 X + ... + c_{d-1} X^{d-1} over GF(p);
+ * its canonical value (fdot_encode / fdot_decode) is the integer
+ * c_0 + c_1 p + ... + c_{d-1} p^{d-1}.  Arithmetic is modulo the monic
+ * primitive polynomial f of degree d whose lower coefficients, read the same
+ * way, are smallest; the generator is the class of X, and codes are as for
+ * prime fields (0 = zero, i = X^i, q-1 = 1).  Supported: encode, decode,
+ * fdot_modp (plus-one table accumulation; FDOT_ALGO_AUTO or
+ * FDOT_ALGO_ZECH_TPLUS1) and fdot_elementwise; the batched and matrix forms
+ * return FDOT_E_UNSUPPORTED.  FDOT_E_NOT_PRIME / FDOT_E_BOUND for a p that
+ * is not prime or a q out of range. */
+fdot_status_t fdot_field_create_ext(uint64_t p, uint32_t d, fdot_field_t* out);
 fdot_status_t fdot_field_info(fdot_field_t f, fdot_field_info_t* out);
 
 /* Conversions (Sec. 2; untimed by the paper's convention, Sec. 3).

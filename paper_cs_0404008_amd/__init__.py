@@ -44,10 +44,12 @@ class FieldInfo(ctypes.Structure):
                 ("recip", ctypes.c_uint32), ("n_im", ctypes.c_uint32), ("b_mod_p", ctypes.c_uint32),
                 ("binv_mod_p", ctypes.c_uint32), ("b2_mod_p", ctypes.c_uint32),
                 ("g", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("inv_p", ctypes.c_double),
-                ("table_bytes", ctypes.c_uint64)]
+                ("table_bytes", ctypes.c_uint64), ("degree", ctypes.c_uint32),
+                ("reserved2", ctypes.c_uint32), ("q", ctypes.c_uint64), ("modulus", ctypes.c_uint64)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_
+                if name not in ("reserved", "reserved2")}
 
 
 _u64, _sz, _vp, _i32, _i64 = (ctypes.c_uint64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int,
@@ -70,6 +72,7 @@ _sig("fdot_choose_rep", [_u64, _u64, ctypes.POINTER(_i32)])
 _sig("fdot_host_fold", [ctypes.POINTER(FieldInfo), _i32, _u64, ctypes.POINTER(_u64)])
 _sig("fdot_zech_tables", [_u64, _vp, _vp, _vp])
 _sig("fdot_field_create", [_u64, _i32, ctypes.POINTER(_vp)])
+_sig("fdot_field_create_ext", [_u64, ctypes.c_uint32, ctypes.POINTER(_vp)])
 _sig("fdot_field_create_host", [_u64, _i32, ctypes.POINTER(_vp)])
 _sig("fdot_field_destroy", [_vp])
 _sig("fdot_field_info", [_vp, ctypes.POINTER(FieldInfo)])
@@ -186,13 +189,19 @@ def workspace_reserve(count: int, stream=None) -> None:
 
 # ---------------------------------------------------------------------- field
 class Field:
-    """GF(p) in one representation; the handle owns the device tables."""
+    """GF(p) in one representation, or GF(p^degree) in discrete logarithms
+    (rep "zech", degree >= 2); the handle owns the device tables."""
 
-    def __init__(self, p: int, rep: str = "zpz", host_only: bool = False):
+    def __init__(self, p: int, rep: str = "zpz", host_only: bool = False, degree: int = 1):
         self.p = int(p)
         self.rep = rep
         h = _vp()
-        if host_only:  # constants only, no GPU (compute calls are refused)
+        if degree > 1:
+            if rep != "zech" or host_only:
+                raise ValueError("extension fields are held in discrete logarithms on the device")
+            _check(_lib.fdot_field_create_ext(self.p, degree, ctypes.byref(h)),
+                   "fdot_field_create_ext")
+        elif host_only:  # constants only, no GPU (compute calls are refused)
             _check(_lib.fdot_field_create_host(self.p, REPS[rep], ctypes.byref(h)),
                    "fdot_field_create_host")
         else:

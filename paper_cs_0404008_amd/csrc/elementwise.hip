@@ -75,7 +75,9 @@ struct RF64 {
   static __device__ bool is_zero(E a) { return a == 0.0; }
 };
 
-// Codes: 0 is the zero element, i in [1, q-1] is g^i (q-1 codes the element 1).
+// Codes: 0 is the zero element, i in [1, q-1] is g^i (q-1 codes the element 1);
+// the same for prime fields and for extensions GF(p^d) (Sec. 2.4.2), whose
+// constants hold q in place of p.
 struct RZech {
   using E = uint16_t;
   static __device__ E zero() { return 0; }
@@ -93,9 +95,10 @@ struct RZech {
   static __device__ E div(E a, E b, const FieldK& F) {
     return (a == 0 || b == 0) ? (E)0 : idx_sub(a, b, F);
   }
-  // -1 = g^((q-1)/2)
+  // -1 = g^((q-1)/2) in odd characteristic (half holds (q-1)/2); in
+  // characteristic 2, -1 = 1 and half holds 0
   static __device__ E neg(E a, const FieldK& F) {
-    return a == 0 ? (E)0 : idx_add(a, F.qbar / 2, F);
+    return a == 0 ? (E)0 : idx_add(a, (uint32_t)F.half, F);
   }
   static __device__ E add(E a, E b, const FieldK& F) {
     if (a == 0) return b;
@@ -255,7 +258,7 @@ fdot_status_t launch_op(const fdot_field_s* f, uint64_t n, const void* alpha, co
     // 1024 threads per workgroup, as many resident workgroups as the LDS
     // holds tables (160 KiB per CU), and no more than the work needs
     constexpr int NT = 1024;
-    const size_t lds = (size_t)f->info.p * sizeof(uint16_t);
+    const size_t lds = (size_t)f->k.p * sizeof(uint16_t);  // q entries
     const uint64_t per_cu = std::max<uint64_t>(1, (160u * 1024u) / lds);
     const unsigned grid = (unsigned)std::max<uint64_t>(
         1, std::min<uint64_t>((work + NT - 1) / NT, (uint64_t)fd_cu_count() * per_cu));

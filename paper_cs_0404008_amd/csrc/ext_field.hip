@@ -1,0 +1,124 @@
+// Dot products over extension fields GF(p^d), q = p^d <= 65536, in discrete
+// logarithms (Sec. 2.4.2): the representation stays atomic, so the per-term
+// work is the prime-field one -- a product is an index sum modulo q-1, a sum
+// goes through the plus-one table (Sec. 2.4, Table 1).  No code stands for a
+// residue mod p here, so partial sums are also combined by table addition:
+// eight independent accumulators per lane (one per 16-bit slot of a 16-byte
+// load, so consecutive terms do not wait on each other's table lookups),
+// then across the wavefront by shuffles, across the workgroup through LDS,
+// and across workgroups by a second, one-workgroup pass.  The plus-one table
+// (2q bytes) is copied into LDS by workgroups that stay resident.
+#include <algorithm>
+
+#include "fdot_internal.h"
+
+namespace {
+
+constexpr int NT = 1024;
+
+__device__ __forceinline__ uint32_t zmul(uint32_t a, uint32_t b, uint32_t qbar) {
+  if (a == 0 || b == 0) return 0;
+  const uint32_t k = a + b;
+  return k > qbar ? k - qbar : k;
+}
+
+// a + b = a (1 + b/a); tab[k] is the code of 1 + (element coded k)
+__device__ __forceinline__ uint32_t zadd(uint32_t a, uint32_t b, uint32_t qbar,
+                                         const uint16_t* tab) {
+  if (a == 0) return b;
+  if (b == 0) return a;
+  const uint32_t k = b > a ? b - a : b + qbar - a;  // code of b / a, in [1, q-1]
+  const uint32_t t = tab[k];
+  if (t == 0) return 0;
+  const uint32_t w = a + t;
+  return w > qbar ? w - qbar : w;
+}
+
+// Sum of the lane values of a workgroup of NT threads; valid in thread 0.
+__device__ uint32_t block_sum(uint32_t acc, uint32_t qbar, const uint16_t* tab, uint32_t* s_part) {
+  for (int off = 32; off > 0; off >>= 1) acc = zadd(acc, (uint32_t)__shfl_xor((int)acc, off), qbar, tab);
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  if (lane == 0) s_part[w] = acc;
+  __syncthreads();
+  uint32_t s = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NT / 64; ++i) s = zadd(s, s_part[i], qbar, tab);
+  return s;
+}
+
+__global__ __launch_bounds__(NT) void ext_dot_kernel(const FieldK F, const uint16_t* x,
+                                                     const uint16_t* y, uint64_t n, int vec,
+                                                     uint16_t* partial) {
+  extern __shared__ uint16_t s_tab[];
+  __shared__ uint32_t s_part[NT / 64];
+  for (uint32_t i = threadIdx.x; i < (uint32_t)F.p; i += NT) s_tab[i] = F.zplus1[i];
+  __syncthreads();
+  const uint32_t qbar = F.qbar;
+  const uint64_t tid = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * NT;
+  uint32_t z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint64_t done = 0;
+  if (vec) {
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    const uint64_t nv = n / 8;
+    for (uint64_t v = tid; v < nv; v += stride) {
+      const v4u a = __builtin_nontemporal_load((const v4u*)x + v);
+      const v4u b = __builtin_nontemporal_load((const v4u*)y + v);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        z[2 * j] = zadd(z[2 * j], zmul(a[j] & 0xFFFFu, b[j] & 0xFFFFu, qbar), qbar, s_tab);
+        z[2 * j + 1] = zadd(z[2 * j + 1], zmul(a[j] >> 16, b[j] >> 16, qbar), qbar, s_tab);
+      }
+    }
+    done = nv * 8;
+  }
+  for (uint64_t i = done + tid; i < n; i += stride) z[0] = zadd(z[0], zmul(x[i], y[i], qbar), qbar, s_tab);
+  uint32_t acc = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc = zadd(acc, z[j], qbar, s_tab);
+  const uint32_t s = block_sum(acc, qbar, s_tab, s_part);
+  if (threadIdx.x == 0) partial[blockIdx.x] = (uint16_t)s;
+}
+
+// The partials live in the stream's workspace, whose combination words the
+// prime-field dot kernels expect to find zero: each is cleared once read.
+__global__ __launch_bounds__(NT) void ext_sum_kernel(const FieldK F, uint16_t* partial,
+                                                     uint32_t count, uint16_t* result) {
+  __shared__ uint32_t s_part[NT / 64];
+  uint32_t acc = 0;
+  for (uint32_t i = threadIdx.x; i < count; i += NT) {
+    acc = zadd(acc, partial[i], F.qbar, F.zplus1);
+    partial[i] = 0;
+  }
+  const uint32_t s = block_sum(acc, F.qbar, F.zplus1, s_part);
+  if (threadIdx.x == 0) result[0] = (uint16_t)s;
+}
+
+}  // namespace
+
+fdot_status_t fd_launch_ext_dot(const fdot_field_s* f, const uint16_t* x, const uint16_t* y,
+                                uint64_t n, uint16_t* result, hipStream_t s) {
+  const uint64_t q = f->k.p;
+  const size_t lds = (size_t)q * sizeof(uint16_t);
+  const uint64_t per_cu = std::max<uint64_t>(1, (160u * 1024u) / (lds + 1024));
+  const bool vec = ((((uintptr_t)x) | ((uintptr_t)y)) & 15u) == 0;
+  const uint64_t work = vec ? n / 8 + 1 : n;
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>((work + NT - 1) / NT, (uint64_t)fd_cu_count() * per_cu));
+  Workspace* w = nullptr;
+  fdot_status_t st = fd_workspace_get(s, grid, &w);  // one 64-bit word per workgroup
+  if (st != FDOT_OK) return st;
+  uint16_t* partial = (uint16_t*)w->acc;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)ext_dot_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    attr_set = true;
+  }
+  if (n > 0)
+    hipLaunchKernelGGL(ext_dot_kernel, dim3(grid), dim3(NT), lds, s, f->k, x, y, n, vec ? 1 : 0,
+                       partial);
+  hipLaunchKernelGGL(ext_sum_kernel, dim3(1), dim3(NT), 0, s, f->k, partial, n > 0 ? grid : 0u,
+                     result);
+  return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
+}

@@ -14,6 +14,7 @@ struct fdot_field_s {
   FieldK k;             // device-ready constants (table pointers on device)
   int device;
   bool host_only;       // constants only: no device tables, no compute
+  uint32_t degree;      // 1: GF(p); d > 1: GF(p^d) in discrete logs (k.p holds q)
   uint16_t* d_zval;     // Zech tables on the device (owned)
   uint16_t* d_zplus1;
   uint16_t* d_zidx;
@@ -77,6 +78,8 @@ fdot_status_t fd_launch_gemm(const fdot_field_s* f, size_t M, size_t N, size_t K
                              const void* A, size_t lda, const void* B, size_t ldb,
                              void* C, size_t ldc, hipStream_t s);
 fdot_status_t fd_launch_zero(void* ptr, size_t bytes, hipStream_t s);
+fdot_status_t fd_launch_ext_dot(const fdot_field_s* f, const uint16_t* x, const uint16_t* y,
+                                uint64_t n, uint16_t* result, hipStream_t s);
 fdot_status_t fd_launch_elementwise(const fdot_field_s* f, fdot_ew_op_t op, uint64_t n,
                                     const void* alpha, const void* x, const void* y, void* r,
                                     hipStream_t s);

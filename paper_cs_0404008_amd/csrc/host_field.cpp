@@ -159,6 +159,8 @@ fdot_status_t fd_fill_params(uint64_t p, fdot_rep_t rep, fdot_field_info_t* out)
       if (p < 3 || p > 255) return FDOT_E_BOUND;  // odd p, |a| <= 127
       break;
   }
+  I.degree = 1;
+  I.q = p;
   *out = I;
   return FDOT_OK;
 }
@@ -317,6 +319,7 @@ fdot_status_t fdot_field_create(uint64_t p, fdot_rep_t rep, fdot_field_t* out) {
   if (!f) return FDOT_E_NOMEM;
   memset(f, 0, sizeof(*f));
   f->info = I;
+  f->degree = 1;
   fd_fieldk_from_info(&I, &f->k);
   if (hipGetDevice(&f->device) != hipSuccess) { delete f; return FDOT_E_DEVICE; }
   if (rep == FDOT_REP_ZECH_U16) {
@@ -338,6 +341,117 @@ fdot_status_t fdot_field_create(uint64_t p, fdot_rep_t rep, fdot_field_t* out) {
     f->k.zidx = f->d_zidx;
     f->k.zplus1 = f->d_zplus1;
   }
+  *out = f;
+  return FDOT_OK;
+}
+
+// GF(p^d) (Sec. 2.4.2).  Elements are coefficient vectors c_0..c_{d-1} over
+// GF(p), valued c_0 + c_1 p + ...; the powers of X are stepped like a linear
+// feedback shift register: multiplying by X shifts the coefficients up and
+// folds the overflowing top coefficient back with X^d = -(f_0 + ... +
+// f_{d-1} X^{d-1}).  A candidate modulus is primitive exactly when this
+// sequence first returns to 1 after q-1 steps.
+namespace {
+struct ExtStepper {
+  uint64_t p;
+  int d;
+  uint32_t f[16];
+  uint32_t c[16];
+  uint64_t value() const {
+    uint64_t v = 0;
+    for (int i = d - 1; i >= 0; --i) v = v * p + c[i];
+    return v;
+  }
+  void times_x() {
+    const uint64_t top = c[d - 1];
+    for (int i = d - 1; i > 0; --i) c[i] = c[i - 1];
+    c[0] = 0;
+    if (top)
+      for (int i = 0; i < d; ++i) c[i] = (uint32_t)((c[i] + (p - top) * f[i]) % p);
+  }
+};
+}  // namespace
+
+fdot_status_t fdot_field_create_ext(uint64_t p, uint32_t d, fdot_field_t* out) {
+  if (!out) return FDOT_E_INVALID_ARG;
+  *out = nullptr;
+  if (d < 2 || d > 16) return FDOT_E_BOUND;
+  if (!fd_is_prime_u64(p)) return FDOT_E_NOT_PRIME;
+  uint64_t q = 1;
+  for (uint32_t i = 0; i < d; ++i) {
+    q *= p;
+    if (q > 65536) return FDOT_E_BOUND;  // codes 0..q-1 in 16 bits
+  }
+  ExtStepper st{};
+  st.p = p;
+  st.d = (int)d;
+  uint64_t low = 0;
+  bool found = false;
+  for (; low < q && !found; ++low) {
+    uint64_t t = low;
+    for (uint32_t i = 0; i < d; ++i) { st.f[i] = (uint32_t)(t % p); t /= p; }
+    if (st.f[0] == 0) continue;  // X divides the candidate
+    for (uint32_t i = 0; i < d; ++i) st.c[i] = 0;
+    st.c[0] = 1;
+    uint64_t k = 0;
+    do { st.times_x(); ++k; } while (st.value() != 1 && k < q);
+    found = (k == q - 1);
+  }
+  if (!found) return FDOT_E_BOUND;
+  --low;
+  uint16_t* h = new (std::nothrow) uint16_t[3 * q];
+  if (!h) return FDOT_E_NOMEM;
+  uint16_t *val = h, *idx = h + q, *plus1 = h + 2 * q;
+  val[0] = 0;
+  idx[0] = 0;
+  for (uint32_t i = 0; i < d; ++i) st.c[i] = 0;
+  st.c[0] = 1;
+  for (uint64_t i = 1; i <= q - 1; ++i) {
+    st.times_x();
+    const uint64_t v = st.value();
+    val[i] = (uint16_t)v;
+    idx[v] = (uint16_t)i;
+  }
+  // plus1[k] = code of 1 + (element coded k): add 1 to the constant coefficient
+  for (uint64_t k = 0; k <= q - 1; ++k) {
+    const uint64_t v = k == 0 ? 0 : val[k];
+    const uint64_t c0 = v % p;
+    plus1[k] = idx[v - c0 + (c0 + 1) % p];
+  }
+  fdot_field_s* f = new (std::nothrow) fdot_field_s;
+  if (!f) { delete[] h; return FDOT_E_NOMEM; }
+  memset(f, 0, sizeof(*f));
+  f->info.p = p;
+  f->info.rep = FDOT_REP_ZECH_U16;
+  f->info.elem_bytes = 2;
+  f->info.table_bytes = 3ull * q * sizeof(uint16_t);
+  f->info.degree = d;
+  f->info.q = q;
+  uint64_t pd = 1;
+  for (uint32_t i = 0; i < d; ++i) pd *= p;
+  f->info.modulus = pd + low;
+  f->degree = d;
+  // kernel constants: codes modulo q-1; -1 = X^((q-1)/2) in odd
+  // characteristic, -1 = 1 (negation is the identity) in characteristic 2
+  f->k.p = q;
+  f->k.p32 = (uint32_t)q;
+  f->k.qbar = (uint32_t)(q - 1);
+  f->k.half = (p & 1) ? (int32_t)((q - 1) / 2) : 0;
+  if (hipGetDevice(&f->device) != hipSuccess) { delete[] h; delete f; return FDOT_E_DEVICE; }
+  uint16_t* dev = nullptr;
+  if (hipMalloc((void**)&dev, 3 * q * sizeof(uint16_t)) != hipSuccess) {
+    delete[] h; delete f; return FDOT_E_NOMEM;
+  }
+  if (hipMemcpy(dev, h, 3 * q * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(dev); delete[] h; delete f; return FDOT_E_DEVICE;
+  }
+  delete[] h;
+  f->d_zval = dev;
+  f->d_zidx = dev + q;
+  f->d_zplus1 = dev + 2 * q;
+  f->k.zval = f->d_zval;
+  f->k.zidx = f->d_zidx;
+  f->k.zplus1 = f->d_zplus1;
   *out = f;
   return FDOT_OK;
 }
@@ -371,6 +485,7 @@ extern "C" fdot_status_t fdot_field_create_host(uint64_t p, fdot_rep_t rep, fdot
   fd_fieldk_from_info(&I, &f->k);
   f->device = -1;
   f->host_only = true;
+  f->degree = 1;
   *out = f;
   return FDOT_OK;
 }

@@ -238,6 +238,11 @@ fdot_status_t fdot_modp_algo(fdot_field_t f, fdot_algo_t algo, const void* x, co
   const size_t es = f->info.elem_bytes;
   if (!aligned_to(result, es)) return FDOT_E_INVALID_ARG;
   if (n && (!x || !y || !aligned_to(x, es) || !aligned_to(y, es))) return FDOT_E_INVALID_ARG;
+  if (f->degree > 1) {  // GF(p^d): plus-one table accumulation only
+    if (algo != FDOT_ALGO_AUTO && algo != FDOT_ALGO_ZECH_TPLUS1) return FDOT_E_UNSUPPORTED;
+    return fd_launch_ext_dot(f, (const uint16_t*)x, (const uint16_t*)y, n, (uint16_t*)result,
+                             (hipStream_t)stream);
+  }
   Workspace* w = nullptr;
   fdot_status_t st = fd_workspace_get((hipStream_t)stream, 1, &w);
   if (st != FDOT_OK) return st;
@@ -254,6 +259,7 @@ fdot_status_t fdot_modp_many_algo(fdot_field_t f, fdot_algo_t algo, size_t count
   if (!f) return FDOT_E_INVALID_ARG;
   if (f->host_only) return FDOT_E_UNSUPPORTED;
   if ((int)algo < FDOT_ALGO_AUTO || (int)algo > FDOT_ALGO_HYBRID) return FDOT_E_INVALID_ARG;
+  if (f->degree > 1) return FDOT_E_UNSUPPORTED;
   if (count == 0) return FDOT_OK;
   if (!desc || !results || !aligned_to(desc, 8) || !aligned_to(results, f->info.elem_bytes))
     return FDOT_E_INVALID_ARG;
@@ -273,6 +279,7 @@ fdot_status_t fgemv_modp(fdot_field_t f, size_t m, size_t n, const void* A, size
                          const void* x, void* y, void* stream) {
   if (!f) return FDOT_E_INVALID_ARG;
   if (f->host_only) return FDOT_E_UNSUPPORTED;
+  if (f->degree > 1) return FDOT_E_UNSUPPORTED;
   if (m == 0) return FDOT_OK;
   const size_t es = f->info.elem_bytes;
   if (!A || !y || (n && !x) || lda < n) return FDOT_E_INVALID_ARG;
@@ -285,6 +292,7 @@ fdot_status_t fgemm_modp(fdot_field_t f, size_t M, size_t N, size_t K, const voi
                          const void* B, size_t ldb, void* C, size_t ldc, void* stream) {
   if (!f) return FDOT_E_INVALID_ARG;
   if (f->host_only) return FDOT_E_UNSUPPORTED;
+  if (f->degree > 1) return FDOT_E_UNSUPPORTED;
   if (M == 0 || N == 0) return FDOT_OK;
   const size_t es = f->info.elem_bytes;
   if (!C || ldc < N || (K && (!A || !B || lda < K || ldb < N))) return FDOT_E_INVALID_ARG;

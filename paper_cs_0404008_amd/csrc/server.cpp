@@ -458,6 +458,7 @@ fdot_status_t fdot_server_submit(fdot_server_t s, const fdot_request_t* req, uin
   if (!s || !req || !ticket || !req->field) return FDOT_E_INVALID_ARG;
   const fdot_request_t& r = *req;
   if (r.op < FDOT_OP_DOT || r.op > FDOT_OP_GEMM || !r.out) return FDOT_E_INVALID_ARG;
+  if (r.field->degree > 1) return FDOT_E_UNSUPPORTED;  // extension fields: not served
   if (r.op == FDOT_OP_DOT && r.n && (!r.a || !r.b)) return FDOT_E_INVALID_ARG;
   if (r.op == FDOT_OP_GEMV && (r.m == 0 || (r.n && (!r.a || !r.b)))) return FDOT_E_INVALID_ARG;
   if (r.op == FDOT_OP_GEMM && (r.m == 0 || r.n == 0 || (r.k && (!r.a || !r.b))))

@@ -1,0 +1,118 @@
+"""GPU parity of extension fields GF(p^d) in discrete logarithms (Sec. 2.4.2)
+against the oracle's polynomial arithmetic, bit for bit: the modulus, the
+code <-> value maps, dot products of ragged and misaligned lengths, the
+elementwise operations, and the refusal of the forms that are not built for
+extensions.  A prime-field dot product on the same stream after an extension
+one checks that the shared workspace is left as the prime-field kernels
+expect it."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_helpers import same, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+fd = pytest.importorskip("paper_cs_0404008_amd")
+
+EXT = [(2, 2), (2, 8), (2, 16), (3, 2), (3, 10), (5, 6), (7, 5), (251, 2)]
+OPS = ("add", "sub", "neg", "mul", "div", "axpy", "axpyin")
+
+_fields = {}
+
+
+def field(p, d):
+    if (p, d) not in _fields:
+        _fields[(p, d)] = fd.Field(p, "zech", degree=d)
+    return _fields[(p, d)]
+
+
+def codes(q, n, seed, stream):
+    return synth.uniform_int(seed, stream, n, q).astype(np.uint16)
+
+
+@pytest.mark.parametrize("p,d", EXT, ids=lambda v: str(v))
+def test_ext_constants_and_maps(p, d):
+    F = field(p, d)
+    q = p ** d
+    assert F.info["degree"] == d and F.info["q"] == q and F.info["p"] == p
+    assert F.info["modulus"] == oracle.ext_modulus(p, d)
+    values = np.arange(q, dtype=np.uint32)
+    enc = to_host(F.encode(to_dev(values)))
+    assert same(enc, oracle.ext_encode(p, d, values))
+    dec = to_host(F.decode(to_dev(enc)))
+    assert same(dec, values)
+
+
+@pytest.mark.parametrize("p,d", EXT, ids=lambda v: str(v))
+def test_ext_dot_matches_oracle(p, d):
+    F = field(p, d)
+    q = p ** d
+    for n in (0, 1, 7, 8, 9, 1000, 100003):
+        x = codes(q, n, 60 + n % 5, 0)
+        y = codes(q, n, 60 + n % 5, 1)
+        got = to_host(F.dot(to_dev(x), to_dev(y)))[0]
+        assert int(got) == oracle.ext_dot(p, d, x, y), (p, d, n)
+    # misaligned operands (element path) and the explicit plus-one schedule
+    n = 50001
+    x = codes(q, n + 1, 61, 0)
+    y = codes(q, n + 1, 61, 1)
+    xd, yd = to_dev(x), to_dev(y)
+    got = to_host(F.dot(xd[1:], yd[1:], algo="zech_tplus1"))[0]
+    assert int(got) == oracle.ext_dot(p, d, x[1:], y[1:])
+    with pytest.raises(fd.FdotError):
+        F.dot(xd, yd, algo="zech_exp")
+
+
+def test_ext_dot_large_and_workspace_left_clean():
+    p, d = 2, 16
+    F = field(p, d)
+    n = (1 << 22) + 5
+    x = codes(p ** d, n, 62, 0)
+    y = codes(p ** d, n, 62, 1)
+    got = to_host(F.dot(to_dev(x), to_dev(y)))[0]
+    assert int(got) == oracle.ext_dot(p, d, x, y)
+    # a prime-field dot on the same stream, whose combination words share the
+    # workspace the extension dot used for its partials
+    G = fd.Field(32749, "zpz")
+    u = synth.uniform_int(63, 0, 300001, 32749).astype(np.uint32)
+    v = synth.uniform_int(63, 1, 300001, 32749).astype(np.uint32)
+    for _ in range(3):
+        assert same(to_host(G.dot(to_dev(u), to_dev(v))), [oracle.dot(32749, "zpz", u, v)])
+        F.dot(to_dev(x[:1000]), to_dev(y[:1000]))
+
+
+@pytest.mark.parametrize("p,d", EXT, ids=lambda v: str(v))
+def test_ext_elementwise_matches_oracle(p, d):
+    F = field(p, d)
+    q = p ** d
+    n = 10007
+    x, y, r = (codes(q, n, 64, k) for k in range(3))
+    x[:4] = [0, q - 1, 1, 0]
+    y[:4] = [0, 0, q - 1, 1]                 # zero divisors among them
+    alpha = int(codes(q, 1, 64, 3)[0])
+    for op in OPS:
+        ins_y = y if op in ("add", "sub", "mul", "div", "axpy") else None
+        out = to_dev(r) if op == "axpyin" else None
+        got = F.elementwise(op, to_dev(x), to_dev(ins_y) if ins_y is not None else None,
+                            alpha=alpha if op in ("axpy", "axpyin") else None, out=out)
+        want = oracle.ext_elementwise(p, d, op, x, ins_y, alpha if op in ("axpy", "axpyin") else None,
+                                      r if op == "axpyin" else None)
+        assert same(to_host(got), want), (p, d, op)
+
+
+def test_ext_unsupported_forms():
+    F = field(3, 2)
+    x = torch.zeros(16, dtype=torch.uint16, device="cuda")
+    with pytest.raises(fd.FdotError):
+        F.dot_many(fd.Field.make_desc([x], [x]))
+    with pytest.raises(fd.FdotError):
+        F.gemm(x.reshape(4, 4), x.reshape(4, 4))
+    with pytest.raises(fd.FdotError):
+        F.gemv(x.reshape(4, 4), x[:4])
+    with pytest.raises(fd.FdotError):
+        fd.Field(2, "zech", degree=17)         # q > 65536
+    with pytest.raises(fd.FdotError):
+        fd.Field(4, "zech", degree=2)          # p not prime
