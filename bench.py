@@ -386,6 +386,32 @@ def extras_elementwise(fd):
     return out
 
 
+def extras_ext_fields(fd):
+    """Dot products over extension fields in discrete logarithms (Sec. 2.4.2)
+    at 2^28 codes per operand (1 GiB per call): GF(2^8), GF(3^10), GF(2^16),
+    against the prime field GF(65521) in the same representation."""
+    import synth
+    n = 1 << 28
+    out = {}
+    for p, d in [(2, 8), (3, 10), (2, 16), (65521, 1)]:
+        F = fd.Field(p, "zech", degree=d)
+        q = p ** d
+        x = torch.empty(n, dtype=torch.uint16, device="cuda")
+        y = torch.empty(n, dtype=torch.uint16, device="cuda")
+        synth.fill_device(x, 11, 0, q, 0)
+        synth.fill_device(y, 11, 1, q, 0)
+        r = torch.empty(1, dtype=torch.uint16, device="cuda")
+        algo = "zech_tplus1"
+        F.dot(x, y, out=r, algo=algo)
+        t = time_events(lambda: F.dot(x, y, out=r, algo=algo), 3)
+        out[f"GF({p}^{d})" if d > 1 else f"GF({p}) plus-one"] = {
+            "ms": round(t * 1e3, 3), "gelem_per_s": round(n / t / 1e9, 1),
+            "GBps": round(4 * n / t / 1e9, 1)}
+        del x, y
+        torch.cuda.empty_cache()
+    return out
+
+
 SWEEP_PRIMES = (251, 4093, 32749, 65521, 1048573, 16777213, 67108859, 2147483647, 4294967291)
 
 
@@ -551,6 +577,9 @@ def main():
         torch.cuda.empty_cache()
         log("extras: elementwise ...")
         extras["elementwise"] = extras_elementwise(fd)
+        torch.cuda.empty_cache()
+        log("extras: extension fields ...")
+        extras["ext_fields"] = extras_ext_fields(fd)
         result["extras"] = extras
     print(json.dumps(result), flush=True)
 
