@@ -126,3 +126,53 @@ def test_graph_replays_are_independent_of_history():
         g.replay()
         torch.cuda.synchronize()
         assert same(to_host(out)[0], want), r
+
+
+@pytest.mark.parametrize("p,rep", [(65521, "zpz"), (2147483647, "mont"), (67108859, "fp64"),
+                                   (32749, "zech"), (251, "centred")])
+def test_graph_elementwise(p, rep):
+    """Every elementwise operation captured once and replayed on new inputs."""
+    F = fd.Field(p, rep)
+    n = 100_003
+    x = torch.empty(n, dtype=TD[rep], device="cuda")
+    y = torch.empty(n, dtype=TD[rep], device="cuda")
+    refill([x, y], p, rep, 699)
+    alpha = int(synth.uniform_int(5, 5, 1, *storage_range(p, rep))[0])
+    for op in ("add", "sub", "neg", "mul", "div", "axpy"):
+        kw = {"alpha": alpha} if op == "axpy" else {}
+        yy = None if op == "neg" else y
+        g, out = capture(lambda: F.elementwise(op, x, yy, **kw))
+
+        def want(xh, yh, op=op, kw=kw):
+            return oracle.elementwise(p, rep, op, xh, None if op == "neg" else yh, **kw)
+        replay_and_check(g, out, [x, y], p, rep, lambda: F.elementwise(op, x, yy, **kw), want)
+
+
+def test_graph_extension_field_dot():
+    """A dot product over GF(2^16) captured once and replayed; its partials
+    share the capture stream's workspace with the prime-field kernels, so a
+    prime-field dot is replayed in the same graph after it."""
+    E = fd.Field(2, "zech", degree=16)
+    P = fd.Field(32749, "zpz")
+    n = 300_007
+    x = torch.empty(n, dtype=torch.uint16, device="cuda")
+    y = torch.empty(n, dtype=torch.uint16, device="cuda")
+    u = torch.empty(n, dtype=torch.uint32, device="cuda")
+    v = torch.empty(n, dtype=torch.uint32, device="cuda")
+
+    def both():
+        return torch.cat([E.dot(x, y).to(torch.int64), P.dot(u, v).to(torch.int64)])
+    for r in range(REPLAYS):
+        synth.fill_device(x, 710 + r, 0, 1 << 16, 0)
+        synth.fill_device(y, 710 + r, 1, 1 << 16, 0)
+        synth.fill_device(u, 710 + r, 2, 32749, 0)
+        synth.fill_device(v, 710 + r, 3, 32749, 0)
+        torch.cuda.synchronize()
+        if r == 0:
+            g, out = capture(both)
+        out.fill_(0)
+        g.replay()
+        torch.cuda.synchronize()
+        got = to_host(out)
+        assert int(got[0]) == oracle.ext_dot(2, 16, to_host(x), to_host(y)), r
+        assert int(got[1]) == int(oracle.dot(32749, "zpz", to_host(u), to_host(v))), r
