@@ -383,6 +383,18 @@ def extras_elementwise(fd):
         out[f"{rep} p={p}"] = row
         del x, y, r
         torch.cuda.empty_cache()
+    # the framework's own elementwise add of int32 tensors of the same size
+    # (two reads, one write), timed only as the achievable rate of such a
+    # stream on this device
+    a = torch.zeros(n, dtype=torch.int32, device="cuda")
+    b = torch.zeros(n, dtype=torch.int32, device="cuda")
+    c = torch.empty(n, dtype=torch.int32, device="cuda")
+    torch.add(a, b, out=c)
+    t = time_events(lambda: torch.add(a, b, out=c), 3)
+    out["library_int32_add"] = {"ms": round(t * 1e3, 3), "GBps": round(12 * n / t / 1e9, 1),
+                                "frac_of_hbm": round(12 * n / t / 8e12, 3)}
+    del a, b, c
+    torch.cuda.empty_cache()
     return out
 
 
