@@ -151,6 +151,15 @@ typedef struct {
   uint64_t n;
 } fdot_desc_t;
 
+/* One instance of a batched dot product over one of several fields. */
+typedef struct {
+  const void* x;   /* device, n elements of the field's storage type */
+  const void* y;   /* device, n elements */
+  uint64_t n;
+  uint32_t field;  /* index into the call's array of fields */
+  uint32_t reserved;
+} fdot_mixed_desc_t;
+
 typedef struct fdot_field_s* fdot_field_t;
 
 /* ------------------------------------------------------------------ host only
@@ -277,6 +286,19 @@ fdot_status_t fdot_modp_many(fdot_field_t f, size_t count, const fdot_desc_t* de
                              void* results, void* stream);
 fdot_status_t fdot_modp_many_algo(fdot_field_t f, fdot_algo_t algo, size_t count,
                                   const fdot_desc_t* desc, void* results, void* stream);
+
+/* results[k] = dot of desc[k] over fields[desc[k].field], k < count: one batch
+ * over several primes (Sec. 1: the dot product as a building block; a request
+ * stream mixes fields).  fields is a host array of nfields prime fields of one
+ * representation (the results array has its element type); desc and results
+ * are device arrays.  For each field the batched path runs once with the
+ * other fields' pairs masked to length 0, and a merge keeps each pair's own
+ * result.  A pair whose field index is >= nfields has its result left
+ * unwritten.  FDOT_E_INVALID_ARG for mixed representations or an extension
+ * field. */
+fdot_status_t fdot_modp_many_mixed(size_t count, const fdot_mixed_desc_t* desc,
+                                   const fdot_field_t* fields, size_t nfields, void* results,
+                                   void* stream);
 
 /* ----------------------------------------------------------- matrix forms */
 

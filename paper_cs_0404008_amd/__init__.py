@@ -81,6 +81,7 @@ _sig("fdot_decode", [_vp, _vp, _vp, _sz, _vp])
 _sig("fdot_modp", [_vp, _vp, _vp, _sz, _vp, _vp])
 _sig("fdot_modp_algo", [_vp, _i32, _vp, _vp, _sz, _vp, _vp])
 _sig("fdot_elementwise", [_vp, _i32, _sz, _vp, _vp, _vp, _vp, _vp])
+_sig("fdot_modp_many_mixed", [_sz, _vp, _vp, _sz, _vp, _vp])
 _sig("fdot_modp_many", [_vp, _sz, _vp, _vp, _vp])
 _sig("fdot_modp_many_algo", [_vp, _i32, _sz, _vp, _vp, _vp])
 _sig("fgemv_modp", [_vp, _sz, _sz, _vp, _sz, _vp, _vp, _vp])
@@ -141,6 +142,33 @@ def max_prime(kind: str, bits: int) -> int:
     out = _u64()
     _check(_lib.fdot_max_prime(BOUNDS[kind], bits, ctypes.byref(out)), "fdot_max_prime")
     return out.value
+
+
+def make_mixed_desc(xs, ys, field_index, device=None) -> torch.Tensor:
+    """Device descriptor array {x, y, n, field} (fdot_mixed_desc_t) for a
+    batch over several fields."""
+    rows = []
+    for x, y, k in zip(xs, ys, field_index):
+        if x.numel() != y.numel():
+            raise ValueError("length mismatch")
+        rows.append([x.data_ptr(), y.data_ptr(), x.numel(), int(k)])
+    dev = device or (xs[0].device if len(xs) else "cuda")
+    return torch.tensor(rows, dtype=torch.int64).reshape(-1, 4).to(dev)
+
+
+def dot_many_mixed(fields, desc: torch.Tensor, out: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+    """fdot_modp_many_mixed: results[k] over fields[desc[k].field] (all of one
+    representation)."""
+    if desc.dtype != torch.int64 or desc.dim() != 2 or desc.shape[1] != 4 or not desc.is_cuda:
+        raise TypeError("desc must be a CUDA int64 tensor of shape [count, 4]")
+    count = desc.shape[0]
+    if out is None:
+        out = torch.empty(count, dtype=fields[0].dtype, device=desc.device)
+    handles = (_vp * max(len(fields), 1))(*[f.handle.value for f in fields])
+    _check(_lib.fdot_modp_many_mixed(count, _ptr(desc), handles, len(fields), _ptr(out),
+                                     _stream(stream)), "fdot_modp_many_mixed")
+    return out
 
 
 def choose_rep(p: int, n: int = 0) -> str:

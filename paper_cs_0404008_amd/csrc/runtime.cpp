@@ -270,6 +270,22 @@ fdot_status_t fdot_modp_many_algo(fdot_field_t f, fdot_algo_t algo, size_t count
   return fd_launch_many(f, algo, count, desc, results, w, (hipStream_t)stream);
 }
 
+fdot_status_t fdot_modp_many_mixed(size_t count, const fdot_mixed_desc_t* desc,
+                                   const fdot_field_t* fields, size_t nfields, void* results,
+                                   void* stream) {
+  if (!fields || nfields == 0 || nfields > 0xFFFFFFFFull) return FDOT_E_INVALID_ARG;
+  for (size_t i = 0; i < nfields; ++i) {
+    const fdot_field_t f = fields[i];
+    if (!f || f->degree > 1 || f->info.rep != fields[0]->info.rep) return FDOT_E_INVALID_ARG;
+    if (f->host_only) return FDOT_E_UNSUPPORTED;
+  }
+  if (count == 0) return FDOT_OK;
+  if (!desc || !results || !aligned_to(desc, 8) || !aligned_to(results, fields[0]->info.elem_bytes))
+    return FDOT_E_INVALID_ARG;
+  if (count > (1ull << 31)) return FDOT_E_INVALID_ARG;
+  return fd_launch_many_mixed(count, desc, fields, nfields, results, (hipStream_t)stream);
+}
+
 fdot_status_t fdot_modp_many(fdot_field_t f, size_t count, const fdot_desc_t* desc, void* results,
                              void* stream) {
   return fdot_modp_many_algo(f, FDOT_ALGO_AUTO, count, desc, results, stream);

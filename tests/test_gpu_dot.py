@@ -11,7 +11,8 @@ import torch
 
 import oracle
 import synth
-from tests.gpu_helpers import ELEM_BYTES, TORCH_DTYPES, same, stored, to_dev, to_host
+from tests.gpu_helpers import (ELEM_BYTES, NP_DTYPES as NP, TORCH_DTYPES, same, storage_range,
+                               stored, to_dev, to_host)
 
 pytestmark = pytest.mark.gpu
 
@@ -187,3 +188,40 @@ def test_encode_decode(p, rep):
     assert same(to_host(enc), oracle.encode(p, rep, canon.astype(np.uint64)))
     dec = F.decode(enc)
     assert same(to_host(dec), canon)
+
+
+@pytest.mark.parametrize("rep,primes", [("zpz", [32749, 65521, 4294967291, 2]),
+                                        ("mont", [2147483647, 65521, 32749]),
+                                        ("fp64", [67108859, 1048573])])
+def test_batched_over_several_fields(rep, primes):
+    """fdot_modp_many_mixed: one batch whose pairs name different primes of
+    one representation (uneven lengths, empty pairs), each result bit-exact
+    against the oracle over its own field; a pair naming no field keeps the
+    value already in its result slot."""
+    fields = [fd.Field(p, rep) for p in primes]
+    ns = [int(v) for v in synth.log_uniform_lengths(21, 0, 300, 0.0, 5.0)]
+    ns[:3] = [0, 1, 64]
+    which = synth.uniform_int(21, 1, len(ns), len(primes))
+    xs, ys, hx, hy = [], [], [], []
+    for k, (n, w) in enumerate(zip(ns, which)):
+        p = primes[int(w)]
+        m, lo = storage_range(p, rep)
+        a = synth.uniform_int(22, 2 * k, int(n), m, lo).astype(NP[rep])
+        b = synth.uniform_int(22, 2 * k + 1, int(n), m, lo).astype(NP[rep])
+        hx.append(a)
+        hy.append(b)
+        xs.append(to_dev(a))
+        ys.append(to_dev(b))
+    field_index = [int(w) for w in which]
+    field_index[5] = len(primes)  # names no field
+    desc = fd.make_mixed_desc(xs, ys, field_index)
+    out = torch.full((len(ns),), 7, dtype=fields[0].dtype, device="cuda")
+    got = to_host(fd.dot_many_mixed(fields, desc, out=out))
+    for k in range(len(ns)):
+        if k == 5:
+            assert got[k] == 7
+            continue
+        p = primes[field_index[k]]
+        assert same(got[k], oracle.dot(p, rep, hx[k], hy[k])), (k, p)
+    with pytest.raises(fd.FdotError):
+        fd.dot_many_mixed([fd.Field(32749, "zpz"), fd.Field(32749, "mont")], desc)
