@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <set>
 
 #include "fdot_internal.h"
 
@@ -33,23 +34,26 @@ __global__ void merge_kernel(const E* field_results, const fdot_mixed_desc_t* de
 
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, std::pair<void*, size_t>> g_buf;
+std::set<void*> g_captured;  // held by a captured graph: never freed
 
 fdot_status_t buffer_for(hipStream_t s, size_t bytes, void** out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return FDOT_E_DEVICE;
   std::lock_guard<std::mutex> g(g_mu);
   auto& e = g_buf[std::make_pair(dev, s)];
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const bool capturing =
+      hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
   if (e.second >= bytes) {
+    if (capturing) g_captured.insert(e.first);
     *out = e.first;
     return FDOT_OK;
   }
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
-    return FDOT_E_BUSY;  // growing allocates
+  if (capturing) return FDOT_E_BUSY;  // growing allocates
   bytes = std::max(bytes, e.second + e.second / 2);
   void* p = nullptr;
   if (fd_alloc_async(&p, bytes, s) != hipSuccess) return FDOT_E_NOMEM;
-  if (e.first) (void)hipFreeAsync(e.first, s);
+  if (e.first && !g_captured.count(e.first)) (void)hipFreeAsync(e.first, s);
   e = std::make_pair(p, bytes);
   *out = p;
   return FDOT_OK;
