@@ -890,6 +890,14 @@ uint64_t lambda_carried(uint64_t limit, uint64_t h, uint64_t carry) {
 // counterpart of the delayed reduction of Sec. 3.1 on matrix cores.
 constexpr uint64_t kSplitMaxHalf = 2139062143ull;  // 127 (1 + 2^8 + 2^16 + 2^24)
 
+// Residue of a stored value: uint32 residues and integral doubles as they
+// are, discrete-log codes (uint16) through the field's table of powers.
+template <typename E>
+__device__ __forceinline__ uint32_t stored_residue(E v, const FieldK& F) {
+  if constexpr (std::is_same<E, uint16_t>::value) return F.zval[v];
+  else return (uint32_t)v;
+}
+
 // Balanced base-256 digits needed for centred residues |c| <= h: D digits
 // in [-128, 127] reach 127 (256^D - 1) / 255.
 int split_digits(uint64_t h) {
@@ -927,7 +935,7 @@ __global__ __launch_bounds__(256) void digits_rows_kernel(const E* A, uint64_t l
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (k + q < K) {
-        balanced_digits((uint32_t)A[row * lda + k + q], F, d[q]);
+        balanced_digits(stored_residue(A[row * lda + k + q], F), F, d[q]);
       } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) d[q][i] = 0;
@@ -956,7 +964,7 @@ __global__ __launch_bounds__(256) void digits_cols_kernel(const E* B, uint64_t l
   const uint32_t k0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   for (uint32_t e = threadIdx.x; e < 64 * 64; e += 256) {
     const uint32_t r = e / 64, c = e % 64;  // r: k, c: n
-    t[r][c] = (k0 + r < K && n0 + c < N) ? (uint32_t)B[(uint64_t)(k0 + r) * ldb + n0 + c] : 0u;
+    t[r][c] = (k0 + r < K && n0 + c < N) ? stored_residue(B[(uint64_t)(k0 + r) * ldb + n0 + c], F) : 0u;
   }
   __syncthreads();
   const uint32_t r = threadIdx.x / 4, c = (threadIdx.x % 4) * 16;  // r: n, c: first k
@@ -985,6 +993,16 @@ __global__ __launch_bounds__(256) void zero_rows_kernel(uint32_t* C, uint64_t ld
     C[(e / N) * ldc + e % N] = 0u;
 }
 
+// C (M x N discrete-log codes, row stride ldc) = codes of Cu (dense residues).
+__global__ __launch_bounds__(256) void residues_to_codes_kernel(const FieldK F, const uint32_t* Cu,
+                                                                uint32_t M, uint32_t N,
+                                                                uint16_t* C, uint64_t ldc) {
+  const uint64_t total = (uint64_t)M * N;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * blockDim.x)
+    C[(e / N) * ldc + e % N] = F.zidx[Cu[e]];
+}
+
 // C (M x N integral doubles, row stride ldc) = Cu (M x N residues, dense).
 __global__ __launch_bounds__(256) void residues_to_f64_kernel(const uint32_t* Cu, uint32_t M,
                                                               uint32_t N, double* C, uint64_t ldc) {
@@ -999,10 +1017,11 @@ fdot_status_t gemm_split(const fdot_field_s* f, size_t M, size_t N, size_t K, co
                          hipStream_t s) {
   const fdot_field_info_t& I = f->info;
   const bool f64 = I.rep == FDOT_REP_FP64;  // doubles in and out; residues summed in scratch
+  const bool zech = I.rep == FDOT_REP_ZECH_U16;  // codes in and out; residues summed in scratch
   const uint32_t ldk = (uint32_t)((K + 63) / 64 * 64);
   const int nd = split_digits((I.p - 1) / 2);
   const size_t planes = (size_t)nd * ((size_t)M + N) * ldk + 256;
-  const size_t bytes = planes + (f64 ? (size_t)4 * M * N : 0);
+  const size_t bytes = planes + ((f64 || zech) ? (size_t)4 * M * N : 0);
   void* scr = nullptr;
   fdot_status_t st = scratch_for(s, bytes, &scr);
   if (st != FDOT_OK) return st;
@@ -1010,7 +1029,7 @@ fdot_status_t gemm_split(const fdot_field_s* f, size_t M, size_t N, size_t K, co
   int8_t* Bd = Ad + (size_t)nd * M * ldk;
   void* Cf = C;
   const size_t ldcf = ldc;
-  if (f64) {
+  if (f64 || zech) {
     C = (char*)scr + planes;
     ldc = N;
   }
@@ -1024,6 +1043,11 @@ fdot_status_t gemm_split(const fdot_field_s* f, size_t M, size_t N, size_t K, co
     hipLaunchKernelGGL(digits_rows_kernel<double>, dim3((unsigned)ag), dim3(256), 0, s,
                        (const double*)A, (uint64_t)lda, (uint32_t)M, (uint32_t)K, ldk, Ad, nd, f->k);
     hipLaunchKernelGGL(digits_cols_kernel<double>, cg, dim3(256), 0, s, (const double*)B,
+                       (uint64_t)ldb, (uint32_t)K, (uint32_t)N, ldk, Bd, nd, f->k);
+  } else if (zech) {
+    hipLaunchKernelGGL(digits_rows_kernel<uint16_t>, dim3((unsigned)ag), dim3(256), 0, s,
+                       (const uint16_t*)A, (uint64_t)lda, (uint32_t)M, (uint32_t)K, ldk, Ad, nd, f->k);
+    hipLaunchKernelGGL(digits_cols_kernel<uint16_t>, cg, dim3(256), 0, s, (const uint16_t*)B,
                        (uint64_t)ldb, (uint32_t)K, (uint32_t)N, ldk, Bd, nd, f->k);
   } else {
     hipLaunchKernelGGL(digits_rows_kernel<uint32_t>, dim3((unsigned)ag), dim3(256), 0, s,
@@ -1080,6 +1104,11 @@ fdot_status_t gemm_split(const fdot_field_s* f, size_t M, size_t N, size_t K, co
   if (f64) {
     hipLaunchKernelGGL(residues_to_f64_kernel, dim3(zg), dim3(256), 0, s, (const uint32_t*)C,
                        (uint32_t)M, (uint32_t)N, (double*)Cf, (uint64_t)ldcf);
+    if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
+  }
+  if (zech) {
+    hipLaunchKernelGGL(residues_to_codes_kernel, dim3(zg), dim3(256), 0, s, f->k,
+                       (const uint32_t*)C, (uint32_t)M, (uint32_t)N, (uint16_t*)Cf, (uint64_t)ldcf);
     if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
   }
   return FDOT_OK;
@@ -1202,6 +1231,18 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
 #undef FD_I8_SHAPE
 #undef FD_I8_LAUNCH
     return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
+  }
+  if (I.rep == FDOT_REP_ZECH_U16) {
+    // discrete logs: the digit products on the int8 matrix cores, from the
+    // codes' residues, above a size (tune key gemm.split.zech_min_work); the
+    // exact vector-ALU kernel below it
+    const bool ok = f->degree == 1 && K >= 1 && K <= kSplitMaxK - 63 && M > 0 && N > 0 &&
+                    fd_tune("gemm.split.disable", 0) == 0 &&
+                    (double)M * (double)N * (double)K >=
+                        (double)fd_tune("gemm.split.zech_min_work", 1ll << 24);
+    if (!ok) return FDOT_E_UNSUPPORTED;
+    *handled = true;
+    return gemm_split(f, M, N, K, A, lda, B, ldb, C, ldc, s);
   }
   if (I.rep != FDOT_REP_FP64 && I.rep != FDOT_REP_ZPZ_U32 && I.rep != FDOT_REP_MONT_U32)
     return FDOT_E_UNSUPPORTED;

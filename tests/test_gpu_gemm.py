@@ -248,23 +248,27 @@ def test_gemm_fp64_wave_layouts(waves):
 @pytest.mark.parametrize("p,rep", [(2147483647, "zpz"), (2147483647, "mont"), (4278124237, "zpz"),
                                    (2654435761, "mont"), (67108859, "fp64"), (67108859, "zpz"),
                                    (67108859, "mont"), (1048573, "fp64"), (65521, "zpz"),
-                                   (32749, "mont"), (32749, "zpz"), (251, "zpz")])
+                                   (32749, "mont"), (32749, "zpz"), (251, "zpz"),
+                                   (32749, "zech"), (65521, "zech"), (3, "zech")])
 @pytest.mark.parametrize("M,N,K,tiles", [(300, 260, 700, "auto"), (1030, 1100, 1000, "auto"),
                                          (1030, 1100, 1000, "large"), (40, 36, 131008, "auto")])
 def test_gemm_digit_split(p, rep, M, N, K, tiles):
     """Primes on the int8 matrix cores through D^2 digit products, D = 4, 3,
-    2 and 1 balanced base-256 digits by the size of p (the size threshold is
-    lowered so that every shape here takes them): ragged shapes, K not a
+    2 and 1 balanced base-256 digits by the size of p, discrete-log codes
+    included (the size thresholds are lowered so that every shape here takes
+    them): ragged shapes, K not a
     multiple of 64, the largest K without folds, the large-tile kernel and
     the small one; sampled entries against the oracle, maximal products
     included."""
     F = field(p, rep)
     fd.tune_set("gemm.split.min_work", 1)
+    fd.tune_set("gemm.split.zech_min_work", 1)
     fd.tune_set("gemm.split.small", 0 if tiles == "large" else None)
     try:
         _digit_split_case(F, p, rep, M, N, K)
     finally:
         fd.tune_set("gemm.split.min_work", None)
+        fd.tune_set("gemm.split.zech_min_work", None)
         fd.tune_set("gemm.split.small", None)
 
 
