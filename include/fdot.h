@@ -232,9 +232,9 @@ fdot_status_t fdot_field_destroy(fdot_field_t f);
  * primitive polynomial f of degree d whose lower coefficients, read the same
  * way, are smallest; the generator is the class of X, and codes are as for
  * prime fields (0 = zero, i = X^i, q-1 = 1).  Supported: encode, decode,
- * fdot_modp (plus-one table accumulation; FDOT_ALGO_AUTO or
- * FDOT_ALGO_ZECH_TPLUS1) and fdot_elementwise; the batched and matrix forms
- * return FDOT_E_UNSUPPORTED.  FDOT_E_NOT_PRIME / FDOT_E_BOUND for a p that
+ * fdot_modp and fdot_modp_many (plus-one table accumulation; FDOT_ALGO_AUTO
+ * or FDOT_ALGO_ZECH_TPLUS1) and fdot_elementwise; the matrix forms and
+ * fdot_modp_many_mixed return FDOT_E_UNSUPPORTED / FDOT_E_INVALID_ARG.  FDOT_E_NOT_PRIME / FDOT_E_BOUND for a p that
  * is not prime or a q out of range. */
 fdot_status_t fdot_field_create_ext(uint64_t p, uint32_t d, fdot_field_t* out);
 fdot_status_t fdot_field_info(fdot_field_t f, fdot_field_info_t* out);

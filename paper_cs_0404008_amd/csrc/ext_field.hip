@@ -7,7 +7,8 @@
 // load, so consecutive terms do not wait on each other's table lookups),
 // then across the wavefront by shuffles, across the workgroup through LDS,
 // and across workgroups by a second, one-workgroup pass.  The plus-one table
-// (2q bytes) is copied into LDS by workgroups that stay resident.
+// (2q bytes) is copied into LDS by workgroups that stay resident.  The
+// batched form gives whole pairs to resident workgroups in turn.
 #include <algorithm>
 
 #include "fdot_internal.h"
@@ -94,7 +95,65 @@ __global__ __launch_bounds__(NT) void ext_sum_kernel(const FieldK F, uint16_t* p
   if (threadIdx.x == 0) result[0] = (uint16_t)s;
 }
 
+// Batched form: resident workgroups take whole pairs in turn (pair k goes to
+// workgroup k mod grid), each reducing its pair with all its lanes and the
+// table copied into LDS once.
+__global__ __launch_bounds__(NT) void ext_many_kernel(const FieldK F, const fdot_desc_t* desc,
+                                                      uint64_t count, uint16_t* results) {
+  extern __shared__ uint16_t s_tab[];
+  __shared__ uint32_t s_part[NT / 64];
+  for (uint32_t i = threadIdx.x; i < (uint32_t)F.p; i += NT) s_tab[i] = F.zplus1[i];
+  __syncthreads();
+  const uint32_t qbar = F.qbar;
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  for (uint64_t k = blockIdx.x; k < count; k += gridDim.x) {
+    const fdot_desc_t d = desc[k];
+    const uint16_t* x = (const uint16_t*)d.x;
+    const uint16_t* y = (const uint16_t*)d.y;
+    uint32_t z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t done = 0;
+    if (((((uintptr_t)x) | ((uintptr_t)y)) & 15u) == 0) {
+      const uint64_t nv = d.n / 8;
+      for (uint64_t v = threadIdx.x; v < nv; v += NT) {
+        const v4u a = __builtin_nontemporal_load((const v4u*)x + v);
+        const v4u b = __builtin_nontemporal_load((const v4u*)y + v);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          z[2 * j] = zadd(z[2 * j], zmul(a[j] & 0xFFFFu, b[j] & 0xFFFFu, qbar), qbar, s_tab);
+          z[2 * j + 1] = zadd(z[2 * j + 1], zmul(a[j] >> 16, b[j] >> 16, qbar), qbar, s_tab);
+        }
+      }
+      done = nv * 8;
+    }
+    for (uint64_t i = done + threadIdx.x; i < d.n; i += NT)
+      z[0] = zadd(z[0], zmul(x[i], y[i], qbar), qbar, s_tab);
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc = zadd(acc, z[j], qbar, s_tab);
+    const uint32_t sum = block_sum(acc, qbar, s_tab, s_part);
+    if (threadIdx.x == 0) results[k] = (uint16_t)sum;
+    __syncthreads();  // s_part is reused by the next pair
+  }
+}
+
 }  // namespace
+
+fdot_status_t fd_launch_ext_many(const fdot_field_s* f, uint64_t count, const fdot_desc_t* desc,
+                                 uint16_t* results, hipStream_t s) {
+  const uint64_t q = f->k.p;
+  const size_t lds = (size_t)q * sizeof(uint16_t);
+  const uint64_t per_cu = std::max<uint64_t>(1, (160u * 1024u) / (lds + 1024));
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>(count, (uint64_t)fd_cu_count() * std::min<uint64_t>(per_cu, 2)));
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)ext_many_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(ext_many_kernel, dim3(grid), dim3(NT), lds, s, f->k, desc, count, results);
+  return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
+}
 
 fdot_status_t fd_launch_ext_dot(const fdot_field_s* f, const uint16_t* x, const uint16_t* y,
                                 uint64_t n, uint16_t* result, hipStream_t s) {

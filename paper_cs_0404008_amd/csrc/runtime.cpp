@@ -259,11 +259,14 @@ fdot_status_t fdot_modp_many_algo(fdot_field_t f, fdot_algo_t algo, size_t count
   if (!f) return FDOT_E_INVALID_ARG;
   if (f->host_only) return FDOT_E_UNSUPPORTED;
   if ((int)algo < FDOT_ALGO_AUTO || (int)algo > FDOT_ALGO_HYBRID) return FDOT_E_INVALID_ARG;
-  if (f->degree > 1) return FDOT_E_UNSUPPORTED;
+  if (f->degree > 1 && algo != FDOT_ALGO_AUTO && algo != FDOT_ALGO_ZECH_TPLUS1)
+    return FDOT_E_UNSUPPORTED;
   if (count == 0) return FDOT_OK;
   if (!desc || !results || !aligned_to(desc, 8) || !aligned_to(results, f->info.elem_bytes))
     return FDOT_E_INVALID_ARG;
   if (count > (1ull << 31)) return FDOT_E_INVALID_ARG;
+  if (f->degree > 1)
+    return fd_launch_ext_many(f, count, desc, (uint16_t*)results, (hipStream_t)stream);
   Workspace* w = nullptr;
   fdot_status_t st = fd_workspace_get((hipStream_t)stream, count, &w);
   if (st != FDOT_OK) return st;

@@ -1,10 +1,10 @@
 """GPU parity of extension fields GF(p^d) in discrete logarithms (Sec. 2.4.2)
 against the oracle's polynomial arithmetic, bit for bit: the modulus, the
 code <-> value maps, dot products of ragged and misaligned lengths, the
-elementwise operations, and the refusal of the forms that are not built for
-extensions.  A prime-field dot product on the same stream after an extension
-one checks that the shared workspace is left as the prime-field kernels
-expect it."""
+elementwise operations, the batched form, and the refusal of the forms that
+are not built for extensions.  A prime-field dot product on the same stream
+after an extension one checks that the shared workspace is left as the
+prime-field kernels expect it."""
 import numpy as np
 import pytest
 import torch
@@ -103,11 +103,34 @@ def test_ext_elementwise_matches_oracle(p, d):
         assert same(to_host(got), want), (p, d, op)
 
 
+@pytest.mark.parametrize("p,d", [(2, 16), (3, 2), (251, 2)])
+def test_ext_batched_dot_matches_oracle(p, d):
+    """The batched form over an extension field: uneven lengths (empty,
+    single, ragged, long), misaligned pairs, each result against the oracle."""
+    F = field(p, d)
+    q = p ** d
+    count = 200 if q <= 4096 else 30  # the oracle rebuilds its tables per pair
+    ns = [int(v) for v in synth.log_uniform_lengths(65, 0, count, 0.0, 4.5)]
+    ns[:4] = [0, 1, 9, 300001 if p == 2 else 20001]
+    xs, ys, hx, hy = [], [], [], []
+    for k, n in enumerate(ns):
+        off = k % 3  # some pairs start off the 16-byte grid
+        a = codes(q, n + off, 66, 2 * k)
+        b = codes(q, n + off, 66, 2 * k + 1)
+        xs.append(to_dev(a)[off:])
+        ys.append(to_dev(b)[off:])
+        hx.append(a[off:])
+        hy.append(b[off:])
+    got = to_host(F.dot_many(fd.Field.make_desc(xs, ys)))
+    for k in range(len(ns)):
+        assert int(got[k]) == oracle.ext_dot(p, d, hx[k], hy[k]), (p, d, k, ns[k])
+
+
 def test_ext_unsupported_forms():
     F = field(3, 2)
     x = torch.zeros(16, dtype=torch.uint16, device="cuda")
     with pytest.raises(fd.FdotError):
-        F.dot_many(fd.Field.make_desc([x], [x]))
+        F.dot_many(fd.Field.make_desc([x], [x]), algo="zech_exp")
     with pytest.raises(fd.FdotError):
         F.gemm(x.reshape(4, 4), x.reshape(4, 4))
     with pytest.raises(fd.FdotError):
