@@ -22,6 +22,9 @@ What is tuned:
   logarithms (Sec. 2.4);
 * the matrix-core tiling of ``fgemm_modp`` (``gemm.i8.tile``,
   ``gemm.f64.waves``);
+* the size above which ``fgemm_modp`` switches from the FP64 matrix cores to
+  int8 digit products, per digit count (``gemm.split.min_work.d<D>``), from
+  square products timed on both paths (``tune_split``);
 * the representation that ``fdot_choose_rep`` returns for each prime size
   (``auto.rep.b<bits>``): the Conclusion's install-time choice of the
   switching thresholds between representations, made here by timing the
@@ -151,6 +154,50 @@ def tune_gemm(field: Field, A: torch.Tensor, B: torch.Tensor, reps: int = 3):
     else:
         return {}, []
     return _search(lambda: field.gemm(A, B, out=C), lambda: C.cpu().numpy().copy(), cands, reps)
+
+
+def tune_split(cases=((32749, "zpz", torch.uint32), (1048573, "fp64", torch.float64),
+                       (67108859, "fp64", torch.float64)),
+               sizes=(256, 512, 768, 1024, 1536, 2048, 3072, 4096), reps: int = 3):
+    """Crossover of the FP64 matrix cores and the int8 digit products, per
+    digit count D: the smallest n such that the digit products are at least
+    as fast at every timed size from n up; writes n^3 as
+    gemm.split.min_work.d<D>.  Both paths must give the same bits."""
+    from synth import fill_device
+    settings, table = {}, []
+    for p, rep, dt in cases:
+        F = Field(p, rep)
+        h = (p - 1) // 2
+        d = 1 if h <= 127 else 2 if h <= 32639 else 3 if h <= 8355711 else 4
+        faster = []
+        for n in sizes:
+            A = torch.empty((n, n), dtype=dt, device="cuda")
+            B = torch.empty((n, n), dtype=dt, device="cuda")
+            fill_device(A, 12, 0, p, 0)
+            fill_device(B, 12, 1, p, 0)
+            C = torch.empty((n, n), dtype=dt, device="cuda")
+            times = {}
+            outs = {}
+            for path, kv in (("fp64", {"gemm.split.disable": 1}), ("digits", {"gemm.split.min_work": 1})):
+                with _Settings(kv):
+                    F.gemm(A, B, out=C)
+                    torch.cuda.synchronize()
+                    outs[path] = C.cpu().numpy().copy()
+                    times[path] = _time(lambda: F.gemm(A, B, out=C), reps)
+            if not np.array_equal(outs["fp64"], outs["digits"]):
+                raise RuntimeError(f"digit products changed the result at p={p} n={n}")
+            faster.append(times["digits"] <= times["fp64"])
+            table.append((p, rep, d, n, times["fp64"], times["digits"]))
+            del A, B, C
+            torch.cuda.empty_cache()
+        cross = None
+        for i in range(len(sizes)):
+            if all(faster[i:]):
+                cross = sizes[i]
+                break
+        if cross is not None:
+            settings[f"gemm.split.min_work.d{d}"] = cross ** 3
+    return settings, table
 
 
 def _is_prime(n: int) -> bool:
@@ -310,6 +357,11 @@ def main(argv=None) -> int:
                 f"{c} {t * 1e3:.3f} ms" for c, t in sorted(table, key=lambda x: x[1])))
             del A, B
             torch.cuda.empty_cache()
+        ssettings, stable = tune_split(sizes=(256, 512, 1024) if args.small else
+                                       (256, 512, 768, 1024, 1536, 2048, 3072, 4096))
+        settings.update(ssettings)
+        for p, rep, d, n, tf, tdig in stable:
+            log.append(f"split p={p} {rep} D={d} n={n}: fp64 {tf * 1e3:.3f} ms, digits {tdig * 1e3:.3f} ms")
     if not args.no_rep:
         bits = range(8, 33, 4) if args.small else range(8, 33)
         rsettings, rows = tune_representation(bits, (1 << 26) if args.small else (1 << 30))

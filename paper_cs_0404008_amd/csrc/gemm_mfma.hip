@@ -20,6 +20,7 @@
 //    assignment of k-slots works as long as A and B use the same one); its 16
 //    results are D[8(r/4) + 4(l/32) + r%4][l%32].
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -1268,14 +1269,18 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
   // gemm.split.min_work, in M*N*K; gemm.split.disable keeps the FP64 path).
   const bool split_ok = h <= kSplitMaxHalf && K >= 1 && K <= kSplitMaxK - 63 && M > 0 && N > 0 &&
                         fd_tune("gemm.split.disable", 0) == 0;
-  // Crossovers measured at square shapes: two digits (4 products) beat the
-  // FP64 cores from about 512^3, four digits (16 products, against FP64
-  // products folded every few terms) from about 1300^3, three digits (9
-  // products, against unfolded FP64 products) from about 2600^3.
+  // Crossovers measured at square shapes (the autotuner's split sweep): two
+  // digits (3 products per weight) and four digits (7, against FP64 products
+  // folded every few terms) beat the FP64 cores from about 512^3, three
+  // digits (5, against unfolded FP64 products) between 2048^3 and 3072^3.
   const int nd = split_digits(h);
-  const int64_t min_work = nd <= 2 ? (1ll << 27) : nd == 3 ? (1ll << 34) : (1ll << 31);
+  const int64_t min_work = nd == 3 ? (1ll << 34) : (1ll << 27);
+  // measured crossover for this digit count (autotuner), else the default;
+  // gemm.split.min_work overrides both
+  char key[32];
+  snprintf(key, sizeof key, "gemm.split.min_work.d%d", nd);
   const bool split_wins = (double)M * (double)N * (double)K >=
-                          (double)fd_tune("gemm.split.min_work", min_work);
+                          (double)fd_tune("gemm.split.min_work", fd_tune(key, min_work));
   if (split_ok && (lam < 4 || split_wins)) {
     *handled = true;
     return gemm_split(f, M, N, K, A, lda, B, ldb, C, ldc, s);

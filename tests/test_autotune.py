@@ -61,3 +61,5 @@ def test_autotune_small_workloads():
         synth.fill_device(B, 8, 1, m, lo)
         best, table = autotune.tune_gemm(F, A, B, reps=1)
         assert len(table) >= 3 and len(best) == 1
+    settings, table = autotune.tune_split(sizes=(256, 512), reps=1)
+    assert len(table) == 6 and all(k.startswith("gemm.split.min_work.d") for k in settings)
