@@ -631,14 +631,17 @@ __device__ __forceinline__ void lds_barrier() {
 // (no zero fill is possible on this path) and 16-byte rows; rows of A and
 // B^T past M and N are read from the last row and only reach outputs that
 // are not stored.
-template <int BJ, int NS, int NW, bool SPLIT = false>
+template <int BJ, int NS, int NW, bool SPLIT = false, int IKT = 64>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(BJ == 4 ? 1 : 2, BJ == 4 ? 1 : 2)))
 void gemm_i8_dma_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, const int8_t* A,
                         uint64_t lda, const int8_t* Bt, uint64_t ldbt, int8_t* C, uint64_t ldc,
                         uint32_t* Cu = nullptr, uint64_t wgt = 0) {
   // NW = 4 wavefronts as 2 x 2, or 8 as 2 x 4 (the workgroup tile twice as
   // wide); each wavefront a 128 x (32 BJ) sub-tile.
-  constexpr int IK = 64, TM = 256, TN = 64 * BJ * (NW / 4), WC = NW / 2;
+  // IKT = 64: rows of 64 bytes, four 16-byte chunks; IKT = 128: rows of
+  // 128 bytes (whole cache lines per row in every load), eight chunks.
+  constexpr int IK = IKT, TM = 256, TN = 64 * BJ * (NW / 4), WC = NW / 2;
+  constexpr int CH = IK / 16, RPI = 64 / CH;  // chunks per row, rows per load
   constexpr int SA = TM * IK, SB = TN * IK, SS = SA + SB;    // bytes per stage
   constexpr int NIA = SA / 1024 / NW, NIB = SB / 1024 / NW;  // DMA instructions per wave
   constexpr int PER = NIA + NIB;
@@ -650,22 +653,26 @@ void gemm_i8_dma_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, cons
   tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, &tm, &tn);
   const uint32_t m0 = tm * TM, n0 = tn * TN;
   const uint32_t wm = (w / WC) * 128, wn = (w % WC) * 32 * BJ;
-  // this lane's part of every DMA instruction: row lane/4 of a 16-row band,
-  // chunk position lane%4
-  const uint32_t lr = lane >> 2, lp = lane & 3u;
+  // this lane's part of every DMA instruction: row lane/CH of an RPI-row
+  // band, chunk position lane%CH; chunk c of row r is stored at position
+  // c ^ f(r), f(r) = (r/4) mod 4 for four chunks, (r/2) mod 8 for eight, so
+  // that any 16 lanes reading one chunk of 16 consecutive rows hit 16
+  // distinct 16-byte bank groups
+  const uint32_t lr = lane / CH, lp = lane % CH;
+  auto fsw = [](uint32_t r) -> uint32_t { return CH == 4 ? ((r >> 2) & 3u) : ((r >> 1) & 7u); };
   const uint8_t* gA[NIA];
   const uint8_t* gB[NIB];
 #pragma unroll
   for (int j = 0; j < NIA; ++j) {
-    const uint32_t r = 16 * (NIA * w + j) + lr;
+    const uint32_t r = RPI * (NIA * w + j) + lr;
     const uint32_t row = m0 + r < M ? m0 + r : M - 1;
-    gA[j] = (const uint8_t*)A + (uint64_t)row * lda + 16 * (lp ^ ((r >> 2) & 3u));
+    gA[j] = (const uint8_t*)A + (uint64_t)row * lda + 16 * (lp ^ fsw(r));
   }
 #pragma unroll
   for (int j = 0; j < NIB; ++j) {
-    const uint32_t r = 16 * (NIB * w + j) + lr;
+    const uint32_t r = RPI * (NIB * w + j) + lr;
     const uint32_t row = n0 + r < N ? n0 + r : N - 1;
-    gB[j] = (const uint8_t*)Bt + (uint64_t)row * ldbt + 16 * (lp ^ ((r >> 2) & 3u));
+    gB[j] = (const uint8_t*)Bt + (uint64_t)row * ldbt + 16 * (lp ^ fsw(r));
   }
   auto issue = [&](uint32_t t, uint32_t stage) {
     int8_t* base = s_dma + stage * SS;
@@ -681,7 +688,7 @@ void gemm_i8_dma_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, cons
           (const __attribute__((address_space(1))) void*)(gB[j] + k0),
           (__attribute__((address_space(3))) void*)(base + SA + 1024 * (NIB * w + j)), 16, 0, 0);
   };
-  auto swz = [](uint32_t r, uint32_t c) -> uint32_t { return (((c >> 4) ^ (r >> 2)) & 3u) << 4; };
+  auto swz = [&](uint32_t r, uint32_t c) -> uint32_t { return ((c >> 4) ^ fsw(r)) << 4; };
   v16i acc[4][BJ];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -1019,7 +1026,12 @@ fdot_status_t gemm_split(const fdot_field_s* f, size_t M, size_t N, size_t K, co
   const fdot_field_info_t& I = f->info;
   const bool f64 = I.rep == FDOT_REP_FP64;  // doubles in and out; residues summed in scratch
   const bool zech = I.rep == FDOT_REP_ZECH_U16;  // codes in and out; residues summed in scratch
-  const uint32_t ldk = (uint32_t)((K + 63) / 64 * 64);
+  // 256 x 256 direct-to-LDS tiles (K-tiles of 128, whole 128-byte rows per
+  // load) once they fill half the chip, else 128 x 128
+  const int64_t small = fd_tune("gemm.split.small", -1);
+  const bool big = M >= 256 && N >= 256 &&
+                   (small == 0 || (small < 0 && ((M + 255) / 256) * ((N + 255) / 256) >= 128));
+  const uint32_t ldk = (uint32_t)(big ? (K + 127) / 128 * 128 : (K + 63) / 64 * 64);
   const int nd = split_digits((I.p - 1) / 2);
   const size_t planes = (size_t)nd * ((size_t)M + N) * ldk + 256;
   const size_t bytes = planes + ((f64 || zech) ? (size_t)4 * M * N : 0);
@@ -1059,15 +1071,11 @@ fdot_status_t gemm_split(const fdot_field_s* f, size_t M, size_t N, size_t K, co
   if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
   const unsigned __int128 p = I.p;
   uint64_t base = I.rep == FDOT_REP_MONT_U32 ? I.binv_mod_p : 1;  // Montgomery: one factor B^-1
-  // 256 x 256 direct-to-LDS tiles once they fill half the chip, else 128 x 128
-  const int64_t small = fd_tune("gemm.split.small", -1);
-  const bool big = M >= 256 && N >= 256 &&
-                   (small == 0 || (small < 0 && ((M + 255) / 256) * ((N + 255) / 256) >= 128));
-  const size_t lds = (size_t)4 * (256 + 256) * 64;
+  const size_t lds = (size_t)2 * (256 + 256) * 128;
   if (big) {
     static bool attr_set = false;
     if (!attr_set) {
-      (void)hipFuncSetAttribute((const void*)gemm_i8_dma_kernel<2, 4, 8, true>,
+      (void)hipFuncSetAttribute((const void*)gemm_i8_dma_kernel<2, 2, 8, true, 128>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       attr_set = true;
     }
@@ -1089,7 +1097,7 @@ fdot_status_t gemm_split(const fdot_field_s* f, size_t M, size_t N, size_t K, co
       const uint32_t Kx = (uint32_t)cnt * ldk;
       if (big) {
         const uint64_t tiles = ((M + 255) / 256) * ((N + 255) / 256);
-        hipLaunchKernelGGL((gemm_i8_dma_kernel<2, 4, 8, true>), dim3((unsigned)tiles), dim3(512),
+        hipLaunchKernelGGL((gemm_i8_dma_kernel<2, 2, 8, true, 128>), dim3((unsigned)tiles), dim3(512),
                            lds, s, f->k, (uint32_t)M, (uint32_t)N, Kx, Ai, ld_all, Bj, ld_all,
                            (int8_t*)nullptr, (uint64_t)ldc, (uint32_t*)C, w);
       } else {
@@ -1129,15 +1137,16 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
     const uint64_t lam = lambda_carried(0x7FFFFFFFull, h, h);
     if (lam < 128 || fd_tune("gemm.i8.disable", 0)) return FDOT_E_UNSUPPORTED;
     *handled = true;
-    int64_t shape = fd_tune("gemm.i8.tile", M >= 1024 && N >= 1024 ? 7 : 2);
+    int64_t shape = fd_tune("gemm.i8.tile", M >= 1024 && N >= 1024 ? 8 : 2);
     // The direct-to-LDS tilings need K a multiple of 64 and 16-byte rows of A;
     // other shapes get zero-padded copies (zero terms leave every sum as it
     // is, so the fold bound still applies to the true K).
-    const uint64_t Kp = (K + 63) / 64 * 64;
-    const bool dma = (shape == 5 || shape == 6 || shape == 7) && K > 0 &&
+    const uint64_t kmul = shape == 8 ? 128 : 64;  // K-tile of the direct-to-LDS kernel
+    const uint64_t Kp = (K + kmul - 1) / kmul * kmul;
+    const bool dma = (shape >= 5 && shape <= 8) && K > 0 &&
                      (uint64_t)K <= (lam / 128) * 128 && M >= 256 && N >= 256 &&
                      Kp <= 0xFFFFFFFFull && fd_tune("gemm.i8.pad", 1) != 0;
-    const bool pad_a = dma && (K % 64 != 0 || lda % 16 != 0 || ((uintptr_t)A) % 16 != 0);
+    const bool pad_a = dma && (K % kmul != 0 || lda % 16 != 0 || ((uintptr_t)A) % 16 != 0);
     const uint64_t ldbt = dma ? Kp : K;
     void* bt = nullptr;
     fdot_status_t st =
@@ -1170,7 +1179,7 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
     // one that applies.
     // the large tile keeps its accumulators unfolded (only when K fits one fold
     // block) and needs 16-byte rows
-    if ((shape >= 3 && shape <= 7) &&
+    if ((shape >= 3 && shape <= 8) &&
         ((uint64_t)K > (lam / 128) * 128 || K % 16 != 0 || lda % 16 != 0 ||
                        ((uintptr_t)A) % 16 != 0 || M < 256 || N < 256))
       shape = 2;
@@ -1189,27 +1198,30 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
   if (shape == 2) { if (vec) FD_I8_LAUNCH(2, 2, KT, true); else FD_I8_LAUNCH(2, 2, KT, false); }  \
   else if (shape == 1) { if (vec) FD_I8_LAUNCH(4, 2, KT, true); else FD_I8_LAUNCH(4, 2, KT, false); } \
   else { if (vec) FD_I8_LAUNCH(4, 4, KT, true); else FD_I8_LAUNCH(4, 4, KT, false); }
-    if ((shape == 5 || shape == 6 || shape == 7) && K % 64 == 0) {
-#define FD_I8_DMA(BJ, NS, NW)                                                                      \
+    if ((shape >= 5 && shape <= 8) && K % kmul == 0) {
+#define FD_I8_DMA(BJ, NS, NW, IKT)                                                                 \
   {                                                                                                \
     constexpr int DTN = 64 * BJ * (NW / 4);                                                        \
-    const size_t lds = (size_t)NS * (256 + DTN) * 64;                                              \
+    const size_t lds = (size_t)NS * (256 + DTN) * IKT;                                             \
     static bool attr_set = false;                                                                  \
     if (!attr_set) {                                                                               \
-      (void)hipFuncSetAttribute((const void*)gemm_i8_dma_kernel<BJ, NS, NW>,                      \
+      (void)hipFuncSetAttribute((const void*)gemm_i8_dma_kernel<BJ, NS, NW, false, IKT>,          \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);             \
       attr_set = true;                                                                             \
     }                                                                                              \
     const uint64_t dma_tiles = ((M + 255) / 256) * ((N + DTN - 1) / DTN);                          \
-    hipLaunchKernelGGL((gemm_i8_dma_kernel<BJ, NS, NW>), dim3((unsigned)dma_tiles), dim3(64 * NW),  \
-                       lds, s, f->k, (uint32_t)M, (uint32_t)N, (uint32_t)K, (const int8_t*)A,      \
-                       (uint64_t)lda, (const int8_t*)bt, ldbt, (int8_t*)C, (uint64_t)ldc);      \
+    hipLaunchKernelGGL((gemm_i8_dma_kernel<BJ, NS, NW, false, IKT>), dim3((unsigned)dma_tiles),    \
+                       dim3(64 * NW), lds, s, f->k, (uint32_t)M, (uint32_t)N, (uint32_t)K,         \
+                       (const int8_t*)A, (uint64_t)lda, (const int8_t*)bt, ldbt, (int8_t*)C,       \
+                       (uint64_t)ldc);                                                             \
   }
-      if (shape == 5) FD_I8_DMA(2, 3, 4) else if (shape == 6) FD_I8_DMA(4, 4, 4) else FD_I8_DMA(2, 4, 8)
+      // 8: K-tiles of 128 (whole 128-byte rows per load), two stages
+      if (shape == 5) FD_I8_DMA(2, 3, 4, 64) else if (shape == 6) FD_I8_DMA(4, 4, 4, 64)
+      else if (shape == 8) FD_I8_DMA(2, 2, 8, 128) else FD_I8_DMA(2, 4, 8, 64)
 #undef FD_I8_DMA
-    } else if (shape >= 3 && shape <= 7) {
+    } else if (shape >= 3 && shape <= 8) {
       // 3: 256 x 256 tile, one wavefront per SIMD; 4: 256 x 128, two
-      const int64_t bkt = (shape == 4 || shape == 5 || shape == 7) ? 64 : (fd_tune("gemm.i8.big.ktile", 128) == 64 ? 64 : 128);
+      const int64_t bkt = (shape == 4 || shape == 5 || shape >= 7) ? 64 : (fd_tune("gemm.i8.big.ktile", 128) == 64 ? 64 : 128);
       const uint32_t big_fold = (uint32_t)(lam / (uint64_t)bkt);
 #define FD_I8_BIG(KT, BJ)                                                                          \
   {                                                                                                \
@@ -1226,7 +1238,7 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
                        (const int8_t*)A, (uint64_t)lda, (const int8_t*)bt, (uint64_t)K,            \
                        (int8_t*)C, (uint64_t)ldc, big_fold);                                       \
   }
-      if (shape == 4 || shape == 5 || shape == 7) FD_I8_BIG(64, 2) else if (bkt == 64) FD_I8_BIG(64, 4) else FD_I8_BIG(128, 4)
+      if (shape == 4 || shape == 5 || shape >= 7) FD_I8_BIG(64, 2) else if (bkt == 64) FD_I8_BIG(64, 4) else FD_I8_BIG(128, 4)
 #undef FD_I8_BIG
     } else if (kt == 64) { FD_I8_SHAPE(64) } else { FD_I8_SHAPE(128) }
 #undef FD_I8_SHAPE
