@@ -236,6 +236,55 @@ def extras_config3(fd):
     return out
 
 
+def measured_read_peak(fd):
+    """Best rate of the plain read-only reduction (fdot_calib_read: each 32-bit
+    word of a 4 GiB buffer read once by 16-byte nontemporal loads and summed)
+    over grids of 1-16 workgroups per CU and 4 or 8 loads in flight per lane."""
+    words = 1 << 30
+    x = torch.ones(words, dtype=torch.int32, device="cuda")
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    best, cfg = 0.0, None
+    for per_cu in (1, 2, 4, 8, 16):
+        for unroll in (4, 8):
+            run = lambda: fd.calib_read(x, out, blocks=cus * per_cu, unroll=unroll)
+            run()
+            t = time_events(run, 5)
+            gbs = words * 4 / t / 1e9
+            if gbs > best:
+                best, cfg = gbs, f"{per_cu} workgroups of 256 per CU, {unroll} loads in flight"
+    torch.cuda.synchronize()
+    if int(out.item()) != words:
+        raise RuntimeError("read calibration kernel returned a wrong sum")
+    del x
+    torch.cuda.empty_cache()
+    return {"value": round(best, 1), "unit": "GB/s",
+            "kernel": "plain read-only reduction (fdot_calib_read) over 4 GiB, best of 10 launch shapes",
+            "best_shape": cfg}
+
+
+def measured_mfma_peaks(fd):
+    """Rate of back-to-back matrix instructions on register operands
+    (fdot_calib_mfma: four independent accumulators per wavefront, eight
+    wavefronts per workgroup), best over 1, 2 and 4 workgroups per CU."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    res = {}
+    for kind, iters, dt, unit in (("i8", 20000, torch.int32, "TOPS"),
+                                  ("f64", 2000, torch.float64, "TFLOP/s")):
+        out = torch.zeros(2, dtype=dt, device="cuda")
+        best = 0.0
+        for per_cu in (1, 2, 4):
+            ops = fd.calib_mfma(kind, iters, 1, 1, out, blocks=cus * per_cu)
+            t = time_events(lambda: fd.calib_mfma(kind, iters, 1, 1, out, blocks=cus * per_cu), 3)
+            best = max(best, ops / t / 1e12)
+        torch.cuda.synchronize()
+        want = iters * (32 if kind == "i8" else 4)
+        if float(out[0].item()) != want:
+            raise RuntimeError("matrix calibration loop returned a wrong accumulator")
+        res[kind] = {"value": round(best, 1), "unit": unit}
+    return res
+
+
 def extras_gemm(fd):
     """fgemm_modp at 8192 x 8192 times 8192 x 4096: p = 251 centred int8 on
     int8 matrix cores; p = 2^20-3 residues in doubles on the FP64 matrix cores
@@ -247,6 +296,10 @@ def extras_gemm(fd):
     import synth
     M, K, N = 8192, 8192, 4096
     out = {}
+    mp = measured_mfma_peaks(fd)
+    out["measured_peaks"] = {
+        "int8": dict(mp["i8"], kernel="v_mfma_i32_32x32x32_i8 issue loop (fdot_calib_mfma)"),
+        "fp64": dict(mp["f64"], kernel="v_mfma_f64_16x16x4f64 issue loop (fdot_calib_mfma)")}
     for p, rep, dt, lo, peak, label, work, tune in [
             (251, "centred", torch.int8, -125, 5000.0, "int8 p=251", 1, {}),
             (1048573, "fp64", torch.float64, 0, 78.6, "fp64 p=2^20-3 FP64 matrix cores", 1,
@@ -268,8 +321,10 @@ def extras_gemm(fd):
         tops = 2.0 * M * N * K / t / 1e12
         for k in tune:
             fd.tune_set(k, None)
+        mpeak = mp["i8" if peak == 5000.0 else "f64"]["value"]
         out[label] = {"ms": round(t * 1e3, 3), "TOPS": round(tops, 1),
-                      "frac_of_peak": round(work * tops / peak, 4), "peak_TOPS": peak}
+                      "frac_of_peak": round(work * tops / peak, 4), "peak_TOPS": peak,
+                      "frac_of_measured_peak": round(work * tops / mpeak, 4)}
         if dt == torch.uint32 or "digit" in label:
             del A, B, C
             torch.cuda.empty_cache()
@@ -563,6 +618,10 @@ def main():
                      "traffic": measured_traffic(BATCHES[dom][:3]),
                      "algorithmic_bytes": batches[dom].bytes},
     }
+    log("measured read peak ...")
+    mpk = measured_read_peak(fd)
+    mpk["frac"] = round(achieved / mpk["value"], 4)
+    result["roofline"]["measured_peak"] = mpk
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(batches)

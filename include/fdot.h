@@ -270,6 +270,36 @@ typedef enum {
 fdot_status_t fdot_elementwise(fdot_field_t f, fdot_ew_op_t op, size_t n, const void* alpha,
                                const void* x, const void* y, void* r, void* stream);
 
+/* ------------------------------------------------------- measured peaks */
+
+/* Calibration kernels, no part of the method: they measure the two roofs the
+ * method's kernels are held against (HBM bandwidth for the streaming forms,
+ * matrix-core rate for the matrix product), so that fractions can be quoted
+ * against measured as well as datasheet peaks.
+ *
+ * fdot_calib_read: *result = the sum mod 2^64 of the n_words 32-bit words at
+ * x, each read once by 16-byte nontemporal loads.  x: device, 16-byte
+ * aligned (may be NULL when n_words is 0), n_words a multiple of 4; result: device, 8-byte aligned,
+ * overwritten (cleared by a kernel first, so the call may be captured).
+ * blocks: workgroups of 256 threads (0 = 8 per compute unit); unroll: loads
+ * in flight per thread, 4 or 8.  FDOT_E_INVALID_ARG otherwise. */
+fdot_status_t fdot_calib_read(const void* x, size_t n_words, uint32_t blocks, uint32_t unroll,
+                              uint64_t* result, void* stream);
+
+/* fdot_calib_mfma: each wavefront of `blocks` workgroups of 512 threads
+ * (0 = 2 per compute unit) runs `iters` rounds of four independent matrix
+ * products on register operands whose every element is a (left) and b
+ * (right).  kind 0: int8 32x32x32 products with int32 accumulation (a, b
+ * integers in [-128, 127]), result int32; kind 1: FP64 16x16x4 products,
+ * result double.  result: device array of two elements, 8-byte aligned;
+ * result[0] = element 0 of the first wavefront's first accumulator, i.e.
+ * iters * 32 * a * b (int32, wrapping) or iters * 4 * a * b; result[1] is a
+ * sink that keeps the other accumulators live and is written only for
+ * non-finite operands.  *ops (host, may be NULL) = operations executed, two
+ * per multiply-add.  FDOT_E_INVALID_ARG for another kind or operand. */
+fdot_status_t fdot_calib_mfma(int kind, uint32_t blocks, uint32_t iters, double a, double b,
+                              void* result, uint64_t* ops, void* stream);
+
 /* ------------------------------------------------------------ dot products */
 
 /* result[0] = sum_{i<n} x_i*y_i over GF(p) (Sec. 1, Sec. 3), x, y, result on

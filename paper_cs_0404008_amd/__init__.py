@@ -89,6 +89,9 @@ _sig("fgemm_modp", [_vp, _sz, _sz, _sz, _vp, _sz, _vp, _sz, _vp, _sz, _vp])
 _sig("fdot_workspace_reserve", [_vp, _sz])
 _sig("fdot_tune_set", [ctypes.c_char_p, _i64])
 _sig("fdot_tune_get", [ctypes.c_char_p, ctypes.POINTER(_i64)])
+_sig("fdot_calib_read", [_vp, _sz, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp])
+_sig("fdot_calib_mfma", [_i32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_double,
+                         _vp, ctypes.POINTER(_u64), _vp])
 
 
 class FdotError(RuntimeError):
@@ -213,6 +216,27 @@ def tune_get(key: str):
 
 def workspace_reserve(count: int, stream=None) -> None:
     _check(_lib.fdot_workspace_reserve(_stream(stream), count), "fdot_workspace_reserve")
+
+
+def calib_read(x: torch.Tensor, out: torch.Tensor, blocks: int = 0, unroll: int = 8,
+               stream=None) -> None:
+    """Measured-peak read kernel: out[0] (int64 device tensor) = sum of the
+    32-bit words of x mod 2^64, x read once."""
+    if x.numel() * x.element_size() % 16:
+        raise FdotError(2, "calib_read: size not a multiple of 16 bytes")
+    _check(_lib.fdot_calib_read(_ptr(x), x.numel() * x.element_size() // 4, blocks, unroll,
+                                _ptr(out), _stream(stream)), "fdot_calib_read")
+
+
+def calib_mfma(kind: str, iters: int, a, b, out: torch.Tensor, blocks: int = 0,
+               stream=None) -> int:
+    """Matrix-core issue loop (kind "i8" or "f64"); out: two-element device
+    tensor (int32 or float64).  Returns the operations it executes."""
+    ops = _u64()
+    _check(_lib.fdot_calib_mfma({"i8": 0, "f64": 1}[kind], blocks, iters, float(a), float(b),
+                                _ptr(out), ctypes.byref(ops), _stream(stream)),
+           "fdot_calib_mfma")
+    return ops.value
 
 
 # ---------------------------------------------------------------------- field

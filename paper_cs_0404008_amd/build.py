@@ -24,7 +24,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
           "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
 SOURCES = ["host_field.cpp", "runtime.cpp", "dot_kernels.hip", "gemm_kernels.hip",
-           "gemm_mfma.hip", "elementwise.hip", "ext_field.hip", "many_mixed.hip", "server.cpp"]
+           "gemm_mfma.hip", "elementwise.hip", "ext_field.hip", "many_mixed.hip", "server.cpp",
+           "calibrate.hip"]
 
 
 def _compile(src: str) -> str:
