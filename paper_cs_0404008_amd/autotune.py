@@ -11,6 +11,8 @@ running process.
 
 What is tuned:
 
+* the single dot product: smallest chunk (``min_chunk.<rep>``) and the
+  number of first-level combination words (``spread.<rep>``);
 * the batched dot product of a given batch: bytes per range
   (``many.range.<rep>``), workgroups per CU (``wg_per_cu.<rep>``) and
   wavefronts per range (``many.slices.<rep>``);
@@ -114,6 +116,20 @@ def tune_batched(field: Field, desc: torch.Tensor, algo: str = "auto",
              for r, w, s in itertools.product(ranges, wg_per_cu, slices)]
     return _search(lambda: field.dot_many(desc, out=out, algo=algo),
                    lambda: out.cpu().numpy().copy(), cands, reps)
+
+
+def tune_single(field: Field, x: torch.Tensor, y: torch.Tensor,
+                min_chunk=(256, 512, 1024, 2048, 4096), spread=(1, 8, 32, 64), reps: int = 3):
+    """Launch shape of one fdot_modp call (a dot short enough to be bound by
+    latency and by the combination of its units rather than by HBM):
+    smallest chunk in elements (``min_chunk.<rep>``) and first-level
+    combination words (``spread.<rep>``)."""
+    rep = field.rep
+    out = torch.empty(1, dtype=field.dtype, device=x.device)
+    cands = [{f"min_chunk.{rep}": m, f"spread.{rep}": s}
+             for m, s in itertools.product(min_chunk, spread)]
+    return _search(lambda: field.dot(x, y, out=out), lambda: out.cpu().numpy().copy(), cands,
+                   reps)
 
 
 def tune_schedule(field: Field, desc: torch.Tensor, reps: int = 3):
@@ -340,6 +356,16 @@ def main(argv=None) -> int:
             log.append(f"schedule p={p} {rep}: " + ", ".join(
                 f"{c} {t * 1e3:.3f} ms" for c, t in stable))
         del xs, ys, desc
+        n1 = 1 << 16 if args.small else 1_000_000
+        x, y = (torch.empty(n1, dtype=F.dtype, device="cuda") for _ in range(2))
+        m, lo = (p, 0) if rep != "centred" else (p, -((p - 1) // 2))
+        synth.fill_device(x, 1, 0, m, lo)
+        synth.fill_device(y, 1, 1, m, lo)
+        best, table = tune_single(F, x, y)
+        settings.update(best)
+        log.append(f"single p={p} {rep} n={n1}: " + ", ".join(
+            f"{c} {t * 1e6:.2f} us" for c, t in sorted(table, key=lambda x: x[1])[:3]))
+        del x, y
         torch.cuda.empty_cache()
     if not args.no_gemm:
         n = 1024 if args.small else 8192

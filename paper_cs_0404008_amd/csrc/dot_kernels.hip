@@ -82,7 +82,14 @@ struct Job {
   uint32_t fold_vecs;        // vectors between two folds
   uint32_t slice_shift;      // log2 of the wavefronts sharing one chunk or range
   uint32_t elem_bytes;       // bytes of one result
+  uint32_t spread;           // single form: first-level combination words (<= 1: one word)
 };
+
+// Single form: first-level combination word j sits kSpreadStride words
+// after the previous one, so that the words fall in distinct cache lines
+// and memory channels and their atomics proceed in parallel.
+constexpr uint32_t kSpreadStride = 32;
+constexpr uint32_t kSpreadMax = 64;
 
 // Chunk length used for a pair of length n: the configured chunk, or longer
 // when the pair would otherwise need more than 65535 work units (chunks x
@@ -630,6 +637,49 @@ struct Combiner {
   }
 };
 
+// Single form.  Every unit of one dot product adding to one word made the
+// atomics queue on one address (about 12 ns each, serialised), which bounded
+// a dot of a few hundred units.  Units are therefore spread over W words
+// (unit u to word u mod W); the wavefront that completes a word adds that
+// word's residue to word 0 and returns the word to zero; the wavefront that
+// completes word 0 (W additions) stores the result.  W = 1 is the plain
+// one-word combination.  Sums stay below 2^48: at most 65535 residues per
+// word.
+template <class Pol>
+struct SpreadCombiner {
+  bool pending = false;
+  uint32_t pw = 0, pnck = 0;
+  uint64_t pr = 0;
+  unsigned long long pold = 0;
+  __device__ __forceinline__ void settle(const FieldK& F, const Job& J, uint32_t W) {
+    if (pending && (pold >> 48) + 1 == pnck) {
+      const uint64_t r1 = mod_u64((pold & kSumMask) + pr, F);
+      atomicExch(J.acc + pw, 0ull);
+      if (W == 1) {
+        Pol::store(J.results, 0, (uint32_t)r1, F);
+      } else {
+        const unsigned long long o2 = atomicAdd(J.acc, (unsigned long long)(r1 + kCountOne));
+        if ((o2 >> 48) + 1 == W) {
+          atomicExch(J.acc, 0ull);
+          Pol::store(J.results, 0, mod_u64((o2 & kSumMask) + r1, F), F);
+        }
+      }
+    }
+    pending = false;
+  }
+  // lane 0 only; unit u of total, first-level words W
+  __device__ __forceinline__ void add(uint32_t u, uint32_t total, uint32_t W, uint64_t wsum,
+                                      const FieldK& F, const Job& J) {
+    settle(F, J, W);
+    const uint32_t j = u % W;
+    pw = W == 1 ? 0u : (j + 1) * kSpreadStride;
+    pnck = (total - j + W - 1) / W;  // units u' < total with u' mod W = j
+    pr = mod_u64(wsum, F);
+    pold = atomicAdd(J.acc + pw, (unsigned long long)(pr + kCountOne));
+    pending = true;
+  }
+};
+
 // Single form: unit u = slice (u mod S) of chunk (u / S), S = 2^slice_shift;
 // consecutive waves of a workgroup take consecutive units, and the grid
 // strides over the rest.
@@ -645,7 +695,8 @@ __global__ __launch_bounds__(NTH) void dot_kernel(const FieldK F, const Job J) {
   const uint64_t cs = chunk_of(J.n, J.chunk, sh);
   const uint64_t total = ((J.n + cs - 1) / cs) << sh;
   const uint64_t wstride = (uint64_t)gridDim.x * (NTH / 64);
-  Combiner<Pol> C;
+  const uint32_t W = J.spread <= 1 ? 1u : J.spread < total ? J.spread : (uint32_t)total;
+  SpreadCombiner<Pol> C;
   for (uint64_t u = (uint64_t)blockIdx.x * (NTH / 64) + (threadIdx.x >> 6); u < total;
        u += wstride) {
     const uint64_t c = u >> sh;
@@ -657,9 +708,9 @@ __global__ __launch_bounds__(NTH) void dot_kernel(const FieldK F, const Job J) {
     if constexpr (kTab) L.tab = s_tab;
     wave_range<Pol>(L, (const E*)J.x + beg, (const E*)J.y + beg, len, lane, slice, S, F, J);
     const uint64_t wsum = wave_sum(L.finish(F));
-    if (lane == 0) C.add(0, total, wsum, F, J);
+    if (lane == 0) C.add((uint32_t)u, (uint32_t)total, W, wsum, F, J);
   }
-  if (lane == 0) C.settle(F, J);
+  if (lane == 0) C.settle(F, J, W);
 }
 
 // Batched form.  The padded sequence [0, T) is cut into R ranges of Q
@@ -1209,8 +1260,9 @@ static const char* rep_key(int rep) {
 // batched kernel (default 512, at most 7680; larger batches get a separate
 // plan launch); chunk.<rep>: largest chunk of the single form (default 128
 // KiB per operand); min_chunk.<rep>: smallest chunk of the single form, which
-// otherwise spreads a vector over every resident wavefront; wg_per_cu.<rep>:
-// workgroups per CU (further clamped by residency).
+// otherwise spreads a vector over every resident wavefront; spread.<rep>:
+// first-level combination words of the single form (default 32, at most
+// 64); wg_per_cu.<rep>: workgroups per CU (further clamped by residency).
 struct Shape {
   uint64_t chunk;
   unsigned wg_per_cu;
@@ -1219,6 +1271,7 @@ struct Shape {
   uint32_t max_groups;
   uint64_t range;
   uint32_t fused;  // largest batch planned inside the kernel (0: never)
+  uint32_t spread;  // single form: first-level combination words
 };
 
 static uint32_t log2_slices(int64_t sl) { return sl >= 8 ? 3 : sl >= 4 ? 2 : sl >= 2 ? 1 : 0; }
@@ -1237,6 +1290,9 @@ static Shape shape_for(const fdot_field_s* f, uint64_t n_single) {
   sh.range = 0;
   sh.fused = 0;
   sh.chunk = 0;
+  snprintf(key, sizeof key, "spread.%s", r);
+  const int64_t sp = fd_tune(key, 32);
+  sh.spread = (uint32_t)(sp < 1 ? 1 : sp > (int64_t)kSpreadMax ? kSpreadMax : sp);
   if (!n_single) {
     snprintf(key, sizeof key, "many.slices.%s", r);
     sh.slice_shift = log2_slices(fd_tune(key, 1));
@@ -1256,7 +1312,7 @@ static Shape shape_for(const fdot_field_s* f, uint64_t n_single) {
   snprintf(key, sizeof key, "chunk.%s", r);
   int64_t chunk = fd_tune(key, (int64_t)(131072 / eb));
   snprintf(key, sizeof key, "min_chunk.%s", r);
-  int64_t mn = fd_tune(key, (int64_t)(16384 / eb));
+  int64_t mn = fd_tune(key, (int64_t)(4096 / eb));
   const uint64_t waves = (uint64_t)fd_cu_count() * sh.wg_per_cu * sh.waves_per_wg;
   const int64_t spread = (int64_t)((n_single + waves - 1) / waves);
   chunk = spread < chunk ? spread : chunk;
@@ -1305,6 +1361,8 @@ fdot_status_t fd_launch_dot(const fdot_field_s* f, fdot_algo_t algo, const void*
   A.J.results = result;
   A.J.fold_vecs = pl.fold_vecs;
   A.J.slice_shift = sh.slice_shift;
+  A.J.spread = sh.spread;
+  while (A.J.spread > 1 && (uint64_t)(A.J.spread + 1) * kSpreadStride > ws->cap) A.J.spread >>= 1;
   A.many = false;
   const uint64_t cs = chunk_of(n, sh.chunk, sh.slice_shift);
   A.work_waves = ((n + cs - 1) / cs) << sh.slice_shift;

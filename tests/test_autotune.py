@@ -52,6 +52,14 @@ def test_autotune_small_workloads():
             assert np.array_equal(F.dot_many(desc).cpu().numpy(), want)
         finally:
             autotune.apply(old)
+    F = fd.Field(32749, "zpz")
+    x = synth.uniform_int(7, 0, 100003, 32749).astype(np.uint32)
+    y = synth.uniform_int(7, 1, 100003, 32749).astype(np.uint32)
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    best, table = autotune.tune_single(F, xd, yd, min_chunk=(256, 4096), spread=(1, 32), reps=1)
+    assert len(table) == 4 and set(best) == {"min_chunk.zpz", "spread.zpz"}
+    import oracle
+    assert int(F.dot(xd, yd).cpu().numpy()[0]) == oracle.dot(32749, "zpz", x, y)
     for p, rep, dt in [(251, "centred", torch.int8), (1048573, "fp64", torch.float64)]:
         F = fd.Field(p, rep)
         m, lo = (p, 0) if rep != "centred" else (p, -((p - 1) // 2))

@@ -225,3 +225,31 @@ def test_batched_over_several_fields(rep, primes):
         assert same(got[k], oracle.dot(p, rep, hx[k], hy[k])), (k, p)
     with pytest.raises(fd.FdotError):
         fd.dot_many_mixed([fd.Field(32749, "zpz"), fd.Field(32749, "mont")], desc)
+
+
+@pytest.mark.parametrize("spread", [1, 2, 7, 32, 64])
+def test_single_form_spread_combination(spread):
+    """Single form with its units spread over first-level combination words:
+    unit counts below, at and above the word count, a ragged last round of
+    words, the largest residues (p = 4294967291, maximal products), and three
+    calls in a row on each size (every word must be back at zero)."""
+    p, rep = 4294967291, "zpz"
+    F = field(p, rep)
+    keys = ("chunk.zpz", "min_chunk.zpz", "spread.zpz")
+    old = {k: fd.tune_get(k) for k in keys}
+    try:
+        fd.tune_set("chunk.zpz", 64)
+        fd.tune_set("min_chunk.zpz", 64)
+        fd.tune_set("spread.zpz", spread)
+        for k, n in enumerate((1, 64, 65, 64 * 7 + 3, 64 * 64, 64 * 65 + 1, 100003)):
+            for pattern in ("random", "maxprod"):
+                x = stored(p, rep, n, 140 + k, 0, pattern)
+                y = stored(p, rep, n, 140 + k, 1, pattern)
+                want = oracle.dot(p, rep, x, y)
+                xd, yd = to_dev(x), to_dev(y)
+                for _ in range(3):
+                    got = to_host(F.dot(xd, yd))[0]
+                    assert same(got, want), (spread, n, pattern)
+    finally:
+        for k, v in old.items():
+            fd.tune_set(k, v)
