@@ -1258,8 +1258,8 @@ static const char* rep_key(int rep) {
 // wavefronts / S); many.range.<rep>: bytes per operand of one range (default
 // 512 KiB); many.fused.<rep>: largest batch whose plan is built inside the
 // batched kernel (default 512, at most 7680; larger batches get a separate
-// plan launch); chunk.<rep>: largest chunk of the single form (default 128
-// KiB per operand); min_chunk.<rep>: smallest chunk of the single form, which
+// plan launch); chunk.<rep>: largest chunk of the single form (default 1
+// MiB per operand); min_chunk.<rep>: smallest chunk of the single form, which
 // otherwise spreads a vector over every resident wavefront; spread.<rep>:
 // first-level combination words of the single form (default 32, at most
 // 64); wg_per_cu.<rep>: workgroups per CU (further clamped by residency).
@@ -1310,7 +1310,7 @@ static Shape shape_for(const fdot_field_s* f, uint64_t n_single) {
   snprintf(key, sizeof key, "slices.%s", r);
   sh.slice_shift = log2_slices(fd_tune(key, 1));
   snprintf(key, sizeof key, "chunk.%s", r);
-  int64_t chunk = fd_tune(key, (int64_t)(131072 / eb));
+  int64_t chunk = fd_tune(key, (int64_t)(1048576 / eb));
   snprintf(key, sizeof key, "min_chunk.%s", r);
   int64_t mn = fd_tune(key, (int64_t)(4096 / eb));
   const uint64_t waves = (uint64_t)fd_cu_count() * sh.wg_per_cu * sh.waves_per_wg;
