@@ -456,7 +456,9 @@ def extras_elementwise(fd):
 def extras_ext_fields(fd):
     """Dot products over extension fields in discrete logarithms (Sec. 2.4.2)
     at 2^28 codes per operand (1 GiB per call): GF(2^8), GF(3^10), GF(2^16),
-    against the prime field GF(65521) in the same representation."""
+    against the prime field GF(65521) in the same representation.  Plus-one
+    table accumulation everywhere; in characteristic 2 also the value XOR
+    schedule (the default there)."""
     import synth
     n = 1 << 28
     out = {}
@@ -468,12 +470,14 @@ def extras_ext_fields(fd):
         synth.fill_device(x, 11, 0, q, 0)
         synth.fill_device(y, 11, 1, q, 0)
         r = torch.empty(1, dtype=torch.uint16, device="cuda")
-        algo = "zech_tplus1"
-        F.dot(x, y, out=r, algo=algo)
-        t = time_events(lambda: F.dot(x, y, out=r, algo=algo), 3)
-        out[f"GF({p}^{d})" if d > 1 else f"GF({p}) plus-one"] = {
-            "ms": round(t * 1e3, 3), "gelem_per_s": round(n / t / 1e9, 1),
-            "GBps": round(4 * n / t / 1e9, 1)}
+        name = f"GF({p}^{d})" if d > 1 else f"GF({p})"
+        for algo in ("zech_tplus1", "zech_exp") if p == 2 else ("zech_tplus1",):
+            F.dot(x, y, out=r, algo=algo)
+            t = time_events(lambda: F.dot(x, y, out=r, algo=algo), 3)
+            lab = "plus-one" if algo == "zech_tplus1" else "value XOR"
+            out[f"{name} {lab}"] = {
+                "ms": round(t * 1e3, 3), "gelem_per_s": round(n / t / 1e9, 1),
+                "GBps": round(4 * n / t / 1e9, 1), "frac_of_hbm_peak": round(4 * n / t / 8e12, 4)}
         del x, y
         torch.cuda.empty_cache()
     return out

@@ -232,10 +232,15 @@ fdot_status_t fdot_field_destroy(fdot_field_t f);
  * primitive polynomial f of degree d whose lower coefficients, read the same
  * way, are smallest; the generator is the class of X, and codes are as for
  * prime fields (0 = zero, i = X^i, q-1 = 1).  Supported: encode, decode,
- * fdot_modp and fdot_modp_many (plus-one table accumulation; FDOT_ALGO_AUTO
- * or FDOT_ALGO_ZECH_TPLUS1) and fdot_elementwise; the matrix forms and
- * fdot_modp_many_mixed return FDOT_E_UNSUPPORTED / FDOT_E_INVALID_ARG.  FDOT_E_NOT_PRIME / FDOT_E_BOUND for a p that
- * is not prime or a q out of range. */
+ * fdot_modp and fdot_modp_many, fdot_elementwise.  Dot-product schedules:
+ * FDOT_ALGO_ZECH_TPLUS1, sums through the plus-one table (any p); and for
+ * p = 2 FDOT_ALGO_ZECH_EXP, each product's value (its coefficient bits)
+ * looked up and the values summed by exclusive or, which is polynomial
+ * addition over GF(2).  FDOT_ALGO_AUTO is ZECH_EXP for p = 2 and
+ * ZECH_TPLUS1 otherwise; other schedules return FDOT_E_UNSUPPORTED.  The
+ * matrix forms and fdot_modp_many_mixed return FDOT_E_UNSUPPORTED /
+ * FDOT_E_INVALID_ARG.  FDOT_E_NOT_PRIME / FDOT_E_BOUND for a p that is not
+ * prime or a q out of range. */
 fdot_status_t fdot_field_create_ext(uint64_t p, uint32_t d, fdot_field_t* out);
 fdot_status_t fdot_field_info(fdot_field_t f, fdot_field_info_t* out);
 

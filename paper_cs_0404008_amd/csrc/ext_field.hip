@@ -9,6 +9,14 @@
 // and across workgroups by a second, one-workgroup pass.  The plus-one table
 // (2q bytes) is copied into LDS by workgroups that stay resident.  The
 // batched form gives whole pairs to resident workgroups in turn.
+//
+// In characteristic 2 there is a cheaper schedule, the extension-field
+// counterpart of converting codes to values (Sec. 2.4): the value of a code
+// is its polynomial's coefficient bits, and adding polynomials over GF(2) is
+// the exclusive or of those bits, exact and carry-free.  So each product code
+// is looked up in the value table and XORed into the accumulator, with no
+// plus-one chain; the final value goes back to a code through the index
+// table.  That is about a third of the vector instructions per term.
 #include <algorithm>
 
 #include "fdot_internal.h"
@@ -16,6 +24,9 @@
 namespace {
 
 constexpr int NT = 1024;
+constexpr int EU = 4;  // vector pairs in flight per lane
+
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint32_t zmul(uint32_t a, uint32_t b, uint32_t qbar) {
   if (a == 0 || b == 0) return 0;
@@ -35,111 +46,178 @@ __device__ __forceinline__ uint32_t zadd(uint32_t a, uint32_t b, uint32_t qbar,
   return w > qbar ? w - qbar : w;
 }
 
+// Accumulator of one lane.  XOR = false: Zech codes summed by the plus-one
+// table (tab = plus-one table); XOR = true: polynomial values over GF(2)
+// summed by exclusive or (tab = value table).
+template <bool XOR>
+struct Acc;
+
+template <>
+struct Acc<false> {
+  uint32_t z[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // one per 16-bit slot of a vector
+  __device__ __forceinline__ void one(uint32_t a, uint32_t b, uint32_t qbar, const uint16_t* tab) {
+    z[0] = zadd(z[0], zmul(a, b, qbar), qbar, tab);
+  }
+  __device__ __forceinline__ void vec(const v4u& a, const v4u& b, uint32_t qbar,
+                                      const uint16_t* tab) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      z[2 * j] = zadd(z[2 * j], zmul(a[j] & 0xFFFFu, b[j] & 0xFFFFu, qbar), qbar, tab);
+      z[2 * j + 1] = zadd(z[2 * j + 1], zmul(a[j] >> 16, b[j] >> 16, qbar), qbar, tab);
+    }
+  }
+  __device__ __forceinline__ uint32_t total(uint32_t qbar, const uint16_t* tab) const {
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc = zadd(acc, z[j], qbar, tab);
+    return acc;
+  }
+};
+
+template <>
+struct Acc<true> {
+  uint32_t v0 = 0, v1 = 0;
+  __device__ __forceinline__ void one(uint32_t a, uint32_t b, uint32_t qbar, const uint16_t* tab) {
+    v0 ^= tab[zmul(a, b, qbar)];  // the zero code's value is 0
+  }
+  __device__ __forceinline__ void vec(const v4u& a, const v4u& b, uint32_t qbar,
+                                      const uint16_t* tab) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      v0 ^= tab[zmul(a[j] & 0xFFFFu, b[j] & 0xFFFFu, qbar)];
+      v1 ^= tab[zmul(a[j] >> 16, b[j] >> 16, qbar)];
+    }
+  }
+  __device__ __forceinline__ uint32_t total(uint32_t, const uint16_t*) const { return v0 ^ v1; }
+};
+
+// Combines two lane or workgroup sums: table addition of codes, or XOR of
+// values.
+template <bool XOR>
+__device__ __forceinline__ uint32_t combine(uint32_t a, uint32_t b, uint32_t qbar,
+                                            const uint16_t* tab) {
+  if constexpr (XOR) return a ^ b;
+  else return zadd(a, b, qbar, tab);
+}
+
+// Streams vectors v0, v0 + step, ... below nv of x and y into z, EU vector
+// pairs loaded before any is consumed, so that enough bytes are in flight to
+// cover the memory latency.
+template <bool XOR>
+__device__ __forceinline__ void stream_vectors(const v4u* x, const v4u* y, uint64_t v0,
+                                               uint64_t step, uint64_t nv, Acc<XOR>& A,
+                                               uint32_t qbar, const uint16_t* tab) {
+  uint64_t v = v0;
+  for (; v + (uint64_t)(EU - 1) * step < nv; v += (uint64_t)EU * step) {
+    v4u a[EU], b[EU];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+      a[u] = __builtin_nontemporal_load(x + v + (uint64_t)u * step);
+      b[u] = __builtin_nontemporal_load(y + v + (uint64_t)u * step);
+    }
+#pragma unroll
+    for (int u = 0; u < EU; ++u) A.vec(a[u], b[u], qbar, tab);
+  }
+  for (; v < nv; v += step) {
+    const v4u a = __builtin_nontemporal_load(x + v);
+    const v4u b = __builtin_nontemporal_load(y + v);
+    A.vec(a, b, qbar, tab);
+  }
+}
+
 // Sum of the lane values of a workgroup of NT threads; valid in thread 0.
+template <bool XOR>
 __device__ uint32_t block_sum(uint32_t acc, uint32_t qbar, const uint16_t* tab, uint32_t* s_part) {
-  for (int off = 32; off > 0; off >>= 1) acc = zadd(acc, (uint32_t)__shfl_xor((int)acc, off), qbar, tab);
+  for (int off = 32; off > 0; off >>= 1)
+    acc = combine<XOR>(acc, (uint32_t)__shfl_xor((int)acc, off), qbar, tab);
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
   if (lane == 0) s_part[w] = acc;
   __syncthreads();
   uint32_t s = 0;
   if (threadIdx.x == 0)
-    for (int i = 0; i < NT / 64; ++i) s = zadd(s, s_part[i], qbar, tab);
+    for (int i = 0; i < NT / 64; ++i) s = combine<XOR>(s, s_part[i], qbar, tab);
   return s;
 }
 
+template <bool XOR>
+__device__ __forceinline__ const uint16_t* table_of(const FieldK& F) {
+  return XOR ? F.zval : F.zplus1;
+}
+
+template <bool XOR>
 __global__ __launch_bounds__(NT) void ext_dot_kernel(const FieldK F, const uint16_t* x,
                                                      const uint16_t* y, uint64_t n, int vec,
                                                      uint16_t* partial) {
   extern __shared__ uint16_t s_tab[];
   __shared__ uint32_t s_part[NT / 64];
-  for (uint32_t i = threadIdx.x; i < (uint32_t)F.p; i += NT) s_tab[i] = F.zplus1[i];
+  const uint16_t* tab = table_of<XOR>(F);
+  for (uint32_t i = threadIdx.x; i < (uint32_t)F.p; i += NT) s_tab[i] = tab[i];
   __syncthreads();
   const uint32_t qbar = F.qbar;
   const uint64_t tid = (uint64_t)blockIdx.x * NT + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * NT;
-  uint32_t z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  Acc<XOR> A;
   uint64_t done = 0;
   if (vec) {
-    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
     const uint64_t nv = n / 8;
-    for (uint64_t v = tid; v < nv; v += stride) {
-      const v4u a = __builtin_nontemporal_load((const v4u*)x + v);
-      const v4u b = __builtin_nontemporal_load((const v4u*)y + v);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        z[2 * j] = zadd(z[2 * j], zmul(a[j] & 0xFFFFu, b[j] & 0xFFFFu, qbar), qbar, s_tab);
-        z[2 * j + 1] = zadd(z[2 * j + 1], zmul(a[j] >> 16, b[j] >> 16, qbar), qbar, s_tab);
-      }
-    }
+    stream_vectors<XOR>((const v4u*)x, (const v4u*)y, tid, stride, nv, A, qbar, s_tab);
     done = nv * 8;
   }
-  for (uint64_t i = done + tid; i < n; i += stride) z[0] = zadd(z[0], zmul(x[i], y[i], qbar), qbar, s_tab);
-  uint32_t acc = 0;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) acc = zadd(acc, z[j], qbar, s_tab);
-  const uint32_t s = block_sum(acc, qbar, s_tab, s_part);
+  for (uint64_t i = done + tid; i < n; i += stride) A.one(x[i], y[i], qbar, s_tab);
+  const uint32_t s = block_sum<XOR>(A.total(qbar, s_tab), qbar, s_tab, s_part);
   if (threadIdx.x == 0) partial[blockIdx.x] = (uint16_t)s;
 }
 
 // The partials live in the stream's workspace, whose combination words the
 // prime-field dot kernels expect to find zero: each is cleared once read.
+// XOR: the partials are values, and the result is the code of their sum.
+template <bool XOR>
 __global__ __launch_bounds__(NT) void ext_sum_kernel(const FieldK F, uint16_t* partial,
                                                      uint32_t count, uint16_t* result) {
   __shared__ uint32_t s_part[NT / 64];
   uint32_t acc = 0;
   for (uint32_t i = threadIdx.x; i < count; i += NT) {
-    acc = zadd(acc, partial[i], F.qbar, F.zplus1);
+    acc = combine<XOR>(acc, partial[i], F.qbar, F.zplus1);
     partial[i] = 0;
   }
-  const uint32_t s = block_sum(acc, F.qbar, F.zplus1, s_part);
-  if (threadIdx.x == 0) result[0] = (uint16_t)s;
+  const uint32_t s = block_sum<XOR>(acc, F.qbar, F.zplus1, s_part);
+  if (threadIdx.x == 0) result[0] = XOR ? F.zidx[s] : (uint16_t)s;
 }
 
 // Batched form: resident workgroups take whole pairs in turn (pair k goes to
 // workgroup k mod grid), each reducing its pair with all its lanes and the
 // table copied into LDS once.
+template <bool XOR>
 __global__ __launch_bounds__(NT) void ext_many_kernel(const FieldK F, const fdot_desc_t* desc,
                                                       uint64_t count, uint16_t* results) {
   extern __shared__ uint16_t s_tab[];
   __shared__ uint32_t s_part[NT / 64];
-  for (uint32_t i = threadIdx.x; i < (uint32_t)F.p; i += NT) s_tab[i] = F.zplus1[i];
+  const uint16_t* tab = table_of<XOR>(F);
+  for (uint32_t i = threadIdx.x; i < (uint32_t)F.p; i += NT) s_tab[i] = tab[i];
   __syncthreads();
   const uint32_t qbar = F.qbar;
-  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
   for (uint64_t k = blockIdx.x; k < count; k += gridDim.x) {
     const fdot_desc_t d = desc[k];
     const uint16_t* x = (const uint16_t*)d.x;
     const uint16_t* y = (const uint16_t*)d.y;
-    uint32_t z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    Acc<XOR> A;
     uint64_t done = 0;
     if (((((uintptr_t)x) | ((uintptr_t)y)) & 15u) == 0) {
       const uint64_t nv = d.n / 8;
-      for (uint64_t v = threadIdx.x; v < nv; v += NT) {
-        const v4u a = __builtin_nontemporal_load((const v4u*)x + v);
-        const v4u b = __builtin_nontemporal_load((const v4u*)y + v);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          z[2 * j] = zadd(z[2 * j], zmul(a[j] & 0xFFFFu, b[j] & 0xFFFFu, qbar), qbar, s_tab);
-          z[2 * j + 1] = zadd(z[2 * j + 1], zmul(a[j] >> 16, b[j] >> 16, qbar), qbar, s_tab);
-        }
-      }
+      stream_vectors<XOR>((const v4u*)x, (const v4u*)y, threadIdx.x, NT, nv, A, qbar, s_tab);
       done = nv * 8;
     }
-    for (uint64_t i = done + threadIdx.x; i < d.n; i += NT)
-      z[0] = zadd(z[0], zmul(x[i], y[i], qbar), qbar, s_tab);
-    uint32_t acc = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) acc = zadd(acc, z[j], qbar, s_tab);
-    const uint32_t sum = block_sum(acc, qbar, s_tab, s_part);
-    if (threadIdx.x == 0) results[k] = (uint16_t)sum;
+    for (uint64_t i = done + threadIdx.x; i < d.n; i += NT) A.one(x[i], y[i], qbar, s_tab);
+    const uint32_t sum = block_sum<XOR>(A.total(qbar, s_tab), qbar, s_tab, s_part);
+    if (threadIdx.x == 0) results[k] = XOR ? F.zidx[sum] : (uint16_t)sum;
     __syncthreads();  // s_part is reused by the next pair
   }
 }
 
 }  // namespace
 
-fdot_status_t fd_launch_ext_many(const fdot_field_s* f, uint64_t count, const fdot_desc_t* desc,
-                                 uint16_t* results, hipStream_t s) {
+fdot_status_t fd_launch_ext_many(const fdot_field_s* f, bool xor_values, uint64_t count,
+                                 const fdot_desc_t* desc, uint16_t* results, hipStream_t s) {
   const uint64_t q = f->k.p;
   const size_t lds = (size_t)q * sizeof(uint16_t);
   const uint64_t per_cu = std::max<uint64_t>(1, (160u * 1024u) / (lds + 1024));
@@ -147,19 +225,29 @@ fdot_status_t fd_launch_ext_many(const fdot_field_s* f, uint64_t count, const fd
       1, std::min<uint64_t>(count, (uint64_t)fd_cu_count() * std::min<uint64_t>(per_cu, 2)));
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)ext_many_kernel,
+    (void)hipFuncSetAttribute((const void*)ext_many_kernel<false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    (void)hipFuncSetAttribute((const void*)ext_many_kernel<true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
     attr_set = true;
   }
-  hipLaunchKernelGGL(ext_many_kernel, dim3(grid), dim3(NT), lds, s, f->k, desc, count, results);
+  if (xor_values)
+    hipLaunchKernelGGL(ext_many_kernel<true>, dim3(grid), dim3(NT), lds, s, f->k, desc, count,
+                       results);
+  else
+    hipLaunchKernelGGL(ext_many_kernel<false>, dim3(grid), dim3(NT), lds, s, f->k, desc, count,
+                       results);
   return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
 }
 
-fdot_status_t fd_launch_ext_dot(const fdot_field_s* f, const uint16_t* x, const uint16_t* y,
-                                uint64_t n, uint16_t* result, hipStream_t s) {
+fdot_status_t fd_launch_ext_dot(const fdot_field_s* f, bool xor_values, const uint16_t* x,
+                                const uint16_t* y, uint64_t n, uint16_t* result, hipStream_t s) {
   const uint64_t q = f->k.p;
   const size_t lds = (size_t)q * sizeof(uint16_t);
-  const uint64_t per_cu = std::max<uint64_t>(1, (160u * 1024u) / (lds + 1024));
+  // resident workgroups per CU: as many as the table copies fit in LDS, and
+  // at most two of NT threads (32 wavefronts per CU)
+  const uint64_t per_cu =
+      std::min<uint64_t>(2, std::max<uint64_t>(1, (160u * 1024u) / (lds + 1024)));
   const bool vec = ((((uintptr_t)x) | ((uintptr_t)y)) & 15u) == 0;
   const uint64_t work = vec ? n / 8 + 1 : n;
   const uint32_t grid = (uint32_t)std::max<uint64_t>(
@@ -170,14 +258,25 @@ fdot_status_t fd_launch_ext_dot(const fdot_field_s* f, const uint16_t* x, const 
   uint16_t* partial = (uint16_t*)w->acc;
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)ext_dot_kernel,
+    (void)hipFuncSetAttribute((const void*)ext_dot_kernel<false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    (void)hipFuncSetAttribute((const void*)ext_dot_kernel<true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
     attr_set = true;
   }
-  if (n > 0)
-    hipLaunchKernelGGL(ext_dot_kernel, dim3(grid), dim3(NT), lds, s, f->k, x, y, n, vec ? 1 : 0,
-                       partial);
-  hipLaunchKernelGGL(ext_sum_kernel, dim3(1), dim3(NT), 0, s, f->k, partial, n > 0 ? grid : 0u,
-                     result);
+  const uint32_t parts = n > 0 ? grid : 0u;
+  if (xor_values) {
+    if (n > 0)
+      hipLaunchKernelGGL(ext_dot_kernel<true>, dim3(grid), dim3(NT), lds, s, f->k, x, y, n,
+                         vec ? 1 : 0, partial);
+    hipLaunchKernelGGL(ext_sum_kernel<true>, dim3(1), dim3(NT), 0, s, f->k, partial, parts,
+                       result);
+  } else {
+    if (n > 0)
+      hipLaunchKernelGGL(ext_dot_kernel<false>, dim3(grid), dim3(NT), lds, s, f->k, x, y, n,
+                         vec ? 1 : 0, partial);
+    hipLaunchKernelGGL(ext_sum_kernel<false>, dim3(1), dim3(NT), 0, s, f->k, partial, parts,
+                       result);
+  }
   return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
 }

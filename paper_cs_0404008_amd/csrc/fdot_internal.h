@@ -81,10 +81,13 @@ fdot_status_t fd_launch_zero(void* ptr, size_t bytes, hipStream_t s);
 fdot_status_t fd_launch_many_mixed(uint64_t count, const fdot_mixed_desc_t* desc,
                                    const fdot_field_s* const* fields, size_t nfields,
                                    void* results, hipStream_t s);
-fdot_status_t fd_launch_ext_many(const fdot_field_s* f, uint64_t count, const fdot_desc_t* desc,
-                                 uint16_t* results, hipStream_t s);
-fdot_status_t fd_launch_ext_dot(const fdot_field_s* f, const uint16_t* x, const uint16_t* y,
-                                uint64_t n, uint16_t* result, hipStream_t s);
+// GF(p^d) dot products; xor_values (characteristic 2 only): accumulate the
+// products' values by exclusive or instead of their codes by the plus-one
+// table.
+fdot_status_t fd_launch_ext_many(const fdot_field_s* f, bool xor_values, uint64_t count,
+                                 const fdot_desc_t* desc, uint16_t* results, hipStream_t s);
+fdot_status_t fd_launch_ext_dot(const fdot_field_s* f, bool xor_values, const uint16_t* x,
+                                const uint16_t* y, uint64_t n, uint16_t* result, hipStream_t s);
 fdot_status_t fd_launch_elementwise(const fdot_field_s* f, fdot_ew_op_t op, uint64_t n,
                                     const void* alpha, const void* x, const void* y, void* r,
                                     hipStream_t s);

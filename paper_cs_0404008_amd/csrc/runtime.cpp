@@ -214,6 +214,19 @@ fdot_status_t fdot_decode(fdot_field_t f, const void* rep, uint32_t* canon, size
   return fd_launch_decode(f, rep, canon, n, (hipStream_t)stream);
 }
 
+// Schedules of a GF(p^d) dot product: the plus-one table (any p), or in
+// characteristic 2 the products' values accumulated by exclusive or
+// (FDOT_ALGO_ZECH_EXP, the default there).
+static fdot_status_t ext_schedule(const fdot_field_s* f, fdot_algo_t algo, bool* xor_values) {
+  const bool char2 = f->info.p == 2;
+  *xor_values = false;
+  if (algo == FDOT_ALGO_AUTO || (algo == FDOT_ALGO_ZECH_EXP && char2)) {
+    *xor_values = char2;
+    return FDOT_OK;
+  }
+  return algo == FDOT_ALGO_ZECH_TPLUS1 ? FDOT_OK : FDOT_E_UNSUPPORTED;
+}
+
 fdot_status_t fdot_elementwise(fdot_field_t f, fdot_ew_op_t op, size_t n, const void* alpha,
                                const void* x, const void* y, void* r, void* stream) {
   if (!f) return FDOT_E_INVALID_ARG;
@@ -238,10 +251,12 @@ fdot_status_t fdot_modp_algo(fdot_field_t f, fdot_algo_t algo, const void* x, co
   const size_t es = f->info.elem_bytes;
   if (!aligned_to(result, es)) return FDOT_E_INVALID_ARG;
   if (n && (!x || !y || !aligned_to(x, es) || !aligned_to(y, es))) return FDOT_E_INVALID_ARG;
-  if (f->degree > 1) {  // GF(p^d): plus-one table accumulation only
-    if (algo != FDOT_ALGO_AUTO && algo != FDOT_ALGO_ZECH_TPLUS1) return FDOT_E_UNSUPPORTED;
-    return fd_launch_ext_dot(f, (const uint16_t*)x, (const uint16_t*)y, n, (uint16_t*)result,
-                             (hipStream_t)stream);
+  if (f->degree > 1) {
+    bool xv = false;
+    const fdot_status_t st = ext_schedule(f, algo, &xv);
+    if (st != FDOT_OK) return st;
+    return fd_launch_ext_dot(f, xv, (const uint16_t*)x, (const uint16_t*)y, n,
+                             (uint16_t*)result, (hipStream_t)stream);
   }
   Workspace* w = nullptr;
   fdot_status_t st = fd_workspace_get((hipStream_t)stream, 1, &w);
@@ -259,14 +274,17 @@ fdot_status_t fdot_modp_many_algo(fdot_field_t f, fdot_algo_t algo, size_t count
   if (!f) return FDOT_E_INVALID_ARG;
   if (f->host_only) return FDOT_E_UNSUPPORTED;
   if ((int)algo < FDOT_ALGO_AUTO || (int)algo > FDOT_ALGO_HYBRID) return FDOT_E_INVALID_ARG;
-  if (f->degree > 1 && algo != FDOT_ALGO_AUTO && algo != FDOT_ALGO_ZECH_TPLUS1)
-    return FDOT_E_UNSUPPORTED;
+  bool xv = false;
+  if (f->degree > 1) {
+    const fdot_status_t st = ext_schedule(f, algo, &xv);
+    if (st != FDOT_OK) return st;
+  }
   if (count == 0) return FDOT_OK;
   if (!desc || !results || !aligned_to(desc, 8) || !aligned_to(results, f->info.elem_bytes))
     return FDOT_E_INVALID_ARG;
   if (count > (1ull << 31)) return FDOT_E_INVALID_ARG;
   if (f->degree > 1)
-    return fd_launch_ext_many(f, count, desc, (uint16_t*)results, (hipStream_t)stream);
+    return fd_launch_ext_many(f, xv, count, desc, (uint16_t*)results, (hipStream_t)stream);
   Workspace* w = nullptr;
   fdot_status_t st = fd_workspace_get((hipStream_t)stream, count, &w);
   if (st != FDOT_OK) return st;

@@ -1,6 +1,7 @@
 """GPU parity of extension fields GF(p^d) in discrete logarithms (Sec. 2.4.2)
 against the oracle's polynomial arithmetic, bit for bit: the modulus, the
-code <-> value maps, dot products of ragged and misaligned lengths, the
+code <-> value maps, dot products of ragged and misaligned lengths (both
+schedules in characteristic 2: plus-one table and value XOR), the
 elementwise operations, the batched form, and the refusal of the forms that
 are not built for extensions.  A prime-field dot product on the same stream
 after an extension one checks that the shared workspace is left as the
@@ -46,24 +47,47 @@ def test_ext_constants_and_maps(p, d):
     assert same(dec, values)
 
 
+def schedules(p):
+    """Dot-product schedules over GF(p^d): the plus-one table always, the
+    value XOR in characteristic 2."""
+    return ("auto", "zech_tplus1", "zech_exp") if p == 2 else ("auto", "zech_tplus1")
+
+
 @pytest.mark.parametrize("p,d", EXT, ids=lambda v: str(v))
 def test_ext_dot_matches_oracle(p, d):
     F = field(p, d)
     q = p ** d
-    for n in (0, 1, 7, 8, 9, 1000, 100003):
-        x = codes(q, n, 60 + n % 5, 0)
-        y = codes(q, n, 60 + n % 5, 1)
-        got = to_host(F.dot(to_dev(x), to_dev(y)))[0]
-        assert int(got) == oracle.ext_dot(p, d, x, y), (p, d, n)
-    # misaligned operands (element path) and the explicit plus-one schedule
-    n = 50001
-    x = codes(q, n + 1, 61, 0)
-    y = codes(q, n + 1, 61, 1)
-    xd, yd = to_dev(x), to_dev(y)
-    got = to_host(F.dot(xd[1:], yd[1:], algo="zech_tplus1"))[0]
-    assert int(got) == oracle.ext_dot(p, d, x[1:], y[1:])
-    with pytest.raises(fd.FdotError):
-        F.dot(xd, yd, algo="zech_exp")
+    for algo in schedules(p):
+        for n in (0, 1, 7, 8, 9, 1000, 100003):
+            x = codes(q, n, 60 + n % 5, 0)
+            y = codes(q, n, 60 + n % 5, 1)
+            if n >= 8:
+                x[:3] = [0, q - 1, 5 % (q - 1) + 1]   # zero, one, and a product with zero
+                y[:3] = [q - 1, q - 1, 0]
+            got = to_host(F.dot(to_dev(x), to_dev(y), algo=algo))[0]
+            assert int(got) == oracle.ext_dot(p, d, x, y), (p, d, n, algo)
+        # misaligned operands (element path)
+        n = 50001
+        x = codes(q, n + 1, 61, 0)
+        y = codes(q, n + 1, 61, 1)
+        xd, yd = to_dev(x), to_dev(y)
+        got = to_host(F.dot(xd[1:], yd[1:], algo=algo))[0]
+        assert int(got) == oracle.ext_dot(p, d, x[1:], y[1:]), (p, d, algo)
+    if p != 2:
+        with pytest.raises(fd.FdotError):
+            F.dot(to_dev(codes(q, 16, 61, 0)), to_dev(codes(q, 16, 61, 1)), algo="zech_exp")
+
+
+def test_ext_char2_value_schedule_cancels_pairs():
+    """In characteristic 2 every element is its own negative: a vector
+    dotted with itself twice over (x || x) . (y || y) sums each product twice
+    and must give zero, through both schedules."""
+    F = field(2, 16)
+    x = codes(1 << 16, 40000, 67, 0)
+    y = codes(1 << 16, 40000, 67, 1)
+    xx, yy = to_dev(np.concatenate([x, x])), to_dev(np.concatenate([y, y]))
+    for algo in ("zech_exp", "zech_tplus1"):
+        assert int(to_host(F.dot(xx, yy, algo=algo))[0]) == 0, algo
 
 
 def test_ext_dot_large_and_workspace_left_clean():
@@ -121,9 +145,11 @@ def test_ext_batched_dot_matches_oracle(p, d):
         ys.append(to_dev(b)[off:])
         hx.append(a[off:])
         hy.append(b[off:])
-    got = to_host(F.dot_many(fd.Field.make_desc(xs, ys)))
-    for k in range(len(ns)):
-        assert int(got[k]) == oracle.ext_dot(p, d, hx[k], hy[k]), (p, d, k, ns[k])
+    want = [oracle.ext_dot(p, d, hx[k], hy[k]) for k in range(len(ns))]
+    for algo in schedules(p):
+        got = to_host(F.dot_many(fd.Field.make_desc(xs, ys), algo=algo))
+        for k in range(len(ns)):
+            assert int(got[k]) == want[k], (p, d, k, ns[k], algo)
 
 
 def test_ext_unsupported_forms():

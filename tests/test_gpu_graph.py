@@ -149,7 +149,7 @@ def test_graph_elementwise(p, rep):
 
 
 def test_graph_extension_field_dot():
-    """A dot product over GF(2^16) captured once and replayed; its partials
+    """Dot products over GF(2^16) captured once and replayed; their partials
     share the capture stream's workspace with the prime-field kernels, so a
     prime-field dot is replayed in the same graph after it."""
     E = fd.Field(2, "zech", degree=16)
@@ -160,8 +160,10 @@ def test_graph_extension_field_dot():
     u = torch.empty(n, dtype=torch.uint32, device="cuda")
     v = torch.empty(n, dtype=torch.uint32, device="cuda")
 
-    def both():
-        return torch.cat([E.dot(x, y).to(torch.int64), P.dot(u, v).to(torch.int64)])
+    def both():  # both GF(2^16) schedules (value XOR, plus-one table), then GF(32749)
+        return torch.cat([E.dot(x, y, algo="zech_exp").to(torch.int64),
+                          E.dot(x, y, algo="zech_tplus1").to(torch.int64),
+                          P.dot(u, v).to(torch.int64)])
     for r in range(REPLAYS):
         synth.fill_device(x, 710 + r, 0, 1 << 16, 0)
         synth.fill_device(y, 710 + r, 1, 1 << 16, 0)
@@ -174,5 +176,6 @@ def test_graph_extension_field_dot():
         g.replay()
         torch.cuda.synchronize()
         got = to_host(out)
-        assert int(got[0]) == oracle.ext_dot(2, 16, to_host(x), to_host(y)), r
-        assert int(got[1]) == int(oracle.dot(32749, "zpz", to_host(u), to_host(v))), r
+        want = oracle.ext_dot(2, 16, to_host(x), to_host(y))
+        assert int(got[0]) == want and int(got[1]) == want, r
+        assert int(got[2]) == int(oracle.dot(32749, "zpz", to_host(u), to_host(v))), r
