@@ -164,7 +164,7 @@ def tune_gemm(field: Field, A: torch.Tensor, B: torch.Tensor, reps: int = 3):
     """Matrix-core tiling of fgemm_modp for this representation and shape."""
     C = torch.empty((A.shape[0], B.shape[1]), dtype=field.dtype, device=A.device)
     if field.rep == "centred":
-        cands = [{"gemm.i8.tile": t} for t in (7, 5, 6, 4, 2)]
+        cands = [{"gemm.i8.tile": t} for t in (8, 9, 7, 5, 6, 4, 2)]
     elif field.rep in ("fp64", "zpz", "mont"):
         cands = [{"gemm.f64.waves": w} for w in (8, 4, 16)]
     else:

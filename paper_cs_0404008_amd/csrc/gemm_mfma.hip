@@ -1141,9 +1141,9 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
     // The direct-to-LDS tilings need K a multiple of 64 and 16-byte rows of A;
     // other shapes get zero-padded copies (zero terms leave every sum as it
     // is, so the fold bound still applies to the true K).
-    const uint64_t kmul = shape == 8 ? 128 : 64;  // K-tile of the direct-to-LDS kernel
+    const uint64_t kmul = shape >= 8 ? 128 : 64;  // K-tile of the direct-to-LDS kernel
     const uint64_t Kp = (K + kmul - 1) / kmul * kmul;
-    const bool dma = (shape >= 5 && shape <= 8) && K > 0 &&
+    const bool dma = (shape >= 5 && shape <= 9) && K > 0 &&
                      (uint64_t)K <= (lam / 128) * 128 && M >= 256 && N >= 256 &&
                      Kp <= 0xFFFFFFFFull && fd_tune("gemm.i8.pad", 1) != 0;
     const bool pad_a = dma && (K % kmul != 0 || lda % 16 != 0 || ((uintptr_t)A) % 16 != 0);
@@ -1169,17 +1169,19 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
       lda = Kp;
     }
     if (dma) K = Kp;
-    // Kernel and workgroup tile (tune key gemm.i8.tile): large matrices use 7 by
-    // default.  Direct-to-LDS loads (K a multiple of 64): 7 = 256 x 256 with
-    // eight wavefronts and four stages, 5 = 256 x 128 with three stages,
-    // 6 = 256 x 256 with four wavefronts and four stages.  Register-staged,
+    // Kernel and workgroup tile (tune key gemm.i8.tile): large matrices use 8 by
+    // default.  Direct-to-LDS loads: 8 = 256 x 256 with eight wavefronts and
+    // two stages of K-tiles of 128, 9 = the same with four wavefronts of
+    // 128 x 128; K-tiles of 64: 7 = 256 x 256 with eight wavefronts and four
+    // stages, 5 = 256 x 128 with three stages, 6 = 256 x 256 with four
+    // wavefronts and four stages.  Register-staged,
     // double-buffered: 4 = 256 x 128, 3 = 256 x 256.  Register-staged with
     // in-loop folds (any K): 2 = 128 x 128 (small matrices), 1 = 256 x 128,
     // 0 = 256 x 256.  A tiling whose conditions fail falls back to the next
     // one that applies.
     // the large tile keeps its accumulators unfolded (only when K fits one fold
     // block) and needs 16-byte rows
-    if ((shape >= 3 && shape <= 8) &&
+    if ((shape >= 3 && shape <= 9) &&
         ((uint64_t)K > (lam / 128) * 128 || K % 16 != 0 || lda % 16 != 0 ||
                        ((uintptr_t)A) % 16 != 0 || M < 256 || N < 256))
       shape = 2;
@@ -1198,7 +1200,7 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
   if (shape == 2) { if (vec) FD_I8_LAUNCH(2, 2, KT, true); else FD_I8_LAUNCH(2, 2, KT, false); }  \
   else if (shape == 1) { if (vec) FD_I8_LAUNCH(4, 2, KT, true); else FD_I8_LAUNCH(4, 2, KT, false); } \
   else { if (vec) FD_I8_LAUNCH(4, 4, KT, true); else FD_I8_LAUNCH(4, 4, KT, false); }
-    if ((shape >= 5 && shape <= 8) && K % kmul == 0) {
+    if ((shape >= 5 && shape <= 9) && K % kmul == 0) {
 #define FD_I8_DMA(BJ, NS, NW, IKT)                                                                 \
   {                                                                                                \
     constexpr int DTN = 64 * BJ * (NW / 4);                                                        \
@@ -1217,9 +1219,10 @@ fdot_status_t fd_launch_gemm_mfma(const fdot_field_s* f, size_t M, size_t N, siz
   }
       // 8: K-tiles of 128 (whole 128-byte rows per load), two stages
       if (shape == 5) FD_I8_DMA(2, 3, 4, 64) else if (shape == 6) FD_I8_DMA(4, 4, 4, 64)
-      else if (shape == 8) FD_I8_DMA(2, 2, 8, 128) else FD_I8_DMA(2, 4, 8, 64)
+      else if (shape == 8) FD_I8_DMA(2, 2, 8, 128) else if (shape == 9) FD_I8_DMA(4, 2, 4, 128)
+      else FD_I8_DMA(2, 4, 8, 64)
 #undef FD_I8_DMA
-    } else if (shape >= 3 && shape <= 8) {
+    } else if (shape >= 3 && shape <= 9) {
       // 3: 256 x 256 tile, one wavefront per SIMD; 4: 256 x 128, two
       const int64_t bkt = (shape == 4 || shape == 5 || shape >= 7) ? 64 : (fd_tune("gemm.i8.big.ktile", 128) == 64 ? 64 : 128);
       const uint32_t big_fold = (uint32_t)(lam / (uint64_t)bkt);

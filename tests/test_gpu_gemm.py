@@ -160,7 +160,7 @@ def _full_size_case(p, rep, dtype):
         assert np.array_equal(lhs, rhs), t
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_gemm_int8_tile_variants(shape):
     """Every int8 matrix-core tiling (register-staged, double-buffered and
     direct-to-LDS), on ragged M and N and a K that some of them take in one
