@@ -236,6 +236,33 @@ def extras_config3(fd):
     return out
 
 
+def extras_gemv(fd):
+    """fgemv_modp on square matrices of 20000 (the served stream's largest):
+    classical residues mod 65521, Montgomery residues mod 2^31-1 and doubles
+    mod 2^26-5.  The matrix is read once, so the rate is bytes of A and x per
+    call over its time."""
+    import synth
+    n = 20000
+    out = {}
+    for p, rep, dt, label in [(65521, "zpz", torch.uint32, "zpz p=65521"),
+                              (2147483647, "mont", torch.uint32, "mont p=2^31-1"),
+                              (67108859, "fp64", torch.float64, "fp64 p=2^26-5")]:
+        F = fd.Field(p, rep)
+        A = torch.empty((n, n), dtype=dt, device="cuda")
+        x = torch.empty(n, dtype=dt, device="cuda")
+        synth.fill_device(A, 6, 0, p)
+        synth.fill_device(x, 6, 1, p)
+        y = torch.empty(n, dtype=dt, device="cuda")
+        F.gemv(A, x, out=y)
+        t = time_events(lambda: F.gemv(A, x, out=y), 5)
+        nbytes = (n * n + 2 * n) * A.element_size()
+        out[label] = {"ms": round(t * 1e3, 3), "GBps": round(nbytes / t / 1e9, 1),
+                      "frac_of_hbm_peak": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4)}
+        del A, x, y
+        torch.cuda.empty_cache()
+    return out
+
+
 def measured_read_peak(fd):
     """Best rate of the plain read-only reduction (fdot_calib_read: each 32-bit
     word of a 4 GiB buffer read once by 16-byte nontemporal loads and summed)
@@ -640,6 +667,9 @@ def main():
         torch.cuda.empty_cache()
         log("extras: fp64 / zech ...")
         extras["config3"] = extras_config3(fd)
+        torch.cuda.empty_cache()
+        log("extras: fgemv ...")
+        extras["fgemv"] = extras_gemv(fd)
         torch.cuda.empty_cache()
         log("extras: fgemm ...")
         extras["fgemm_config4"] = extras_gemm(fd)

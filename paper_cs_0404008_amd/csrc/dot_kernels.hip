@@ -1046,6 +1046,94 @@ __global__ __launch_bounds__(256) void gemv_kernel(const FieldK F, const Job J, 
   if (lane == 0) Pol::store(y, row, mod_u64(v, F), F);
 }
 
+// y = A x, RB rows per wavefront: every 16-byte vector of x is loaded once
+// for RB rows, so x's re-reads (from L2) cost 1/RB load per term instead of
+// one.  Rows and x share their 16-byte phase (checked by the host), so one
+// head, one vector loop and one tail serve all RB rows.  Policies that fold
+// do so once fold_vecs vectors have been added since the last fold, as in
+// the dot product.
+template <class Pol, int RB>
+__global__ __launch_bounds__(256) void gemv_rows_kernel(const FieldK F, const Job J, uint64_t m,
+                                                        uint64_t n, uint64_t lda, const void* A,
+                                                        const void* x, void* y) {
+  using E = typename Pol::E;
+  constexpr int VW = Pol::VW, U = 2, W = 64;
+  constexpr bool kF = Folds<Pol>::value;
+  extern __shared__ uint16_t s_tab[];
+  constexpr bool kTab = HasTable<Pol>::value;
+  if constexpr (kTab) {
+    const uint16_t* src = std::is_same<Pol, PZechExp>::value ? F.zval : F.zplus1;
+    for (uint32_t i = threadIdx.x; i < F.p32; i += 256) s_tab[i] = src[i];
+    __syncthreads();
+  }
+  const uint64_t r0 = ((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RB;
+  if (r0 >= m) return;
+  const uint32_t lane = threadIdx.x & 63u;
+  const E* xs = (const E*)x;
+  const E* rows[RB];
+  Pol L[RB];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    // rows past m repeat the last row; their sums are not stored
+    const uint64_t r = r0 + j < m ? r0 + j : m - 1;
+    rows[j] = (const E*)A + r * lda;
+    L[j].init(F);
+    if constexpr (kTab) L[j].tab = s_tab;
+  }
+  const uintptr_t ax = (uintptr_t)xs & 15u;
+  uint64_t head = ax ? (16u - ax) / sizeof(E) : 0;
+  if (head > n) head = n;
+  if (lane < head) {
+    const E xe = load_s(xs + lane);
+#pragma unroll
+    for (int j = 0; j < RB; ++j) L[j].one(load_s(rows[j] + lane), xe, F, J);
+  }
+  const u32x4* xv = (const u32x4*)(xs + head);
+  const uint64_t nv = (n - head) / VW;
+  const uint64_t t0 = head + nv * VW;
+  const uint32_t fv = J.fold_vecs;
+  uint32_t pending = 0;
+  uint64_t i = lane;
+  for (; i + (uint64_t)(U - 1) * W < nv; i += (uint64_t)U * W) {
+    u32x4 b[U], a[RB][U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      b[u] = load_nt(xv + i + (uint64_t)u * W);
+#pragma unroll
+      for (int j = 0; j < RB; ++j) a[j][u] = load_nt((const u32x4*)(rows[j] + head) + i + (uint64_t)u * W);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int j = 0; j < RB; ++j) L[j].vec(a[j][u], b[u], F);
+      if constexpr (kF) {
+        if (++pending >= fv) {
+#pragma unroll
+          for (int j = 0; j < RB; ++j) L[j].fold(F);
+          pending = 0;
+        }
+      }
+    }
+  }
+  if (i < nv) {  // at most U - 1 = 1 vector left for this lane
+    const u32x4 b = load_nt(xv + i);
+#pragma unroll
+    for (int j = 0; j < RB; ++j) L[j].vec(load_nt((const u32x4*)(rows[j] + head) + i), b, F);
+    // at most fv vectors since the last fold: finish() folds the rest
+  }
+  if (lane < n - t0) {
+    const E xe = load_s(xs + t0 + lane);
+#pragma unroll
+    for (int j = 0; j < RB; ++j) L[j].one(load_s(rows[j] + t0 + lane), xe, F, J);
+  }
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    const uint64_t v = wave_sum(L[j].finish(F));
+    if (lane == 0 && r0 + j < m) Pol::store(y, r0 + j, mod_u64(v, F), F);
+  }
+}
+
 // ---------------------------------------------------------------- launching
 enum class Kind {
   ZpzDelayed, ZpzPerTerm, ZpzOverflow, ZpzHybrid, MontDelayed, MontPerTerm, MontOverflow,
@@ -1426,9 +1514,25 @@ fdot_status_t fd_launch_zero(void* ptr, size_t bytes, hipStream_t s) {
 }
 
 template <class Pol>
-static fdot_status_t launch_gemv_t(const fdot_field_s* f, const Job& J, size_t m, size_t n,
+static fdot_status_t launch_gemv_t(const fdot_field_s* f, const Job& J0, size_t m, size_t n,
                                    const void* A, size_t lda, const void* x, void* y, size_t lds,
                                    hipStream_t s) {
+  // Rows that keep the 16-byte phase of x go four to a wavefront (tune key
+  // gemv.rows = 1 keeps one wavefront per row).
+  const uint64_t eb = f->info.elem_bytes;
+  const bool same_phase = ((uintptr_t)A % 16 == (uintptr_t)x % 16) && (lda * eb) % 16 == 0;
+  const bool folds_ok = !Folds<Pol>::value || J0.fold_vecs >= 1;
+  if (same_phase && folds_ok && n >= 256 && fd_tune("gemv.rows", 4) == 4) {
+    auto fr = gemv_rows_kernel<Pol, 4>;
+    if (lds > 65536)
+      (void)hipFuncSetAttribute((const void*)fr, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+    const uint64_t waves = (m + 3) / 4;
+    hipLaunchKernelGGL(fr, dim3((unsigned)((waves + 3) / 4)), dim3(256), lds, s, f->k, J0,
+                       (uint64_t)m, (uint64_t)n, (uint64_t)lda, A, x, y);
+    return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
+  }
+  const Job& J = J0;
   auto fn = gemv_kernel<Pol>;
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -94,6 +94,35 @@ def test_gemv_matches_oracle(p, rep):
             assert same(got, oracle.gemv(p, rep, A, x)), (p, rep, m, n, pattern)
 
 
+GEMV_BALANCED = [(65521, "zpz"), (4294967291, "zpz"), (2147483647, "mont"), (67108859, "fp64"),
+                 (32749, "zech"), (251, "centred")]
+
+
+@pytest.mark.parametrize("p,rep", GEMV_BALANCED, ids=lambda v: str(v))
+def test_gemv_row_blocks_match_oracle(p, rep):
+    """Rows that keep x's 16-byte phase go four to a wavefront: row counts
+    that are not a multiple of four, ragged row lengths inside padded rows,
+    operands that start one element past the 16-byte grid (head and tail
+    elements), maximal products; the one-wavefront-per-row kernel on the same
+    operands."""
+    F = field(p, rep)
+    for t, (m, n, off) in enumerate([(4201, 4099, 0), (2103, 8193, 1), (9, 300, 1), (5, 257, 0)]):
+        lda = (n + off + 15) // 16 * 16 + 16
+        pattern = "maxprod" if t % 2 == 0 else "random"
+        Aw = mat(p, rep, m, lda, 75 + t, 0, pattern)
+        xw = stored(p, rep, n + off, 75 + t, 1, pattern)
+        want = oracle.gemv(p, rep, np.ascontiguousarray(Aw[:, off:off + n]), xw[off:])
+        Ad = to_dev(Aw)[:, off:off + n]
+        xd = to_dev(xw)[off:]
+        for rows in (4, 1):
+            fd.tune_set("gemv.rows", rows)
+            try:
+                got = to_host(F.gemv(Ad, xd))
+                assert same(got, want), (p, rep, m, n, off, rows)
+            finally:
+                fd.tune_set("gemv.rows", None)
+
+
 def test_gemm_special_cases():
     p, rep = 1048573, "fp64"
     F = field(p, rep)
