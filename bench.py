@@ -576,17 +576,30 @@ def extras_served(fd, n_req=2000):
     return res
 
 
+EXTRAS = {  # name -> function of the library module (plain_vs_batched also takes a batch)
+    "plain_vs_batched": None, "single_dot": extras_single, "config3": extras_config3,
+    "fgemv": extras_gemv, "fgemm_config4": extras_gemm, "served_config5": extras_served,
+    "prime_sweep": extras_prime_sweep, "elementwise": extras_elementwise,
+    "ext_fields": extras_ext_fields,
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--extras", choices=["all", "none"], default="all")
+    ap.add_argument("--extras", default="all",
+                    help="all, none, or a comma-separated list of: " + ", ".join(EXTRAS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device-to-device three times (the known-size "
                          "reference for hardware byte counters), then exit")
     args = ap.parse_args()
+    if args.extras not in ("all", "none"):
+        unknown = [n for n in args.extras.split(",") if n not in EXTRAS]
+        if unknown:
+            raise SystemExit(f"unknown extras {unknown}; known: {', '.join(EXTRAS)}")
     if args.calibrate_copy:
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
@@ -656,35 +669,19 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(batches)
-    if args.extras == "all":
+    if args.extras != "none":
+        names = list(EXTRAS) if args.extras == "all" else args.extras.split(",")
         extras = {}
-        log("extras: plain vs batched ...")
-        extras["plain_vs_batched"] = extras_plain(fd, batches[0])
-        del batches
-        torch.cuda.empty_cache()
-        log("extras: single dot ...")
-        extras["single_dot"] = extras_single(fd)
-        torch.cuda.empty_cache()
-        log("extras: fp64 / zech ...")
-        extras["config3"] = extras_config3(fd)
-        torch.cuda.empty_cache()
-        log("extras: fgemv ...")
-        extras["fgemv"] = extras_gemv(fd)
-        torch.cuda.empty_cache()
-        log("extras: fgemm ...")
-        extras["fgemm_config4"] = extras_gemm(fd)
-        torch.cuda.empty_cache()
-        log("extras: served stream ...")
-        extras["served_config5"] = extras_served(fd)
-        torch.cuda.empty_cache()
-        log("extras: prime sweep ...")
-        extras["prime_sweep"] = extras_prime_sweep(fd)
-        torch.cuda.empty_cache()
-        log("extras: elementwise ...")
-        extras["elementwise"] = extras_elementwise(fd)
-        torch.cuda.empty_cache()
-        log("extras: extension fields ...")
-        extras["ext_fields"] = extras_ext_fields(fd)
+        for name in EXTRAS:  # in the fixed order
+            if name not in names:
+                continue
+            log(f"extras: {name} ...")
+            if name == "plain_vs_batched":
+                extras[name] = extras_plain(fd, batches[0])
+            else:
+                extras[name] = EXTRAS[name](fd)
+            batches.clear()  # the batch operands (about 14 GB) are not needed after the first
+            torch.cuda.empty_cache()
         result["extras"] = extras
     print(json.dumps(result), flush=True)
 
