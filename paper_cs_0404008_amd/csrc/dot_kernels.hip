@@ -1048,14 +1048,19 @@ __global__ __launch_bounds__(256) void gemv_kernel(const FieldK F, const Job J, 
 
 // y = A x, RB rows per wavefront: every 16-byte vector of x is loaded once
 // for RB rows, so x's re-reads (from L2) cost 1/RB load per term instead of
-// one.  Rows and x share their 16-byte phase (checked by the host), so one
-// head, one vector loop and one tail serve all RB rows.  Policies that fold
-// do so once fold_vecs vectors have been added since the last fold, as in
-// the dot product.
+// one.  The rows of one wavefront and the copy of x it reads share their
+// 16-byte phase, so one head, one vector loop and one tail serve all RB rows.
+// Row phases repeat with period P (P = 1 when a row is a whole number of
+// 16-byte units): the rows of class c (r = c mod P) go RB at a time to a
+// wavefront, which reads a copy of x placed at class c's phase (xbase +
+// c xstride + phase); with P = 1 and x in phase, x itself.  Policies that
+// fold do so once fold_vecs vectors have been added since the last fold, as
+// in the dot product.
 template <class Pol, int RB>
 __global__ __launch_bounds__(256) void gemv_rows_kernel(const FieldK F, const Job J, uint64_t m,
                                                         uint64_t n, uint64_t lda, const void* A,
-                                                        const void* x, void* y) {
+                                                        const void* x, void* y, uint32_t P,
+                                                        const uint8_t* xbase, uint64_t xstride) {
   using E = typename Pol::E;
   constexpr int VW = Pol::VW, U = 2, W = 64;
   constexpr bool kF = Folds<Pol>::value;
@@ -1066,16 +1071,22 @@ __global__ __launch_bounds__(256) void gemv_rows_kernel(const FieldK F, const Jo
     for (uint32_t i = threadIdx.x; i < F.p32; i += 256) s_tab[i] = src[i];
     __syncthreads();
   }
-  const uint64_t r0 = ((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RB;
+  const uint64_t wv = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint64_t c = wv % P, q = wv / P;
+  const uint64_t r0 = c + (uint64_t)P * RB * q;  // rows r0 + P j, j < RB
   if (r0 >= m) return;
+  const uint64_t rlast = c + (uint64_t)P * ((m - 1 - c) / P);  // last row of class c
   const uint32_t lane = threadIdx.x & 63u;
-  const E* xs = (const E*)x;
+  const E* xs = P == 1 && xbase == nullptr
+                    ? (const E*)x
+                    : (const E*)(xbase + c * xstride +
+                                 (((uintptr_t)A + c * lda * sizeof(E)) & 15u));
   const E* rows[RB];
   Pol L[RB];
 #pragma unroll
   for (int j = 0; j < RB; ++j) {
-    // rows past m repeat the last row; their sums are not stored
-    const uint64_t r = r0 + j < m ? r0 + j : m - 1;
+    // rows past the class's last repeat it; their sums are not stored
+    const uint64_t r = r0 + (uint64_t)P * j <= rlast ? r0 + (uint64_t)P * j : rlast;
     rows[j] = (const E*)A + r * lda;
     L[j].init(F);
     if constexpr (kTab) L[j].tab = s_tab;
@@ -1130,8 +1141,19 @@ __global__ __launch_bounds__(256) void gemv_rows_kernel(const FieldK F, const Jo
 #pragma unroll
   for (int j = 0; j < RB; ++j) {
     const uint64_t v = wave_sum(L[j].finish(F));
-    if (lane == 0 && r0 + j < m) Pol::store(y, r0 + j, mod_u64(v, F), F);
+    const uint64_t r = r0 + (uint64_t)P * j;
+    if (lane == 0 && r <= rlast) Pol::store(y, r, mod_u64(v, F), F);
   }
+}
+
+// Copies of x at the 16-byte phase of each row class c < P (gridDim.y = P).
+template <typename E>
+__global__ void x_phase_copies_kernel(const E* x, uint64_t n, uint8_t* xbase, uint64_t xstride,
+                                      uintptr_t a_addr, uint64_t row_bytes) {
+  const uint64_t c = blockIdx.y;
+  E* dst = (E*)(xbase + c * xstride + ((a_addr + c * row_bytes) & 15u));
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
+    dst[i] = x[i];
 }
 
 // ---------------------------------------------------------------- launching
@@ -1517,19 +1539,38 @@ template <class Pol>
 static fdot_status_t launch_gemv_t(const fdot_field_s* f, const Job& J0, size_t m, size_t n,
                                    const void* A, size_t lda, const void* x, void* y, size_t lds,
                                    hipStream_t s) {
-  // Rows that keep the 16-byte phase of x go four to a wavefront (tune key
-  // gemv.rows = 1 keeps one wavefront per row).
-  const uint64_t eb = f->info.elem_bytes;
-  const bool same_phase = ((uintptr_t)A % 16 == (uintptr_t)x % 16) && (lda * eb) % 16 == 0;
+  // Rows go four to a wavefront, each wavefront's rows of one 16-byte phase
+  // class, reading x itself when every row is in phase with it and otherwise
+  // a copy of x per class (tune key gemv.rows = 1 keeps one wavefront per
+  // row).
+  const uint64_t eb = sizeof(typename Pol::E);
   const bool folds_ok = !Folds<Pol>::value || J0.fold_vecs >= 1;
-  if (same_phase && folds_ok && n >= 256 && fd_tune("gemv.rows", 4) == 4) {
+  if (folds_ok && n >= 256 && fd_tune("gemv.rows", 4) == 4) {
+    const uint64_t d = (lda * eb) % 16;
+    const uint32_t P = d == 0 ? 1u : 16u / (uint32_t)(d & (~d + 1));  // 16 / gcd(d, 16)
+    const uint8_t* xbase = nullptr;
+    uint64_t xstride = 0;
+    if (P > 1 || (uintptr_t)A % 16 != (uintptr_t)x % 16) {
+      xstride = (n * eb + 16 + 255) & ~(uint64_t)255;
+      void* scr = nullptr;
+      fdot_status_t st = fd_scratch_get(s, (size_t)P * xstride, &scr);
+      if (st != FDOT_OK) return st;
+      xbase = (const uint8_t*)scr;
+      const unsigned gx = (unsigned)std::min<uint64_t>((n + 255) / 256, 1024);
+      hipLaunchKernelGGL(x_phase_copies_kernel<typename Pol::E>, dim3(gx, P), dim3(256), 0, s,
+                         (const typename Pol::E*)x, (uint64_t)n, (uint8_t*)scr, xstride,
+                         (uintptr_t)A, (uint64_t)(lda * eb));
+      if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
+    }
     auto fr = gemv_rows_kernel<Pol, 4>;
     if (lds > 65536)
       (void)hipFuncSetAttribute((const void*)fr, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds);
-    const uint64_t waves = (m + 3) / 4;
+    const uint64_t per_class = ((m + P - 1) / P + 3) / 4;  // wavefronts per class
+    const uint64_t waves = per_class * P;
+    if ((waves + 3) / 4 > 0x7FFFFFFFull) return FDOT_E_INVALID_ARG;
     hipLaunchKernelGGL(fr, dim3((unsigned)((waves + 3) / 4)), dim3(256), lds, s, f->k, J0,
-                       (uint64_t)m, (uint64_t)n, (uint64_t)lda, A, x, y);
+                       (uint64_t)m, (uint64_t)n, (uint64_t)lda, A, x, y, P, xbase, xstride);
     return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
   }
   const Job& J = J0;

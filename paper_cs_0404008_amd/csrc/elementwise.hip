@@ -18,12 +18,13 @@
 // inverse is b^(p-2) (Fermat), by square-and-multiply with the
 // representation's own product: the same instruction stream for every lane,
 // where the extended Euclidean algorithm of Sec. 2.1 would branch per lane.
-// A zero divisor gives the zero element.
+// On the vector path one exponentiation serves all the divisors of a lane's
+// 16 bytes (simultaneous inversion).  A zero divisor gives the zero element.
 //
 // Every lane handles 16 bytes of each operand (one vector load) when all
 // pointers are 16-byte aligned, else one element, with as many workgroups as
-// that takes.  The kernels are bound by HBM except division (ALU-bound: about
-// 2 log2 p products per element).
+// that takes.  The kernels are bound by HBM except division (ALU-bound: one
+// exponentiation, about 1.5 log2 p products, per vector of divisors).
 #include <string.h>
 
 #include <algorithm>
@@ -188,6 +189,32 @@ __device__ typename R::E divide(typename R::E a, typename R::E b, const FieldK& 
   }
 }
 
+// Division of W elements with one inversion (simultaneous inversion): the
+// divisors' prefix products, one exponentiation for the inverse of the whole
+// product, then each divisor's inverse peeled off with two products.  That is
+// about 4 products per element plus one exponentiation per W elements,
+// instead of one exponentiation per element.  A zero divisor enters the
+// product as one and gives the zero element.
+template <class R, int W>
+__device__ __forceinline__ void divide_vec(const typename R::E* a, const typename R::E* b,
+                                           typename R::E* out, const FieldK& F) {
+  using E = typename R::E;
+  E c[W], pre[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) c[k] = R::is_zero(b[k]) ? R::one(F) : b[k];
+  pre[0] = c[0];
+#pragma unroll
+  for (int k = 1; k < W; ++k) pre[k] = R::mul(pre[k - 1], c[k], F);
+  E inv = inverse<R>(pre[W - 1], F);  // inverse of c[0] ... c[k] while peeling
+#pragma unroll
+  for (int k = W - 1; k > 0; --k) {
+    const E ik = R::mul(inv, pre[k - 1], F);  // 1 / c[k]
+    inv = R::mul(inv, c[k], F);
+    out[k] = R::is_zero(b[k]) ? R::zero() : R::mul(a[k], ik, F);
+  }
+  out[0] = R::is_zero(b[0]) ? R::zero() : R::mul(a[0], inv, F);
+}
+
 template <class R, int OP>
 __device__ __forceinline__ typename R::E apply(typename R::E a, typename R::E x,
                                                typename R::E y, const FieldK& F) {
@@ -232,8 +259,12 @@ __global__ __launch_bounds__(NT) void ew_kernel(const FieldK Fin, uint64_t n,
       V yv = {};
       if constexpr (reads_y<OP>()) yv = load16((const V*)y + v);
       V out;
+      if constexpr (OP == FDOT_EW_DIV && !std::is_same<R, RZech>::value) {
+        divide_vec<R, W>(xv.e, yv.e, out.e, F);
+      } else {
 #pragma unroll
-      for (int k = 0; k < W; ++k) out.e[k] = apply<R, OP>(a, xv.e[k], yv.e[k], F);
+        for (int k = 0; k < W; ++k) out.e[k] = apply<R, OP>(a, xv.e[k], yv.e[k], F);
+      }
       store16((V*)r + v, out);
     }
     for (uint64_t i = nv * W + tid; i < n; i += stride)

@@ -54,6 +54,9 @@ fdot_status_t fd_workspace_get(hipStream_t s, size_t count, Workspace** out);
 // called before a library-owned stream is destroyed.
 void fd_workspace_release(hipStream_t s);
 void fd_scratch_release(hipStream_t s);
+// Per-stream device scratch of at least `bytes` (stream-ordered growth; under
+// graph capture only an existing buffer that is large enough).
+fdot_status_t fd_scratch_get(hipStream_t s, size_t bytes, void** out);
 // Stream-ordered device allocation from the default pool, which keeps freed
 // blocks for reuse.
 hipError_t fd_alloc_async(void** p, size_t bytes, hipStream_t s);

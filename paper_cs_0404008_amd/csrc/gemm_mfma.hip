@@ -865,6 +865,10 @@ fdot_status_t scratch_for(hipStream_t s, size_t bytes, void** out) {
 
 }  // namespace
 
+fdot_status_t fd_scratch_get(hipStream_t s, size_t bytes, void** out) {
+  return scratch_for(s, bytes, out);
+}
+
 void fd_scratch_release(hipStream_t s) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return;

@@ -118,3 +118,26 @@ def test_elementwise_argument_errors():
     assert L.fdot_elementwise(F.handle, 0, 8, None, ctypes.c_void_p(x.data_ptr()), None,
                               ctypes.c_void_p(x.data_ptr()), None) == -1  # add without y
     assert ELEM_BYTES["zpz"] == 4 and TORCH_DTYPES["zpz"] == torch.uint32
+
+
+@pytest.mark.parametrize("p,rep", [(32749, "zpz"), (4294967291, "zpz"), (2654435761, "mont"),
+                                   (67108859, "fp64"), (251, "centred"), (3, "centred"),
+                                   (2, "zpz")])
+def test_division_shares_one_inversion_per_vector(p, rep):
+    """The vector path inverts all the divisors of a lane's 16 bytes at once:
+    zero divisors at every position of a vector, vectors of zeros only,
+    vectors of ones, the largest residues, and a ragged tail."""
+    F = field(p, rep)
+    n = 4096 + 7
+    x = stored(p, rep, n, 95, 0)
+    y = stored(p, rep, n, 95, 1)
+    canon = oracle.decode(p, rep, y).astype(np.int64)
+    per = 16 // ELEM_BYTES[rep]
+    for k in range(per):                        # one zero at lane position k
+        canon[per * (2 + k) + k] = 0
+    canon[per * 40: per * 42] = 0               # whole vectors of zeros
+    canon[per * 50: per * 52] = 1 % p           # and of ones
+    canon[per * 60: per * 62] = p - 1
+    y = oracle.encode(p, rep, canon)
+    got = run(F, "div", x, y, x, None)
+    assert same(got, want(p, rep, "div", x, y, x, None)), (p, rep)

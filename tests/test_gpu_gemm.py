@@ -100,25 +100,40 @@ GEMV_BALANCED = [(65521, "zpz"), (4294967291, "zpz"), (2147483647, "mont"), (671
 
 @pytest.mark.parametrize("p,rep", GEMV_BALANCED, ids=lambda v: str(v))
 def test_gemv_row_blocks_match_oracle(p, rep):
-    """Rows that keep x's 16-byte phase go four to a wavefront: row counts
-    that are not a multiple of four, ragged row lengths inside padded rows,
-    operands that start one element past the 16-byte grid (head and tail
-    elements), maximal products; the one-wavefront-per-row kernel on the same
+    """Rows go four to a wavefront, grouped by their 16-byte phase: rows that
+    are a whole number of 16-byte units and in phase with x (x read
+    directly), rows out of phase with x (one shifted copy of x), and
+    contiguous rows of ragged length whose phases cycle (a copy of x per
+    phase class); row counts that are not a multiple of four or of the
+    cycle, maximal products; the one-wavefront-per-row kernel on the same
     operands."""
     F = field(p, rep)
-    for t, (m, n, off) in enumerate([(4201, 4099, 0), (2103, 8193, 1), (9, 300, 1), (5, 257, 0)]):
-        lda = (n + off + 15) // 16 * 16 + 16
+    eb = {"zpz": 4, "mont": 4, "fp64": 8, "zech": 2, "centred": 1}[rep]
+    w16 = 16 // eb                    # elements per 16 bytes
+    cases = [  # m, n, lda, offset of A's first row, offset of x
+        (4201, 4099, (4099 + w16 - 1) // w16 * w16 + w16, 0, 0),
+        (2103, 8193, (8194 + w16 - 1) // w16 * w16 + w16, 1, 1),
+        (9, 300, (301 + w16 - 1) // w16 * w16, 1, 1),
+        (64, 1000, 1000 + w16, 0, 1),
+        (1003, 4099, 4099, 0, 0),
+        (777, 2051, 2051, 0, 1),
+        (5, 257, 257, 1, 0),
+    ]
+    for t, (m, n, lda, oa, ox) in enumerate(cases):
         pattern = "maxprod" if t % 2 == 0 else "random"
-        Aw = mat(p, rep, m, lda, 75 + t, 0, pattern)
-        xw = stored(p, rep, n + off, 75 + t, 1, pattern)
-        want = oracle.gemv(p, rep, np.ascontiguousarray(Aw[:, off:off + n]), xw[off:])
-        Ad = to_dev(Aw)[:, off:off + n]
-        xd = to_dev(xw)[off:]
+        flat = stored(p, rep, m * lda + oa, 75 + t, 0, pattern)
+        xw = stored(p, rep, n + ox, 75 + t, 1, pattern)
+        A = np.lib.stride_tricks.as_strided(flat[oa:], shape=(m, n),
+                                            strides=(lda * flat.itemsize, flat.itemsize))
+        want = oracle.gemv(p, rep, np.ascontiguousarray(A), xw[ox:])
+        Ad = torch.as_strided(to_dev(flat)[oa:], (m, n), (lda, 1))
+        xd = to_dev(xw)[ox:]
         for rows in (4, 1):
             fd.tune_set("gemv.rows", rows)
             try:
-                got = to_host(F.gemv(Ad, xd))
-                assert same(got, want), (p, rep, m, n, off, rows)
+                for _ in range(2):
+                    got = to_host(F.gemv(Ad, xd))
+                    assert same(got, want), (p, rep, m, n, lda, oa, ox, rows)
             finally:
                 fd.tune_set("gemv.rows", None)
 
