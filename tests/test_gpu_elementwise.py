@@ -141,3 +141,18 @@ def test_division_shares_one_inversion_per_vector(p, rep):
     y = oracle.encode(p, rep, canon)
     got = run(F, "div", x, y, x, None)
     assert same(got, want(p, rep, "div", x, y, x, None)), (p, rep)
+
+
+@pytest.mark.parametrize("p", [251, 241, 3, 5, 127])
+def test_centred_products_exhaustive(p):
+    """Centred residues (Sec. 3.2.2): every product and every AXPY a x + y
+    (with the extreme multipliers +-h) over all pairs (x, y) of residues,
+    against the oracle: the signed remainder over its whole domain."""
+    F = field(p, "centred")
+    h = (p - 1) // 2
+    vals = np.arange(-h, h + 1, dtype=np.int8)
+    x = np.repeat(vals, vals.size)
+    y = np.tile(vals, vals.size)
+    for op, alpha in (("mul", None), ("axpy", np.int8(h)), ("axpy", np.int8(-h))):
+        got = run(F, op, x, y, y, alpha)
+        assert same(got, want(p, "centred", op, x, y, y, alpha)), (p, op, alpha)
