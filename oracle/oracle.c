@@ -563,7 +563,16 @@ int orc_ext_elementwise(uint64_t p, int d, int op, size_t n, const uint16_t* a,
   orc_ext E;
   int rc = ext_init(&E, p, d);
   if (rc) { ext_free(&E); return rc; }
-  const uint64_t av = (op == 5 || op == 6) ? E.exp[a[0] < E.q ? a[0] : 0] : 0;
+  /* every code read must be canonical, in [0, q-1] (Sec. 2.4): refuse the
+   * call before writing anything */
+  const int reads_y = op == 0 || op == 1 || op == 3 || op == 4 || op == 5;
+  if ((op == 5 || op == 6) && a[0] >= E.q) { ext_free(&E); return ORC_E_NONCANON; }
+  for (size_t i = 0; i < n; ++i)
+    if (x[i] >= E.q || (reads_y && y[i] >= E.q) || (op == 6 && r[i] >= E.q)) {
+      ext_free(&E);
+      return ORC_E_NONCANON;
+    }
+  const uint64_t av = (op == 5 || op == 6) ? E.exp[a[0]] : 0;
   for (size_t i = 0; i < n; ++i) {
     const uint64_t u = E.exp[x[i]];
     uint64_t v = 0;

@@ -554,3 +554,31 @@ def test_ext_dot_against_elementwise_and_bruteforce():
         cx = oracle.ext_encode(2, 2, [x0, x1])
         cy = oracle.ext_encode(2, 2, [y0, y1])
         assert oracle.ext_decode(2, 2, [oracle.ext_dot(2, 2, cx, cy)])[0] == want
+
+
+def test_ext_noncanonical_codes_are_rejected():
+    """Codes of GF(q) are 0 .. q-1 (Sec. 2.4): every extension-field entry
+    point refuses a code >= q in any operand it reads, and the scalar of
+    AXPY/AXPYIN too; a code it does not read is not checked."""
+    p, d = 3, 2  # q = 9
+    good = np.array([0, 1, 8, 4], dtype=np.uint16)
+    bad = np.array([0, 9, 1, 2], dtype=np.uint16)
+    with pytest.raises(ValueError):
+        oracle.ext_dot(p, d, bad, good)
+    with pytest.raises(ValueError):
+        oracle.ext_decode(p, d, bad)
+    for op in ("add", "sub", "mul", "div", "axpy"):
+        with pytest.raises(ValueError):
+            oracle.ext_elementwise(p, d, op, good, bad, alpha=1)
+        with pytest.raises(ValueError):
+            oracle.ext_elementwise(p, d, op, bad, good, alpha=1)
+    with pytest.raises(ValueError):
+        oracle.ext_elementwise(p, d, "neg", bad)
+    with pytest.raises(ValueError):
+        oracle.ext_elementwise(p, d, "axpy", good, good, alpha=9)
+    with pytest.raises(ValueError):
+        oracle.ext_elementwise(p, d, "axpyin", good, alpha=1, r=bad)
+    with pytest.raises(ValueError):
+        oracle.ext_elementwise(p, d, "axpyin", good, alpha=200, r=good)
+    # neg reads no y: a y outside the field is not an operand
+    assert oracle.ext_elementwise(p, d, "neg", good, bad).shape == good.shape
