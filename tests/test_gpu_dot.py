@@ -71,6 +71,38 @@ def test_dot_matches_oracle(p, rep, algo):
         assert same(got, oracle.dot_many(p, rep, xs, ys)), (p, rep, algo, pattern)
 
 
+@pytest.mark.parametrize("range_bytes", [None, 4096])
+@pytest.mark.parametrize("p,rep,algo", [c for c in CASES if c[1] != "zech"],
+                         ids=lambda v: str(v))
+def test_batched_separate_plan(p, rep, algo, range_bytes):
+    """The batched form with its plan built by a separate launch, the path
+    of every batch above the in-kernel plan limit (tables: always), for
+    every policy and schedule: ragged and empty pairs, misaligned views, the
+    maximal-product pattern; with the default ranges and with ranges of 4 KiB
+    per operand, so that pairs are cut across many ranges."""
+    F = field(p, rep)
+    keys = {f"many.fused.{rep}": 0, f"many.range.{rep}": range_bytes}
+    for k, v in keys.items():
+        fd.tune_set(k, v)
+    try:
+        C = default_chunk(rep)
+        ns = [0, 1, 3, 63, 64, 65, 1000, C - 1, C, C + 1, 0, 3 * C + 17, 5, 2 * C + 3, 777]
+        for pattern in ("random", "maxprod"):
+            xs = [stored(p, rep, n, 150 + k, 0, pattern) for k, n in enumerate(ns)]
+            ys = [stored(p, rep, n, 150 + k, 1, pattern) for k, n in enumerate(ns)]
+            xd, yd = [to_dev(v) for v in xs], [to_dev(v) for v in ys]
+            big = to_dev(stored(p, rep, 9000, 151, 0, pattern))
+            xd.append(big[1:4001]); yd.append(big[3:4003])
+            xs.append(to_host(big[1:4001])); ys.append(to_host(big[3:4003]))
+            desc = fd.Field.make_desc(xd, yd)
+            for _ in range(2):
+                got = to_host(F.dot_many(desc, algo=algo))
+                assert same(got, oracle.dot_many(p, rep, xs, ys)), (p, rep, algo, pattern)
+    finally:
+        for k in keys:
+            fd.tune_set(k, None)
+
+
 @pytest.mark.parametrize("p,rep", [(32749, "zpz"), (2147483647, "mont"), (67108859, "fp64"),
                                    (32749, "zech"), (251, "centred"), (4294967291, "zpz")])
 def test_misaligned_and_aliased(p, rep):
