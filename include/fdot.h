@@ -322,6 +322,22 @@ fdot_status_t fdot_modp_many(fdot_field_t f, size_t count, const fdot_desc_t* de
 fdot_status_t fdot_modp_many_algo(fdot_field_t f, fdot_algo_t algo, size_t count,
                                   const fdot_desc_t* desc, void* results, void* stream);
 
+/* For callers that cannot allocate device memory at the call: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, results and kernels as fdot_modp_many_algo, but the batch's
+ * device scratch (a combination word per pair and the plan of the batch,
+ * about 1.5 MiB) is a fixed array inside the library, one copy per GPU, held
+ * until the process ends; the call makes no device allocation.  count may be
+ * at most FDOT_NOALLOC_MAX_PAIRS (FDOT_E_INVALID_ARG above it).  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (on two
+ * streams, or from two threads) race and their results are unspecified;
+ * calls ordered on one stream are safe.  Each call first clears its pairs'
+ * combination words with a kernel, so a call may be captured into a graph
+ * and replayed. */
+#define FDOT_NOALLOC_MAX_PAIRS 65536
+fdot_status_t fdot_modp_many_noalloc(fdot_field_t f, fdot_algo_t algo, size_t count,
+                                     const fdot_desc_t* desc, void* results, void* stream);
+
 /* results[k] = dot of desc[k] over fields[desc[k].field], k < count: one batch
  * over several primes (Sec. 1: the dot product as a building block; a request
  * stream mixes fields).  fields is a host array of nfields prime fields of one

@@ -29,6 +29,7 @@ ACCS = {"u64": 0, "u32": 1, "f64": 2, "i32_centred": 3, "f64_centred": 4, "mont_
         "u64_hybrid": 6}
 BOUNDS = {"axpy_signed": 0, "axpy_unsigned": 1, "montgomery": 2, "zech_index": 3}
 FOLDS = {"remainder": 0, "redc": 1, "fp64": 2}
+NOALLOC_MAX_PAIRS = 65536  # FDOT_NOALLOC_MAX_PAIRS
 EW_OPS = {"add": 0, "sub": 1, "neg": 2, "mul": 3, "div": 4, "axpy": 5, "axpyin": 6}
 NP_DTYPES = {"zpz": "uint32", "mont": "uint32", "fp64": "float64", "zech": "uint16",
              "centred": "int8"}
@@ -84,6 +85,7 @@ _sig("fdot_elementwise", [_vp, _i32, _sz, _vp, _vp, _vp, _vp, _vp])
 _sig("fdot_modp_many_mixed", [_sz, _vp, _vp, _sz, _vp, _vp])
 _sig("fdot_modp_many", [_vp, _sz, _vp, _vp, _vp])
 _sig("fdot_modp_many_algo", [_vp, _i32, _sz, _vp, _vp, _vp])
+_sig("fdot_modp_many_noalloc", [_vp, _i32, _sz, _vp, _vp, _vp])
 _sig("fgemv_modp", [_vp, _sz, _sz, _vp, _sz, _vp, _vp, _vp])
 _sig("fgemm_modp", [_vp, _sz, _sz, _sz, _vp, _sz, _vp, _sz, _vp, _sz, _vp])
 _sig("fdot_workspace_reserve", [_vp, _sz])
@@ -358,6 +360,19 @@ class Field:
             out = torch.empty(count, dtype=self.dtype, device=desc.device)
         _check(_lib.fdot_modp_many_algo(self._h, ALGOS[algo], count, _ptr(desc), _ptr(out),
                                         _stream(stream)), "fdot_modp_many")
+        return out
+
+    def dot_many_noalloc(self, desc: torch.Tensor, out: torch.Tensor, algo: str = "auto",
+                         stream=None) -> torch.Tensor:
+        """fdot_modp_many_noalloc: dot_many with the library's fixed scratch
+        (no device allocation at the call; at most NOALLOC_MAX_PAIRS pairs)."""
+        if desc.dtype != torch.int64 or desc.dim() != 2 or desc.shape[1] != 3 or not desc.is_cuda:
+            raise TypeError("desc must be a CUDA int64 tensor of shape [count, 3]")
+        self._need(out, "out")
+        if out.numel() < desc.shape[0]:
+            raise ValueError("out is shorter than the batch")
+        _check(_lib.fdot_modp_many_noalloc(self._h, ALGOS[algo], desc.shape[0], _ptr(desc),
+                                           _ptr(out), _stream(stream)), "fdot_modp_many_noalloc")
         return out
 
     def gemv(self, A: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None = None,
