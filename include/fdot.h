@@ -293,15 +293,21 @@ fdot_status_t fdot_calib_read(const void* x, size_t n_words, uint32_t blocks, ui
 
 /* fdot_calib_mfma: each wavefront of `blocks` workgroups of 512 threads
  * (0 = 2 per compute unit) runs `iters` rounds of four independent matrix
- * products on register operands whose every element is a (left) and b
- * (right).  kind 0: int8 32x32x32 products with int32 accumulation (a, b
- * integers in [-128, 127]), result int32; kind 1: FP64 16x16x4 products,
- * result double.  result: device array of two elements, 8-byte aligned;
- * result[0] = element 0 of the first wavefront's first accumulator, i.e.
- * iters * 32 * a * b (int32, wrapping) or iters * 4 * a * b; result[1] is a
- * sink that keeps the other accumulators live and is written only for
- * non-finite operands.  *ops (host, may be NULL) = operations executed, two
- * per multiply-add.  FDOT_E_INVALID_ARG for another kind or operand. */
+ * products on register operands.  kind 0: int8 32x32x32 products with int32
+ * accumulation, every left operand element a and right one b (integers in
+ * [-128, 127]), result int32; kind 1: FP64 16x16x4 products, result double;
+ * kind 2: int8 32x32x32 on pseudo-random operand bytes (a = seed, an integer
+ * in [0, 2^32); b unused): chain c of lane l holds the words
+ * h(a ^ h(256 l + 4 c + w)) of the left operand and h(a ^ h(256 l + 128 + w))
+ * of the right one, w < 4, h the lowbias32 integer hash.  Matrix-core power,
+ * and so the clock, depends on operand bits: kinds 0 and 1 measure the issue
+ * rate, kind 2 what random data can reach.  result: device array of two
+ * elements, 8-byte aligned; result[0] = element 0 of the first wavefront's
+ * first accumulator, i.e. iters * 32 * a * b (kind 0, int32, wrapping),
+ * iters * 4 * a * b (kind 1), iters * (bytewise dot of lanes 0 and 32)
+ * (kind 2, wrapping); result[1] is a sink that keeps the other accumulators
+ * live.  *ops (host, may be NULL) = operations executed, two per
+ * multiply-add.  FDOT_E_INVALID_ARG for another kind or operand. */
 fdot_status_t fdot_calib_mfma(int kind, uint32_t blocks, uint32_t iters, double a, double b,
                               void* result, uint64_t* ops, void* stream);
 
@@ -372,6 +378,22 @@ fdot_status_t fgemm_modp(fdot_field_t f, size_t M, size_t N, size_t K, const voi
 /* Pre-size the per-stream workspace for batches of up to `count` instances.
  * Call before capturing a stream into a HIP graph: a capture cannot allocate. */
 fdot_status_t fdot_workspace_reserve(void* stream, size_t count);
+
+/* Kernel trace, for measuring a streaming kernel apart from the launches
+ * around it (a batched call is a plan launch and the streaming kernel).
+ * While enabled, every streaming dot-product kernel (the single form of
+ * fdot_modp*, the batched kernel of fdot_modp_many*) is bracketed by a pair
+ * of HIP events recorded on the call's own stream.  fdot_trace_enable(1)
+ * starts a new record (event pairs are created on first use and reused, at
+ * most 65536 per record); fdot_trace_enable(0) stops recording.
+ * fdot_trace_read waits for the recorded events and writes the device time
+ * of each traced kernel in milliseconds, in launch order, to ms[0 ..
+ * min(cap, *count) - 1]; *count = kernels recorded.  FDOT_E_NOMEM if the
+ * record overflowed or an event could not be created.  Host only apart from
+ * the event records; not for use while another thread is issuing traced
+ * calls. */
+fdot_status_t fdot_trace_enable(int on);
+fdot_status_t fdot_trace_read(double* ms, size_t cap, size_t* count);
 
 /* Tuned launch parameters, keyed by name (e.g. "chunk.zpz", "wg_per_cu.zpz").
  * fdot_tune_set with value INT64_MIN removes the key (back to the built-in

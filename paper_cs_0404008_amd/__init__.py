@@ -89,6 +89,8 @@ _sig("fdot_modp_many_noalloc", [_vp, _i32, _sz, _vp, _vp, _vp])
 _sig("fgemv_modp", [_vp, _sz, _sz, _vp, _sz, _vp, _vp, _vp])
 _sig("fgemm_modp", [_vp, _sz, _sz, _sz, _vp, _sz, _vp, _sz, _vp, _sz, _vp])
 _sig("fdot_workspace_reserve", [_vp, _sz])
+_sig("fdot_trace_enable", [_i32])
+_sig("fdot_trace_read", [_vp, _sz, ctypes.POINTER(_sz)])
 _sig("fdot_tune_set", [ctypes.c_char_p, _i64])
 _sig("fdot_tune_get", [ctypes.c_char_p, ctypes.POINTER(_i64)])
 _sig("fdot_calib_read", [_vp, _sz, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp])
@@ -216,6 +218,23 @@ def tune_get(key: str):
     return None if st != 0 else out.value
 
 
+def trace_enable(on: bool = True) -> None:
+    """Start (on) or stop recording the device time of every streaming
+    dot-product kernel (fdot_trace_enable)."""
+    _check(_lib.fdot_trace_enable(1 if on else 0), "fdot_trace_enable")
+
+
+def trace_read():
+    """Device milliseconds of each traced kernel since trace_enable(True), in
+    launch order (waits for them)."""
+    import numpy as np
+    n = _sz()
+    _check(_lib.fdot_trace_read(None, 0, ctypes.byref(n)), "fdot_trace_read")
+    out = np.zeros(max(n.value, 1), dtype=np.float64)
+    _check(_lib.fdot_trace_read(out.ctypes.data, n.value, ctypes.byref(n)), "fdot_trace_read")
+    return out[:n.value]
+
+
 def workspace_reserve(count: int, stream=None) -> None:
     _check(_lib.fdot_workspace_reserve(_stream(stream), count), "fdot_workspace_reserve")
 
@@ -232,10 +251,11 @@ def calib_read(x: torch.Tensor, out: torch.Tensor, blocks: int = 0, unroll: int 
 
 def calib_mfma(kind: str, iters: int, a, b, out: torch.Tensor, blocks: int = 0,
                stream=None) -> int:
-    """Matrix-core issue loop (kind "i8" or "f64"); out: two-element device
-    tensor (int32 or float64).  Returns the operations it executes."""
+    """Matrix-core issue loop (kind "i8", "f64", or "i8_random" with a = seed);
+    out: two-element device tensor (int32 or float64).  Returns the
+    operations it executes."""
     ops = _u64()
-    _check(_lib.fdot_calib_mfma({"i8": 0, "f64": 1}[kind], blocks, iters, float(a), float(b),
+    _check(_lib.fdot_calib_mfma({"i8": 0, "f64": 1, "i8_random": 2}[kind], blocks, iters, float(a), float(b),
                                 _ptr(out), ctypes.byref(ops), _stream(stream)),
            "fdot_calib_mfma")
     return ops.value

@@ -1,7 +1,8 @@
 // Measured peaks, reported beside the datasheet figures: a plain read-only
 // reduction (the rate at which HBM feeds a kernel that does nothing but read
 // and add), and back-to-back matrix instructions on register operands (the
-// rate at which the matrix cores retire work with no memory traffic).  No
+// rate at which the matrix cores retire work with no memory traffic; for
+// int8 on constant and on pseudo-random operands).  No
 // part of the method runs here; the roofline fractions of the library's
 // kernels are quoted against both kinds of peak.
 #include "fdot_internal.h"
@@ -74,6 +75,51 @@ __global__ __launch_bounds__(MT) void mfma_i8_loop_kernel(uint32_t iters, int a,
   if (other == INT32_MIN + 1) result[1] = other;
 }
 
+// Operand words of the random-operand loop: the "lowbias32" integer hash
+// (C. Wellons) of (lane, chain, word), mixed with the seed.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// The int8 loop on operands that look like data: every lane holds its own
+// pseudo-random bytes (chain c of A: words mix(seed ^ mix(lane 256 + 4c + w)),
+// B: words mix(seed ^ mix(lane 256 + 128 + w)), w < 4).  Matrix-core power,
+// hence the clock the chip holds, depends on the operand bits: constant
+// operands measure the issue rate, these the rate a product of random
+// residues can reach with no memory traffic at all.  Element 0 of chain 0
+// of the first wavefront gains sum_k A[0][k] B[k][0] per product, i.e. the
+// bytewise dot products of lanes 0 and 32.
+__global__ __launch_bounds__(MT) void mfma_i8_rand_loop_kernel(uint32_t iters, uint32_t seed,
+                                                               int32_t* result) {
+  const uint32_t lane = threadIdx.x & 63u;
+  v4i va[CH], vb;
+#pragma unroll
+  for (int c = 0; c < CH; ++c)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) va[c][w] = (int)mix32(seed ^ mix32(lane * 256u + 4u * c + w));
+#pragma unroll
+  for (int w = 0; w < 4; ++w) vb[w] = (int)mix32(seed ^ mix32(lane * 256u + 128u + w));
+  v16i acc[CH];
+#pragma unroll
+  for (int c = 0; c < CH; ++c)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[c][e] = 0;
+  for (uint32_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) acc[c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(va[c], vb, acc[c], 0, 0, 0);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) result[0] = acc[0][0];
+  int32_t other = 0;
+#pragma unroll
+  for (int c = 1; c < CH; ++c) other ^= acc[c][0] ^ acc[c][15];
+  if (other == 0x7FFFFFFF && blockIdx.x == 0 && threadIdx.x == 0) result[1] = other;
+}
+
 // The same with FP64 products 16x16x4: each element gains 4ab per product.
 __global__ __launch_bounds__(MT) void mfma_f64_loop_kernel(uint32_t iters, double a, double b,
                                                            double* result) {
@@ -115,15 +161,20 @@ extern "C" fdot_status_t fdot_calib_read(const void* x, size_t n_words, uint32_t
 
 extern "C" fdot_status_t fdot_calib_mfma(int kind, uint32_t blocks, uint32_t iters, double a,
                                          double b, void* result, uint64_t* ops, void* stream) {
-  if (!result || (kind != 0 && kind != 1) || ((uintptr_t)result & 7u)) return FDOT_E_INVALID_ARG;
+  if (!result || kind < 0 || kind > 2 || ((uintptr_t)result & 7u)) return FDOT_E_INVALID_ARG;
   if (kind == 0 && !(a >= -128.0 && a <= 127.0 && b >= -128.0 && b <= 127.0 &&
                      a == (double)(int)a && b == (double)(int)b))
     return FDOT_E_INVALID_ARG;
+  if (kind == 2 && !(a >= 0.0 && a <= 4294967295.0 && a == (double)(uint32_t)a))
+    return FDOT_E_INVALID_ARG;
   const hipStream_t s = (hipStream_t)stream;
   const uint32_t grid = blocks ? blocks : (uint32_t)fd_cu_count() * 2u;
-  const uint64_t per_product = kind == 0 ? 2ull * 32 * 32 * 32 : 2ull * 16 * 16 * 4;
+  const uint64_t per_product = kind != 1 ? 2ull * 32 * 32 * 32 : 2ull * 16 * 16 * 4;
   if (ops) *ops = (uint64_t)grid * (MT / 64) * iters * CH * per_product;
-  if (kind == 0)
+  if (kind == 2)
+    hipLaunchKernelGGL(mfma_i8_rand_loop_kernel, dim3(grid), dim3(MT), 0, s, iters,
+                       (uint32_t)a, (int32_t*)result);
+  else if (kind == 0)
     hipLaunchKernelGGL(mfma_i8_loop_kernel, dim3(grid), dim3(MT), 0, s, iters, (int)a, (int)b,
                        (int32_t*)result);
   else

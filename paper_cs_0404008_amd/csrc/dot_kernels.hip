@@ -1294,8 +1294,10 @@ static fdot_status_t launch_t(Launch A) {
     const uint64_t need = (A.work_waves + WPW - 1) / WPW;
     if (need < grid) grid = need;
     if (grid < 1) grid = 1;
+    const int tr = fd_trace_begin(A.s);
     hipLaunchKernelGGL((dot_kernel<Pol, NTH>), dim3((unsigned)grid), dim3(NTH), A.lds, A.s, A.F,
                        A.J);
+    fd_trace_end(A.s, tr);
     return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
   }
   // Groups of S resident wavefronts; a pair meets at most R ranges, so
@@ -1317,15 +1319,19 @@ static fdot_status_t launch_t(Launch A) {
   J.groups = (uint32_t)groups;
   J.max_ranges = (uint32_t)max_ranges;
   if (fused) {
+    const int tr = fd_trace_begin(A.s);
     hipLaunchKernelGGL((many_kernel<Pol, NTH, true>), dim3((unsigned)grid), dim3(NTH), lds, A.s,
                        A.F, J);
+    fd_trace_end(A.s, tr);
   } else {
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(PLAN_NT), 0, A.s, J.desc, J.count,
                        (uint32_t)groups, S, A.range, (uint32_t)max_ranges, A.ws->first,
                        A.ws->units, A.ws->start, A.ws->tq, J.results, A.elem_bytes);
     if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
+    const int tr = fd_trace_begin(A.s);
     hipLaunchKernelGGL((many_kernel<Pol, NTH, false>), dim3((unsigned)grid), dim3(NTH), A.lds,
                        A.s, A.F, J);
+    fd_trace_end(A.s, tr);
   }
   return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
 }

@@ -61,6 +61,11 @@ fdot_status_t fd_scratch_get(hipStream_t s, size_t bytes, void** out);
 // blocks for reuse.
 hipError_t fd_alloc_async(void** p, size_t bytes, hipStream_t s);
 int64_t fd_tune(const char* key, int64_t fallback);
+// Kernel trace (fdot_trace_enable): fd_trace_begin records the start event of
+// a traced kernel on s and returns its slot (-1 when tracing is off or the
+// pool is full); fd_trace_end records its end.
+int fd_trace_begin(hipStream_t s);
+void fd_trace_end(hipStream_t s, int slot);
 int fd_cu_count();
 
 // Launchers (dot_kernels.hip, gemm_kernels.hip).  All validate nothing: the

@@ -48,7 +48,43 @@ void load_tune_file_locked() {
 
 bool aligned_to(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// Kernel trace: a pool of event pairs, reused from the start at every enable.
+constexpr size_t kTraceMax = 1u << 16;
+std::mutex g_tr_mu;
+bool g_tr_on = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_tr_pool;
+size_t g_tr_used = 0;
+bool g_tr_lost = false;
+
 }  // namespace
+
+int fd_trace_begin(hipStream_t s) {
+  std::lock_guard<std::mutex> g(g_tr_mu);
+  if (!g_tr_on) return -1;
+  if (g_tr_used == g_tr_pool.size()) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (g_tr_pool.size() >= kTraceMax || hipEventCreate(&a) != hipSuccess) {
+      g_tr_lost = true;
+      return -1;
+    }
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      g_tr_lost = true;
+      return -1;
+    }
+    g_tr_pool.emplace_back(a, b);
+  }
+  const int slot = (int)g_tr_used++;
+  if (hipEventRecord(g_tr_pool[slot].first, s) != hipSuccess) g_tr_lost = true;
+  return slot;
+}
+
+void fd_trace_end(hipStream_t s, int slot) {
+  if (slot < 0) return;
+  std::lock_guard<std::mutex> g(g_tr_mu);
+  if ((size_t)slot < g_tr_pool.size() && hipEventRecord(g_tr_pool[slot].second, s) != hipSuccess)
+    g_tr_lost = true;
+}
 
 int64_t fd_tune(const char* key, int64_t fallback) {
   std::lock_guard<std::mutex> g(g_tune_mu);
@@ -190,6 +226,31 @@ fdot_status_t fdot_tune_get(const char* key, int64_t* value) {
   auto it = g_tune.find(key);
   if (it == g_tune.end()) return FDOT_E_NOT_FOUND;
   *value = it->second;
+  return FDOT_OK;
+}
+
+fdot_status_t fdot_trace_enable(int on) {
+  std::lock_guard<std::mutex> g(g_tr_mu);
+  g_tr_on = on != 0;
+  if (g_tr_on) {
+    g_tr_used = 0;
+    g_tr_lost = false;
+  }
+  return FDOT_OK;
+}
+
+fdot_status_t fdot_trace_read(double* ms, size_t cap, size_t* count) {
+  if (!count || (cap && !ms)) return FDOT_E_INVALID_ARG;
+  std::lock_guard<std::mutex> g(g_tr_mu);
+  if (g_tr_lost) return FDOT_E_NOMEM;
+  *count = g_tr_used;
+  for (size_t i = 0; i < g_tr_used && i < cap; ++i) {
+    if (hipEventSynchronize(g_tr_pool[i].second) != hipSuccess) return FDOT_E_DEVICE;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, g_tr_pool[i].first, g_tr_pool[i].second) != hipSuccess)
+      return FDOT_E_DEVICE;
+    ms[i] = t;
+  }
   return FDOT_OK;
 }
 

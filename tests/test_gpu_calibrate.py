@@ -42,6 +42,38 @@ def test_mfma_i8_loop(a, b, iters):
     assert ops == 3 * 8 * iters * 4 * 2 * 32 ** 3
 
 
+def _lowbias32(x):
+    """The lowbias32 integer hash (C. Wellons), on Python integers."""
+    x &= 0xFFFFFFFF
+    x ^= x >> 16
+    x = (x * 0x7FEB352D) & 0xFFFFFFFF
+    x ^= x >> 15
+    x = (x * 0x846CA68B) & 0xFFFFFFFF
+    x ^= x >> 16
+    return x
+
+
+def _sbytes(word):
+    return [((word >> (8 * j)) & 0xFF) - (256 if (word >> (8 * j)) & 0x80 else 0) for j in range(4)]
+
+
+@pytest.mark.parametrize("seed,iters", [(0, 1), (12345, 3), (4294967295, 1000)])
+def test_mfma_i8_random_operand_loop(seed, iters):
+    """Element 0 of the first accumulator = iters x (bytewise dot of lanes 0
+    and 32 of chain 0's left operand with the right operand), int32 wrap."""
+    out = torch.zeros(2, dtype=torch.int32, device="cuda")
+    ops = fd.calib_mfma("i8_random", iters, seed, 0, out, blocks=5)
+    per = 0
+    for lane in (0, 32):
+        for w in range(4):
+            a = _lowbias32(seed ^ _lowbias32(lane * 256 + w))
+            b = _lowbias32(seed ^ _lowbias32(lane * 256 + 128 + w))
+            per += sum(x * y for x, y in zip(_sbytes(a), _sbytes(b)))
+    want = (iters * per + (1 << 31)) % (1 << 32) - (1 << 31)
+    assert int(out[0].item()) == want
+    assert ops == 5 * 8 * iters * 4 * 2 * 32 ** 3
+
+
 @pytest.mark.parametrize("a,b,iters", [(1.5, 2.0, 1000), (-0.25, 8.0, 7)])
 def test_mfma_f64_loop(a, b, iters):
     out = torch.zeros(2, dtype=torch.float64, device="cuda")
@@ -62,5 +94,7 @@ def test_calib_rejects_bad_arguments():
         fd.calib_mfma("i8", 1, 200, 1, out.view(torch.int32))
     with pytest.raises(fd.FdotError):
         fd.calib_mfma("i8", 1, 0.5, 1, out.view(torch.int32))
+    with pytest.raises(fd.FdotError):
+        fd.calib_mfma("i8_random", 1, -1, 0, out.view(torch.int32))
     with pytest.raises(KeyError):
         fd.calib_mfma("bf16", 1, 1, 1, out)
