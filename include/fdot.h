@@ -410,10 +410,16 @@ fdot_status_t fdot_tune_get(const char* key, int64_t* value);
  * run are admitted as soon as an in-flight slot and enough of the HBM
  * budget are free; at every scheduling step the admitted dot requests of one
  * field are fused into one batched launch, and launches are spread over
- * several HIP streams so that their work overlaps on the device.  Results
- * are exact, so a request's result is the same alone and in any mix.
- * Operands stay device-resident and owned by the caller until the request is
- * done; the server never copies or frees them. */
+ * several HIP streams by estimated device time: long matrix products on one,
+ * long streaming requests on another, everything shorter than short_ns on
+ * the rest, so that short requests never wait behind long ones in a stream
+ * and the work of different requests overlaps on the device.  Results are
+ * exact, so a request's result is the same alone and in any mix.  Operands
+ * stay device-resident and owned by the caller until the request is done;
+ * the server never copies or frees them.  The server's launches run on its
+ * own streams: operands must be complete on the device when the request is
+ * submitted, or the request names a HIP event (ready) that its launch
+ * waits for. */
 
 typedef enum { FDOT_OP_DOT = 0, FDOT_OP_GEMV = 1, FDOT_OP_GEMM = 2 } fdot_op_t;
 
@@ -426,7 +432,11 @@ typedef struct {
   void* out;           /* DOT: 1 elem; GEMV: y (m);      GEMM: C (m x n) */
   uint64_t m, n, k;    /* dense row-major operands, leading dimension = row length */
   uint64_t footprint;  /* device bytes charged against the budget while the request
-                          is admitted; 0 = its operand and result bytes */
+                          is admitted; 0 = its operand and result bytes plus the
+                          library scratch it takes (an upper bound) */
+  void* ready;         /* optional hipEvent_t recorded after the operands were
+                          produced; the request's launch waits for it (NULL: the
+                          operands are complete at submit) */
 } fdot_request_t;
 
 typedef struct {
@@ -444,6 +454,16 @@ typedef struct {
                             overlap never slows the longest requests (0 = off:
                             on the mixed stream it cost more waiting behind
                             long requests than it saved) */
+  uint64_t short_ns;     /* with three or more streams: matrix products run on
+                            stream 0; streaming requests (or fused dot batches)
+                            estimated below short_ns on streams 2.., longer ones
+                            on stream 1; 0 = 100 us */
+  uint32_t matrix_depth; /* at most this many matrix products outstanding on
+                            stream 0; the others wait in the server, admitted, and
+                            the shortest estimate goes next (the oldest once it has
+                            waited four times its estimate, at least 2 ms); 0 = 2;
+                            UINT32_MAX: no limit (each launched when admitted) */
+  uint32_t reserved;
 } fdot_server_cfg_t;
 
 typedef struct {
@@ -453,6 +473,8 @@ typedef struct {
   uint64_t done_ns;      /* when the scheduler saw its launch complete */
   int32_t status;        /* FDOT_OK, or the error of its launch */
   uint32_t batch_size;   /* requests carried by the same launch */
+  uint32_t stream;       /* index of the server stream it was launched on */
+  uint32_t reserved;
 } fdot_timing_t;
 
 typedef struct {

@@ -430,19 +430,21 @@ OPS = {"dot": 0, "gemv": 1, "gemm": 2}
 class Request(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("reserved", ctypes.c_int32), ("field", _vp),
                 ("a", _vp), ("b", _vp), ("out", _vp), ("m", _u64), ("n", _u64), ("k", _u64),
-                ("footprint", _u64)]
+                ("footprint", _u64), ("ready", _vp)]
 
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", _u64), ("max_inflight", ctypes.c_uint32),
                 ("max_queue", ctypes.c_uint32), ("streams", ctypes.c_uint32),
                 ("max_batch", ctypes.c_uint32), ("fake_device", ctypes.c_uint32),
-                ("plain", ctypes.c_uint32), ("exclusive_ns", _u64)]
+                ("plain", ctypes.c_uint32), ("exclusive_ns", _u64), ("short_ns", _u64),
+                ("matrix_depth", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class Timing(ctypes.Structure):
     _fields_ = [("submit_ns", _u64), ("admit_ns", _u64), ("launch_ns", _u64), ("done_ns", _u64),
-                ("status", ctypes.c_int32), ("batch_size", ctypes.c_uint32)]
+                ("status", ctypes.c_int32), ("batch_size", ctypes.c_uint32),
+                ("stream", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -462,11 +464,13 @@ _sig("fdot_server_destroy", [_vp])
 
 
 def make_request(op: str, field: "Field", a, b, out, m: int = 0, n: int = 0, k: int = 0,
-                 footprint: int = 0) -> Request:
+                 footprint: int = 0, ready=None) -> Request:
     """A request on device tensors (a, b, out) of field's dtype; a/b/out may
-    also be raw device addresses (ints)."""
+    also be raw device addresses (ints).  ready: an optional torch.cuda.Event
+    recorded after the operands were written; the launch waits for it."""
     addr = lambda t: t if isinstance(t, int) else t.data_ptr()  # noqa: E731
-    return Request(OPS[op], 0, field.handle, addr(a), addr(b), addr(out), m, n, k, footprint)
+    ev = None if ready is None else (ready.cuda_event if hasattr(ready, "cuda_event") else int(ready))
+    return Request(OPS[op], 0, field.handle, addr(a), addr(b), addr(out), m, n, k, footprint, ev)
 
 
 class Server:
@@ -474,9 +478,11 @@ class Server:
 
     def __init__(self, hbm_budget: int = 0, max_inflight: int = 0, max_queue: int = 0,
                  streams: int = 0, max_batch: int = 0, fake_device: bool = False,
-                 plain: bool = False, exclusive_ns: int = 0):
+                 plain: bool = False, exclusive_ns: int = 0, short_ns: int = 0,
+                 matrix_depth: int = 0):
         cfg = ServerConfig(hbm_budget, max_inflight, max_queue, streams, max_batch,
-                           1 if fake_device else 0, 1 if plain else 0, exclusive_ns)
+                           1 if fake_device else 0, 1 if plain else 0, exclusive_ns, short_ns,
+                           matrix_depth, 0)
         h = _vp()
         _check(_lib.fdot_server_create(ctypes.byref(cfg), ctypes.byref(h)), "fdot_server_create")
         self._h = h
@@ -520,7 +526,8 @@ class Server:
         tm = (Timing * max(n, 1))()
         _check(_lib.fdot_server_replay(self._h, arr, at, n, tm), "fdot_server_replay")
         dt = np.dtype([("submit_ns", np.uint64), ("admit_ns", np.uint64), ("launch_ns", np.uint64),
-                       ("done_ns", np.uint64), ("status", np.int32), ("batch_size", np.uint32)])
+                       ("done_ns", np.uint64), ("status", np.int32), ("batch_size", np.uint32),
+                       ("stream", np.uint32), ("reserved", np.uint32)])
         return np.frombuffer(bytes(tm), dtype=dt, count=n).copy()
 
     def stats(self) -> dict:

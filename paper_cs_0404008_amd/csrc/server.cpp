@@ -11,10 +11,21 @@
 //   3. launches everything admitted: the dot requests of one field are fused
 //      into one batched launch (descriptors staged through pinned memory,
 //      results scattered back to each request's output), matrix-vector and
-//      matrix products are launched one by one.  Matrix products, bound by
-//      the matrix cores, go in arrival order to one stream, so two of them
-//      never share the chip; the HBM-bound requests go to the least-loaded
-//      of the other streams (by estimated outstanding work) and overlap them.
+//      matrix products are launched one by one, each on a lane chosen by
+//      its estimated device time (below).
+// Lanes (three or more streams): every matrix product goes to stream 0
+// (bound by the matrix cores, and a large one takes whole CUs: two products
+// never share the chip, and a product never holds up streaming work queued
+// behind it in another stream); a streaming request (matrix-vector product,
+// fused dot batch) estimated to take at least short_ns goes to stream 1, a
+// shorter one to the least-loaded of the remaining streams.  A HIP stream
+// runs its launches in order, so a short request never waits behind a long
+// one.  The server keeps matrix products admitted but unlaunched until
+// fewer than matrix_depth (default 2) are outstanding on stream 0, and
+// then releases the one with the shortest estimated time, or the oldest once
+// it has waited longer than four times its own estimate (at least 2 ms), so
+// that small products do not queue behind large ones and none waits
+// forever.
 // Requests that arrive while others run are therefore taken into the next
 // launch as soon as capacity frees up.  In "plain" mode every request is one
 // launch on one stream in arrival order: the baseline that serving is
@@ -69,15 +80,23 @@ struct Launch {
   uint64_t est = 0;   // estimated device time, counted in that stream's load
   uint64_t fake_done = 0;
   int32_t status = FDOT_OK;
+  bool matrix = false;  // a matrix product counted in matrix_out
 };
 
+// Device bytes a request holds while admitted: its operands and result, plus
+// the scratch the library takes for it (transposed or digit-split operands
+// and the residue sum of a matrix product, copies of x for a matrix-vector
+// product); an upper bound, used against the HBM budget.
 uint64_t footprint_of(const fdot_request_t& r) {
   if (r.footprint) return r.footprint;
   const uint64_t e = r.field->info.elem_bytes;
   switch (r.op) {
     case FDOT_OP_DOT: return (2 * r.n + 1) * e;
-    case FDOT_OP_GEMV: return (r.m * r.n + r.n + r.m) * e;
-    case FDOT_OP_GEMM: return (r.m * r.k + r.k * r.n + r.m * r.n) * e;
+    case FDOT_OP_GEMV: return (r.m * r.n + r.n + r.m) * e + 16 * (r.n * e + 272);
+    case FDOT_OP_GEMM: {
+      const uint64_t kp = (r.k + 127) / 128 * 128;
+      return (r.m * r.k + r.k * r.n + r.m * r.n) * e + 4 * (r.m + r.n) * kp + 4 * r.m * r.n + 4096;
+    }
   }
   return 0;
 }
@@ -130,6 +149,8 @@ struct fdot_server_s {
   std::vector<uint64_t> admitted;
   std::vector<Launch> inflight;
   bool heavy_inflight = false;  // an exclusive request is admitted or running
+  std::vector<uint64_t> held;   // admitted matrix products not yet launched (matrix_depth)
+  uint32_t matrix_out = 0;      // matrix-product launches outstanding on stream 0
   uint64_t used_fp = 0;
   uint32_t n_admitted = 0;  // admitted and not yet done
   std::vector<hipStream_t> streams;
@@ -140,16 +161,21 @@ struct fdot_server_s {
   std::vector<uint64_t> load;  // per stream: estimated ns of work issued and not done
   fdot_server_stats_t st;
 
-  // Matrix products (bound by the matrix cores) run in arrival order on
-  // stream 0, so two of them never share the chip and stretch each other;
-  // streaming requests (bound by HBM) take the least-loaded of the other
-  // streams and overlap the products.  Plain: everything on the one stream.
-  int pick_stream(const fdot_request_t& r) {
+  // The stream of a launch whose estimated device time is est (the lanes of
+  // the header comment).  Fewer than three streams: matrix products on
+  // stream 0, the rest on the least-loaded other one.  Plain: the one stream.
+  int pick_stream(const fdot_request_t& r, uint64_t est) {
     if (cfg.plain || streams.size() == 1) return 0;
     if (r.op == FDOT_OP_GEMM) return 0;
-    int best = 1 + (int)(rr++ % (streams.size() - 1));
-    for (size_t i = 1; i < streams.size(); ++i)
-      if (load[i] < load[best]) best = (int)i;
+    int first = 1;
+    if (streams.size() >= 3) {
+      if (est >= cfg.short_ns) return 1;
+      first = 2;
+    }
+    const int span = (int)streams.size() - first;
+    int best = first + (int)(rr++ % (uint32_t)span);
+    for (int i = first; i < (int)streams.size(); ++i)
+      if (load[i] < load[best]) best = i;
     return best;
   }
 
@@ -185,6 +211,8 @@ struct fdot_server_s {
   // Launch one request by itself.
   fdot_status_t launch_one(Req& q, hipStream_t s) {
     const fdot_request_t& r = q.r;
+    if (r.ready && hipStreamWaitEvent(s, (hipEvent_t)r.ready, 0) != hipSuccess)
+      return FDOT_E_DEVICE;
     switch (r.op) {
       case FDOT_OP_DOT: {
         Workspace* w = nullptr;
@@ -213,11 +241,14 @@ struct fdot_server_s {
     if (L.ev) free_events.push_back(L.ev);
     if (L.slot >= 0) slots[L.slot].busy = false;
     load[L.stream] -= L.est;
+    if (L.matrix) --matrix_out;
   }
 
   void issue(std::vector<uint64_t> tickets, int si, uint64_t est, fdot_status_t stt, int slot) {
     hipStream_t s = streams[si];
     Launch L;
+    L.matrix = !cfg.plain && tickets.size() == 1 && reqs[tickets[0]].r.op == FDOT_OP_GEMM;
+    if (L.matrix) ++matrix_out;
     L.tickets = std::move(tickets);
     L.slot = slot;
     L.stream = si;
@@ -229,6 +260,7 @@ struct fdot_server_s {
       Req& q = reqs[tk];
       q.t.launch_ns = now;
       q.t.batch_size = (uint32_t)L.tickets.size();
+      q.t.stream = (uint32_t)si;
       dur = std::max(dur, fake_ns(q.r));
     }
     ++st.launches;
@@ -252,8 +284,8 @@ struct fdot_server_s {
     if (cfg.plain || cfg.fake_device) {
       if (cfg.plain) {
         for (uint64_t tk : todo) {
-          const int si = pick_stream(reqs[tk].r);
           const uint64_t est = est_ns(reqs[tk].r);
+          const int si = pick_stream(reqs[tk].r, est);
           load[si] += est;
           const fdot_status_t stt = cfg.fake_device ? FDOT_OK : launch_one(reqs[tk], streams[si]);
           issue({tk}, si, est, stt, -1);
@@ -267,9 +299,11 @@ struct fdot_server_s {
       Req& q = reqs[tk];
       if (q.r.op == FDOT_OP_DOT) {
         dots[q.r.field].push_back(tk);
+      } else if (q.r.op == FDOT_OP_GEMM) {
+        held.push_back(tk);
       } else {
-        const int si = pick_stream(q.r);
         const uint64_t est = est_ns(q.r);
+        const int si = pick_stream(q.r, est);
         load[si] += est;
         const fdot_status_t stt = cfg.fake_device ? FDOT_OK : launch_one(q, streams[si]);
         issue({tk}, si, est, stt, -1);
@@ -280,10 +314,10 @@ struct fdot_server_s {
       for (size_t b = 0; b < v.size(); b += cfg.max_batch) {
         const size_t e = std::min(v.size(), b + (size_t)cfg.max_batch);
         std::vector<uint64_t> group(v.begin() + b, v.begin() + e);
-        const int si = pick_stream(reqs[group[0]].r);
-        hipStream_t s = streams[si];
         uint64_t est = 0;
         for (uint64_t tk : group) est += est_ns(reqs[tk].r);
+        const int si = pick_stream(reqs[group[0]].r, est);
+        hipStream_t s = streams[si];
         load[si] += est;
         if (cfg.fake_device) {
           issue(group, si, est, FDOT_OK, -1);
@@ -313,7 +347,13 @@ struct fdot_server_s {
         const size_t bytes = n * (sizeof(fdot_desc_t) + sizeof(void*));
         fdot_status_t stt = FDOT_OK;
         Workspace* w = nullptr;
-        if (hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s) != hipSuccess) stt = FDOT_E_DEVICE;
+        for (uint64_t tk : group) {
+          const fdot_request_t& r = reqs[tk].r;
+          if (r.ready && hipStreamWaitEvent(s, (hipEvent_t)r.ready, 0) != hipSuccess)
+            stt = FDOT_E_DEVICE;
+        }
+        if (stt == FDOT_OK && hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+          stt = FDOT_E_DEVICE;
         if (stt == FDOT_OK) stt = fd_workspace_get(s, n, &w);
         void* results = d + bytes;
         if (stt == FDOT_OK)
@@ -324,6 +364,34 @@ struct fdot_server_s {
         issue(group, si, est, stt, slot);
       }
     }
+  }
+
+  // Launch held matrix products while fewer than matrix_depth are
+  // outstanding: the shortest estimate first, the oldest once it has waited
+  // more than max(2 ms, 4 x its estimate).  Returns whether any launched.
+  bool release_held() {
+    bool any = false;
+    const uint64_t now = now_ns();
+    while (!held.empty() && matrix_out < cfg.matrix_depth) {
+      size_t pick = 0;
+      for (size_t i = 1; i < held.size(); ++i)
+        if (est_ns(reqs[held[i]].r) < est_ns(reqs[held[pick]].r)) pick = i;
+      size_t oldest = 0;
+      for (size_t i = 1; i < held.size(); ++i)
+        if (reqs[held[i]].t.admit_ns < reqs[held[oldest]].t.admit_ns) oldest = i;
+      const Req& o = reqs[held[oldest]];
+      const uint64_t patience = std::max<uint64_t>(2000000, 4 * est_ns(o.r));
+      if (now - o.t.admit_ns > patience) pick = oldest;
+      const uint64_t tk = held[pick];
+      held.erase(held.begin() + (ptrdiff_t)pick);
+      Req& q = reqs[tk];
+      const uint64_t est = est_ns(q.r);
+      load[0] += est;
+      const fdot_status_t stt = cfg.fake_device ? FDOT_OK : launch_one(q, streams[0]);
+      issue({tk}, 0, est, stt, -1);
+      any = true;
+    }
+    return any;
   }
 
   void run() {
@@ -374,8 +442,9 @@ struct fdot_server_s {
         launch_admitted();
         moved = true;
       }
+      if (!held.empty() && release_held()) moved = true;
       if (moved) progress.notify_all();
-      if (stop && pending.empty() && admitted.empty() && inflight.empty()) break;
+      if (stop && pending.empty() && admitted.empty() && held.empty() && inflight.empty()) break;
       if (!moved) {
         if (inflight.empty())
           wake.wait_for(lk, std::chrono::milliseconds(1));
@@ -411,8 +480,12 @@ fdot_status_t fdot_server_create(const fdot_server_cfg_t* cfg, fdot_server_t* ou
     c.fake_device = cfg->fake_device;
     c.plain = cfg->plain;
     c.exclusive_ns = cfg->exclusive_ns;
+    c.short_ns = cfg->short_ns;
+    c.matrix_depth = cfg->matrix_depth;
   }
+  if (c.matrix_depth == 0) c.matrix_depth = 2;
   if (c.exclusive_ns == 0) c.exclusive_ns = ~0ull;  // off
+  if (c.short_ns == 0) c.short_ns = 100000;
   if (c.streams > 64) return FDOT_E_INVALID_ARG;
   fdot_server_s* s = new (std::nothrow) fdot_server_s;
   if (!s) return FDOT_E_NOMEM;

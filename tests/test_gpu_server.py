@@ -121,3 +121,42 @@ def test_served_burst_and_back_pressure():
         assert same(to_host(o), w)
     assert srv.stats()["peak_inflight"] <= 8
     srv.close()
+
+
+def test_ready_event_orders_operands():
+    """Operands written on another stream: each request names the event
+    recorded after its operands, and its launch waits for it."""
+    p, rep = 65521, "zpz"
+    F = fd.Field(p, rep)
+    side = torch.cuda.Stream()
+    n = 1 << 20
+    src = [torch.empty(n, dtype=torch.uint32, device="cuda") for _ in range(2)]
+    fill(src[0], p, rep, 70, 0)
+    fill(src[1], p, rep, 70, 1)
+    torch.cuda.synchronize()
+    x = torch.zeros(n, dtype=torch.uint32, device="cuda")
+    y = torch.zeros(n, dtype=torch.uint32, device="cuda")
+    out = torch.empty(1, dtype=torch.uint32, device="cuda")
+    A = torch.zeros((512, 512), dtype=torch.uint32, device="cuda")
+    v = torch.empty(512, dtype=torch.uint32, device="cuda")
+    yv = torch.empty(512, dtype=torch.uint32, device="cuda")
+    torch.cuda.synchronize()
+    srv = fd.Server(streams=4)
+    with torch.cuda.stream(side):
+        for _ in range(20):  # keep the side stream busy for a while first
+            x.copy_(src[1])
+        x.copy_(src[0])
+        y.copy_(src[1])
+        A.copy_(src[0][:512 * 512].view(512, 512))
+        v.copy_(src[1][:512])
+        ev = torch.cuda.Event()
+        ev.record(side)
+    t1 = srv.submit(fd.make_request("dot", F, x, y, out, n=n, ready=ev))
+    t2 = srv.submit(fd.make_request("gemv", F, A, v, yv, m=512, n=512, ready=ev))
+    srv.drain(60000)
+    assert srv.poll(t1)[1].status == 0 and srv.poll(t2)[1].status == 0
+    srv.close()
+    torch.cuda.synchronize()
+    xh, yh = to_host(src[0]), to_host(src[1])
+    assert same(to_host(out), oracle.dot(p, rep, xh, yh).reshape(1))
+    assert same(to_host(yv), oracle.gemv(p, rep, xh[:512 * 512].reshape(512, 512), yh[:512]))

@@ -83,7 +83,9 @@ def test_batching_and_plain_mode():
 
 def test_back_pressure_and_rejection():
     big = fd.make_request("gemm", F2, FAKE, FAKE, FAKE, m=4096, n=4096, k=4096)  # ~1.5 ms simulated
-    srv = fd.Server(fake_device=True, hbm_budget=big.footprint or 3 * 4096 * 4096 * 8,
+    # room for the product, its library scratch (digit planes, residue sum)
+    # and the small requests, not for two products
+    srv = fd.Server(fake_device=True, hbm_budget=2 * 3 * 4096 * 4096 * 8,
                     max_inflight=1, max_queue=4)
     srv.submit(big)
     statuses = [srv.try_submit(dot(F1, 10))[0] for _ in range(8)]
@@ -134,3 +136,59 @@ def test_long_requests_run_alone():
     srv2.drain(20000)
     tm = [srv2.poll(t)[1] for t in ts]
     assert tm[4].admit_ns < tm[3].done_ns
+
+
+def test_lanes_by_estimated_time():
+    """With four streams: matrix products on stream 0, long streaming
+    requests on stream 1, streaming requests estimated below short_ns on
+    streams 2 and 3; plain mode keeps one stream."""
+    srv = fd.Server(fake_device=True, streams=4, short_ns=100_000, max_inflight=64)
+    long_gemm = srv.submit(fd.make_request("gemm", F2, FAKE, FAKE, FAKE, m=2048, n=2048, k=2048))
+    long_gemv = srv.submit(fd.make_request("gemv", F2, FAKE, FAKE, FAKE, m=20000, n=20000))
+    small_gemm = srv.submit(fd.make_request("gemm", F3, FAKE, FAKE, FAKE, m=64, n=64, k=64))
+    small_gemv = srv.submit(fd.make_request("gemv", F1, FAKE, FAKE, FAKE, m=100, n=100))
+    dots = [srv.submit(dot(F1, 1000)) for _ in range(5)]
+    srv.drain(20000)
+    lane = lambda t: srv.poll(t)[1].stream  # noqa: E731
+    assert lane(long_gemm) == 0 and lane(long_gemv) == 1
+    assert lane(small_gemm) == 0  # every matrix product on the matrix lane
+    assert lane(small_gemv) in (2, 3)
+    assert all(lane(t) in (2, 3) for t in dots)
+    srv.close()
+    plain = fd.Server(fake_device=True, plain=True)
+    ts = [plain.submit(fd.make_request("gemm", F2, FAKE, FAKE, FAKE, m=2048, n=2048, k=2048)),
+          plain.submit(dot(F1, 1000))]
+    plain.drain(20000)
+    assert all(plain.poll(t)[1].stream == 0 for t in ts)
+
+
+def test_footprint_counts_library_scratch():
+    """The admitted footprint of a matrix product includes the scratch the
+    library takes for it (digit planes and the residue sum), so a budget of
+    exactly its operand bytes refuses it."""
+    m = n = k = 1024
+    operands = (m * k + k * n + m * n) * 8
+    srv = fd.Server(fake_device=True, hbm_budget=operands)
+    assert srv.try_submit(fd.make_request("gemm", F2, FAKE, FAKE, FAKE, m=m, n=n, k=k))[0] == -6
+    srv.close()
+
+
+def test_matrix_products_shortest_first_with_aging():
+    """matrix_depth = 1: one product outstanding at a time; of the waiting
+    ones the shortest estimate goes next, so small products overtake a queue
+    of large ones, and a large one still runs once it has waited long."""
+    srv = fd.Server(fake_device=True, streams=4, matrix_depth=1, max_inflight=64)
+    big = lambda: fd.make_request("gemm", F2, FAKE, FAKE, FAKE, m=1536, n=1536, k=1536)  # noqa: E731
+    small = lambda: fd.make_request("gemm", F3, FAKE, FAKE, FAKE, m=64, n=64, k=64)  # noqa: E731
+    order = ["b", "b", "b", "s", "s", "b", "s"]
+    ts = [srv.submit(big() if k == "b" else small()) for k in order]
+    srv.drain(60000)
+    tm = [srv.poll(t)[1] for t in ts]
+    # never two products outstanding at once
+    spans = sorted((t.launch_ns, t.done_ns) for t in tm)
+    assert all(a[1] <= b[0] for a, b in zip(spans, spans[1:]))
+    # the small ones submitted behind large ones start before the later large ones
+    for i in (3, 4, 6):
+        assert tm[i].launch_ns < tm[5].launch_ns or tm[i].launch_ns < tm[2].launch_ns
+    assert all(t.status == 0 and t.stream == 0 for t in tm)
+    srv.close()
