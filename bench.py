@@ -103,39 +103,139 @@ class Batch:
         self.F.dot_many(self.desc, out=self.out, algo=self.algo)
 
 
-def cpu_baseline(batches, max_instances=384, min_seconds=10.0):
-    """The oracle (as it stands) on the first instances of every batch,
-    regenerated on the host from the same seeds, passed over repeatedly
-    until about min_seconds of CPU work have been timed."""
+def host_cpu():
+    """(model name, cores this process may run on, threads the oracle uses:
+    the affinity count, capped by OMP_NUM_THREADS when that is set)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(aff, int(omp)) if omp.isdigit() and int(omp) > 0 else aff
+    return model, aff, threads
+
+
+def timed_passes(fn, min_seconds, max_passes=1000):
+    """Seconds per pass of fn, repeated until min_seconds have been timed."""
+    passes, elapsed = 0, 0.0
+    while (elapsed < min_seconds or passes == 0) and passes < max_passes:
+        t0 = time.perf_counter()
+        fn()
+        elapsed += time.perf_counter() - t0
+        passes += 1
+    return elapsed / passes, passes
+
+
+def cpu_baseline(batches, stride=16):
+    """The oracle (as it stands: per-term __int128 reduction, OpenMP over
+    instances) on the host cores.  Headline workload: every stride-th pair
+    of each batch (pairs spread over the whole batch), regenerated on the
+    host from the same seeds, checked bit for bit against the GPU results of
+    those pairs, then timed on one thread and on all the threads the process
+    may use.  Other workloads: labelled samples, timed the same way."""
     import oracle
     import synth
+    model, aff, threads = host_cpu()
     sample = []
     terms = 0
     for b in batches:
-        ns = b.ns[:max_instances]
-        xs = [synth.uniform_int(SEED, 2 * k, int(n), b.p).astype(np.uint32) for k, n in enumerate(ns)]
-        ys = [synth.uniform_int(SEED, 2 * k + 1, int(n), b.p).astype(np.uint32) for k, n in enumerate(ns)]
+        idx = list(range(0, len(b.ns), stride))
+        ns = [int(b.ns[k]) for k in idx]
+        xs = [synth.uniform_int(SEED, 2 * k, n, b.p).astype(np.uint32) for k, n in zip(idx, ns)]
+        ys = [synth.uniform_int(SEED, 2 * k + 1, n, b.p).astype(np.uint32) for k, n in zip(idx, ns)]
+        oracle.set_threads(threads)
         res = oracle.dot_many(b.p, b.rep, xs, ys)
-        gpu = b.out[:len(ns)].cpu().numpy()
+        gpu = b.out.cpu().numpy()[idx]
         if res.tobytes() != gpu.tobytes():
             raise SystemExit(f"GPU and oracle disagree on batch p={b.p}")
         sample.append((b, xs, ys))
         terms += int(np.sum(ns))
-    rounds = 0
-    elapsed = 0.0
-    while elapsed < min_seconds and rounds < 1000:
-        t0 = time.perf_counter()
+    nbytes = terms * 8
+
+    def pass_all():
         for b, xs, ys in sample:
             oracle.dot_many(b.p, b.rep, xs, ys)
-        elapsed += time.perf_counter() - t0
-        rounds += 1
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    nbytes = terms * 8
-    return {"value": round(nbytes * rounds / elapsed / 1e9, 4), "unit": "GB/s", "cores": cores,
-            "kind": "oracle", "gelem_per_s": round(terms * rounds / elapsed / 1e9, 4),
-            "sample": f"first {max_instances} instances of each of the 3 batches "
-                      f"({terms} terms, {nbytes / 1e9:.2f} GB) timed over {rounds} passes "
-                      f"({elapsed:.1f} s); per-term __int128 reduction, OpenMP over instances"}
+
+    oracle.set_threads(1)
+    t1, n1 = timed_passes(pass_all, 6.0)
+    oracle.set_threads(threads)
+    tn, nn = timed_passes(pass_all, 4.0)
+    out = {"value": round(nbytes / tn / 1e9, 4), "unit": "GB/s", "cores": threads,
+           "kind": "oracle", "gelem_per_s": round(terms / tn / 1e9, 4),
+           "single_thread": {"value": round(nbytes / t1 / 1e9, 4), "unit": "GB/s",
+                             "gelem_per_s": round(terms / t1 / 1e9, 4), "passes": n1},
+           "cpu_model": model, "affinity_cores": aff,
+           "sample": f"every {stride}th pair of each of the 3 batches of 4096 "
+                     f"({len(sample[0][1])} pairs per batch, {terms} terms, "
+                     f"{nbytes / 1e9:.2f} GB), all checked bit for bit against the GPU; "
+                     f"{nn} timed passes on {threads} threads, {n1} on one"}
+    out["other_workloads"] = cpu_baseline_others(threads)
+    oracle.set_threads(threads)
+    return out
+
+
+def cpu_baseline_others(threads):
+    """Labelled oracle timings of the other workloads, on samples of their
+    own inputs (regenerated on the host from their seeds)."""
+    import oracle
+    import synth
+    rows = {}
+    # single dot, p = 32749, n = 1e6, seed 1 (one dot: one thread)
+    p, n = 32749, 1_000_000
+    x = synth.uniform_int(1, 0, n, p).astype(np.uint32)
+    y = synth.uniform_int(1, 1, n, p).astype(np.uint32)
+    t, k = timed_passes(lambda: oracle.dot(p, "zpz", x, y), 1.0)
+    rows["single dot p=32749 n=1e6"] = {"ms": round(t * 1e3, 3), "gelem_per_s": round(n / t / 1e9, 4),
+                                         "threads": 1, "sample": "the whole workload"}
+    # 1024 pairs of length 4e6 (seed 3): sixteen pairs spread over the batch
+    # (one instance per thread at most: the oracle spreads instances)
+    pick = [int(k) for k in np.linspace(0, 1023, 16).round()]
+    n = 4_000_000
+    for p, rep, dt in ((67108859, "fp64", np.float64), (32749, "zech", np.uint16)):
+        # stored values uniform over the representation's range (discrete-log
+        # codes 0 .. p-1), as the GPU workload draws them
+        xs = [synth.uniform_int(3, 2 * k, n, p).astype(dt) for k in pick]
+        ys = [synth.uniform_int(3, 2 * k + 1, n, p).astype(dt) for k in pick]
+        terms = n * len(pick)
+        es = np.dtype(dt).itemsize
+        oracle.set_threads(1)
+        t1, _ = timed_passes(lambda: oracle.dot_many(p, rep, xs, ys), 1.0)
+        oracle.set_threads(threads)
+        tn, _ = timed_passes(lambda: oracle.dot_many(p, rep, xs, ys), 1.0)
+        rows[f"1024 x 4e6 {rep} p={p}"] = {
+            "GBps": round(2 * es * terms / tn / 1e9, 4), "gelem_per_s": round(terms / tn / 1e9, 4),
+            "single_thread_gelem_per_s": round(terms / t1 / 1e9, 4),
+            "threads": min(threads, len(pick)),
+            "sample": f"pairs {pick} of the 1024 ({terms} terms)"}
+    # matrix product 8192 x 8192 x 4096, p = 251 centred (seed 4): sampled
+    # entries and the two matrix-vector products of one Freivalds trial
+    p, M, K, N = 251, 8192, 8192, 4096
+    A = synth.uniform_int(4, 0, M * K, 251, -125).astype(np.int8).reshape(M, K)
+    B = synth.uniform_int(4, 1, K * N, 251, -125).astype(np.int8).reshape(K, N)
+    rng = np.random.default_rng(44)
+    rows_i, cols_i = rng.integers(0, M, 4096), rng.integers(0, N, 4096)
+    oracle.set_threads(threads)
+    te, _ = timed_passes(lambda: oracle.gemm_entries(p, "centred", A, B, rows_i, cols_i), 1.0)
+    r = synth.uniform_int(44, 0, N, 251, -125).astype(np.int8)
+
+    def freivalds_rhs():
+        oracle.gemv(p, "centred", A, oracle.gemv(p, "centred", B, r))
+
+    tf, _ = timed_passes(freivalds_rhs, 1.0)
+    rows["fgemm 8192x8192x4096 p=251 centred"] = {
+        "entries_per_s": round(4096 / te, 1), "threads": threads,
+        "full_product_s_extrapolated": round(M * N / (4096 / te), 1),
+        "freivalds_trial_ms": round(tf * 1e3, 1),
+        "sample": "4096 sampled entries (8192 terms each); one Freivalds trial's A(Br) "
+                  "(two matrix-vector products); the full-product time is an "
+                  "extrapolation from the entry rate, not a measurement"}
+    return rows
 
 
 def time_events(fn, reps):
@@ -760,6 +860,15 @@ def main():
             torch.cuda.empty_cache()
         result["extras"] = extras
     print(json.dumps(result), flush=True)
+    # bench.py starts no process of its own (the oracle library is built
+    # beforehand); name any child that exists at the end, for the record
+    try:
+        import psutil
+        kids = psutil.Process().children(recursive=True)
+        if kids:
+            log("child processes at exit: " + ", ".join(f"{k.pid} {k.name()}" for k in kids))
+    except Exception:  # the check is informational only
+        pass
 
 
 if __name__ == "__main__":

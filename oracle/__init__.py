@@ -55,6 +55,9 @@ def lib():
         L.orc_gemm.argtypes = [u64, i32, sz, sz, sz, vp, sz, vp, sz, vp, sz]
         L.orc_gemm_entries.argtypes = [u64, i32, sz, vp, sz, vp, sz, sz, vp, vp, vp]
         L.orc_gemv.argtypes = [u64, i32, sz, sz, vp, sz, vp, vp]
+        L.orc_set_threads.argtypes = [i32]
+        L.orc_set_threads.restype = None
+        L.orc_get_threads.argtypes = []
         L.orc_elementwise.argtypes = [u64, i32, i32, sz, vp, vp, vp, vp]
         L.orc_ext_modulus.argtypes = [u64, i32, vp]
         L.orc_ext_encode.argtypes = [u64, i32, vp, vp, sz]
@@ -76,6 +79,16 @@ def _arr(a, rep):
 def _check(rc: int, what: str) -> None:
     if rc != 0:
         raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+def set_threads(n: int) -> None:
+    """Threads of the batched oracle entry points (n <= 0: one per processor);
+    only the time changes, never a result."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
 
 
 def is_prime(p: int) -> bool:

@@ -35,6 +35,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef unsigned __int128 u128;
 
@@ -595,3 +598,21 @@ int orc_ext_elementwise(uint64_t p, int d, int op, size_t n, const uint16_t* a,
 }
 
 int orc_version(void) { return 1; }
+
+/* Threads of the batched entry points (for timing the oracle; every result is
+ * computed the same way whatever the count).  n <= 0: one per processor. */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+  (void)n;
+#endif
+}
+
+int orc_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
