@@ -46,7 +46,9 @@ typedef enum {
   FDOT_E_DEVICE = -5,      /* a HIP call failed */
   FDOT_E_NOMEM = -6,       /* device or host allocation failed */
   FDOT_E_BUSY = -7,        /* queue full / workspace cannot grow now */
-  FDOT_E_NOT_FOUND = -8    /* unknown ticket or key */
+  FDOT_E_NOT_FOUND = -8,   /* unknown ticket or key */
+  FDOT_E_NONCANON = -9     /* an input is not canonical in its representation
+                              (reported only where validation was asked for) */
 } fdot_status_t;
 
 /* Element representations (Sec. 2).  Storage type and canonical range:
@@ -212,10 +214,38 @@ fdot_status_t fdot_zech_tables(uint64_t p, uint16_t* value, uint16_t* index,
 
 /* ----------------------------------------------------------------- fields */
 
+/* Options of a field (fdot_field_create); NULL or all zero = defaults.
+ *  validate: nonzero = every compute call on the field (fdot_modp*,
+ *    fdot_modp_many*, fgemv_modp, fgemm_modp, fdot_elementwise) first counts
+ *    the non-canonical elements of its inputs with a check kernel on the
+ *    call's stream and waits for the result, so the call becomes synchronous;
+ *    when any is found it returns FDOT_E_NONCANON and computes nothing.  A
+ *    stream under graph capture cannot wait: FDOT_E_UNSUPPORTED there.
+ *    Canonical ranges are those of fdot_rep_t (Sec. 2.1: a residue is an
+ *    integer in [0, p)).  fdot_modp_many_mixed does not validate.
+ *  algo: the schedule (fdot_algo_t) used where a dot-product call asks for
+ *    FDOT_ALGO_AUTO; 0 = the library's choice.  FDOT_E_UNSUPPORTED at
+ *    creation for a schedule the representation does not have.
+ *  block: the delayed schedules of the dot-product, batched and
+ *    matrix-vector forms fold each accumulator after at most block products
+ *    (rounded down to the kernel's vectors, at least one vector) instead of
+ *    lambda; 0 = lambda.  FDOT_E_BOUND above lambda of the representation's
+ *    delayed schedule (lambda_u64, lambda_redc, lambda_f64, lambda_i32c, or
+ *    (2^32-1)/(p-1) values per sum for discrete logarithms).  Matrix
+ *    products keep their own K-blocks. */
+typedef struct {
+  uint32_t validate;
+  int32_t algo;
+  uint64_t block;
+  uint64_t reserved[2]; /* zero */
+} fdot_options_t;
+
 /* Create a field: validates like fdot_field_params, then uploads its device
- * tables (Zech) to the current device.  The handle is immutable and may be
- * shared by threads and streams; destroy it once no enqueued work uses it. */
-fdot_status_t fdot_field_create(uint64_t p, fdot_rep_t rep, fdot_field_t* out);
+ * tables (Zech) to the current device.  opt may be NULL.  The handle is
+ * immutable and may be shared by threads and streams; destroy it once no
+ * enqueued work uses it. */
+fdot_status_t fdot_field_create(uint64_t p, fdot_rep_t rep, const fdot_options_t* opt,
+                                fdot_field_t* out);
 /* A field handle with its constants only (no device tables, no GPU touched):
  * usable where only the field's description is needed (request planning, the
  * request server in fake-device mode); compute calls on it return
@@ -243,6 +273,13 @@ fdot_status_t fdot_field_destroy(fdot_field_t f);
  * prime or a q out of range. */
 fdot_status_t fdot_field_create_ext(uint64_t p, uint32_t d, fdot_field_t* out);
 fdot_status_t fdot_field_info(fdot_field_t f, fdot_field_info_t* out);
+
+/* Count the non-canonical elements of x[0 .. n-1] (stored values of the
+ * field's representation, device, aligned to the element size) and add the
+ * count to *count (device, 8-byte aligned; the caller clears it).  Enqueued
+ * on the stream; no wait. */
+fdot_status_t fdot_validate(fdot_field_t f, const void* x, size_t n, uint64_t* count,
+                            void* stream);
 
 /* Conversions (Sec. 2; untimed by the paper's convention, Sec. 3).
  * canon: device uint32 residues in [0, p); rep: device storage array. */

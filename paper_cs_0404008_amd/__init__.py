@@ -72,7 +72,13 @@ _sig("fdot_max_prime", [_i32, ctypes.c_uint32, ctypes.POINTER(_u64)])
 _sig("fdot_choose_rep", [_u64, _u64, ctypes.POINTER(_i32)])
 _sig("fdot_host_fold", [ctypes.POINTER(FieldInfo), _i32, _u64, ctypes.POINTER(_u64)])
 _sig("fdot_zech_tables", [_u64, _vp, _vp, _vp])
-_sig("fdot_field_create", [_u64, _i32, ctypes.POINTER(_vp)])
+class Options(ctypes.Structure):
+    _fields_ = [("validate", ctypes.c_uint32), ("algo", ctypes.c_int32), ("block", ctypes.c_uint64),
+                ("reserved", ctypes.c_uint64 * 2)]
+
+
+_sig("fdot_field_create", [_u64, _i32, ctypes.POINTER(Options), ctypes.POINTER(_vp)])
+_sig("fdot_validate", [_vp, _vp, _sz, _vp, _vp])
 _sig("fdot_field_create_ext", [_u64, ctypes.c_uint32, ctypes.POINTER(_vp)])
 _sig("fdot_field_create_host", [_u64, _i32, ctypes.POINTER(_vp)])
 _sig("fdot_field_destroy", [_vp])
@@ -266,10 +272,19 @@ class Field:
     """GF(p) in one representation, or GF(p^degree) in discrete logarithms
     (rep "zech", degree >= 2); the handle owns the device tables."""
 
-    def __init__(self, p: int, rep: str = "zpz", host_only: bool = False, degree: int = 1):
+    def __init__(self, p: int, rep: str = "zpz", host_only: bool = False, degree: int = 1,
+                 validate: bool = False, algo: str = "auto", block: int = 0):
+        """validate / algo / block: the creation options of fdot_field_create
+        (check inputs before every compute call, the schedule used for
+        "auto", the delay block of the delayed schedules; 0 = lambda)."""
         self.p = int(p)
         self.rep = rep
         h = _vp()
+        opts = None
+        if validate or algo != "auto" or block:
+            if degree > 1 or host_only:
+                raise ValueError("options apply to device prime fields")
+            opts = ctypes.byref(Options(1 if validate else 0, ALGOS[algo], int(block)))
         if degree > 1:
             if rep != "zech" or host_only:
                 raise ValueError("extension fields are held in discrete logarithms on the device")
@@ -279,7 +294,8 @@ class Field:
             _check(_lib.fdot_field_create_host(self.p, REPS[rep], ctypes.byref(h)),
                    "fdot_field_create_host")
         else:
-            _check(_lib.fdot_field_create(self.p, REPS[rep], ctypes.byref(h)), "fdot_field_create")
+            _check(_lib.fdot_field_create(self.p, REPS[rep], opts, ctypes.byref(h)),
+                   "fdot_field_create")
         self._h = h
         info = FieldInfo()
         _check(_lib.fdot_field_info(h, ctypes.byref(info)), "fdot_field_info")
@@ -299,6 +315,18 @@ class Field:
     def _need(self, t: torch.Tensor, name: str):
         if t.dtype != self.dtype or not t.is_cuda:
             raise TypeError(f"{name} must be a CUDA tensor of dtype {self.dtype}")
+
+    def validate(self, x: torch.Tensor, count: torch.Tensor | None = None, stream=None):
+        """fdot_validate: add the number of non-canonical stored values of x to
+        count (a one-element int64 device tensor, created zeroed if None)."""
+        self._need(x, "x")
+        if not x.is_contiguous():
+            raise ValueError("x must be contiguous")
+        if count is None:
+            count = torch.zeros(1, dtype=torch.int64, device=x.device)
+        _check(_lib.fdot_validate(self._h, _ptr(x), x.numel(), _ptr(count), _stream(stream)),
+               "fdot_validate")
+        return count
 
     def encode(self, canon: torch.Tensor, out: torch.Tensor | None = None, stream=None):
         if canon.dtype != torch.uint32 or not canon.is_cuda or not canon.is_contiguous():

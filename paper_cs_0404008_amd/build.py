@@ -25,7 +25,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
 
 SOURCES = ["host_field.cpp", "runtime.cpp", "dot_kernels.hip", "gemm_kernels.hip",
            "gemm_mfma.hip", "elementwise.hip", "ext_field.hip", "many_mixed.hip", "server.cpp",
-           "calibrate.hip", "noalloc.hip"]
+           "calibrate.hip", "noalloc.hip", "validate.hip"]
 
 
 def _compile(src: str) -> str:

@@ -1181,7 +1181,7 @@ static uint32_t clamp_vecs(uint64_t v) {
 }
 
 // Choose the lane policy and its fold period from the field's block lengths.
-static fdot_status_t make_plan(const fdot_field_s* f, fdot_algo_t algo, Plan* pl) {
+static fdot_status_t make_plan_lambda(const fdot_field_s* f, fdot_algo_t algo, Plan* pl) {
   const fdot_field_info_t& I = f->info;
   if (algo == FDOT_ALGO_AUTO) algo = fd_default_algo(f, 0);
   pl->fold_vecs = 0xFFFFFFFFu;
@@ -1244,6 +1244,27 @@ static fdot_status_t make_plan(const fdot_field_s* f, fdot_algo_t algo, Plan* pl
       return FDOT_OK;
   }
   return FDOT_E_UNSUPPORTED;
+}
+
+// The plan, with the field's block option applied: a delayed schedule folds
+// after at most block products per accumulator (products per vector and
+// accumulator: two for 32-bit residues, one for doubles, four discrete-log
+// values per sum, sixteen centred int8 products), whole vectors, at least
+// one.  A shorter block only folds more often, so exactness is kept.
+static fdot_status_t make_plan(const fdot_field_s* f, fdot_algo_t algo, Plan* pl) {
+  const fdot_status_t st = make_plan_lambda(f, algo, pl);
+  if (st != FDOT_OK || f->opt.block == 0 || pl->fold_vecs == 0xFFFFFFFFu) return st;
+  uint64_t per = 2;
+  switch (pl->kind) {
+    case Kind::F64: per = 1; break;
+    case Kind::ZechExp: per = 4; break;
+    case Kind::Centred: per = 16; break;
+    default: break;
+  }
+  uint64_t v = f->opt.block / per;
+  if (v < 1) v = 1;
+  if (v < pl->fold_vecs) pl->fold_vecs = (uint32_t)v;
+  return FDOT_OK;
 }
 
 // Workgroups of `fn` that can be resident on one CU with `lds` bytes of
@@ -1443,6 +1464,7 @@ static Shape shape_for(const fdot_field_s* f, uint64_t n_single) {
 
 fdot_algo_t fd_default_algo(const fdot_field_s* f, uint64_t) {
   const fdot_field_info_t& I = f->info;
+  if (f->opt.algo != FDOT_ALGO_AUTO) return (fdot_algo_t)f->opt.algo;  // creation option
   switch (I.rep) {
     case FDOT_REP_ZPZ_U32:
       if (I.lambda_u64 >= 2) return FDOT_ALGO_DELAYED;

@@ -11,6 +11,7 @@
 
 struct fdot_field_s {
   fdot_field_info_t info;
+  fdot_options_t opt;   // creation options (all zero: defaults)
   FieldK k;             // device-ready constants (table pointers on device)
   int device;
   bool host_only;       // constants only: no device tables, no compute
@@ -37,9 +38,29 @@ struct Workspace {
   uint64_t* first = nullptr;          // cap: position of each pair in the padded sequence
   uint32_t* units = nullptr;          // cap: units of each pair
   uint32_t* start = nullptr;          // kMaxRanges: first pair of each range
-  uint64_t* tq = nullptr;             // 8: the batch's ranges and their claim counter
+  uint64_t* tq = nullptr;             // 8 words: the batch's range totals (0..2); word
+                                      // kTqCheckWord counts non-canonical inputs
   bool captured = false;  // handed to a graph capture: never freed on growth
 };
+
+// Word of Workspace::tq that input validation counts into.
+constexpr int kTqCheckWord = 4;
+
+// One operand of a call to validate: rows x cols elements, row stride ld.
+struct FdCheck {
+  const void* x;
+  uint64_t rows, cols, ld;
+};
+
+// Validation (validate.hip).  fd_validate_call counts the non-canonical
+// elements of the listed operands (and of every pair of desc, if given)
+// into `word` (NULL: the stream's workspace word), waits for the stream and
+// returns FDOT_E_NONCANON if there are any.
+fdot_status_t fd_validate_call(const fdot_field_s* f, hipStream_t s, const FdCheck* parts,
+                               int nparts, const fdot_desc_t* desc, uint64_t count_pairs,
+                               unsigned long long* word);
+// Host check of a scalar operand (elementwise alpha) in the representation.
+bool fd_canonical_host(const fdot_field_s* f, const void* value);
 
 // Host-side helpers (host_field.cpp).
 int fd_is_prime_u64(uint64_t n);

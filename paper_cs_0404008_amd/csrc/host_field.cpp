@@ -211,6 +211,53 @@ int fd_zech_build(uint64_t p, uint32_t g, uint16_t* value, uint16_t* index, uint
   return 0;
 }
 
+// Largest block length of the representation's delayed schedule (the bound a
+// block option may not exceed).
+static uint64_t delayed_lambda(const fdot_field_info_t& I) {
+  switch (I.rep) {
+    case FDOT_REP_ZPZ_U32: return I.lambda_u64;
+    case FDOT_REP_MONT_U32: return I.lambda_redc;
+    case FDOT_REP_FP64: return I.lambda_f64;
+    case FDOT_REP_ZECH_U16: return 0xFFFFFFFFull / (I.p - 1);
+    case FDOT_REP_CENTRED_I8: return I.lambda_i32c;
+  }
+  return 0;
+}
+
+// Schedules each representation has (fdot_algo_t).
+static bool algo_allowed(int rep, int algo) {
+  if (algo == FDOT_ALGO_AUTO) return true;
+  switch (rep) {
+    case FDOT_REP_ZPZ_U32:
+    case FDOT_REP_MONT_U32:
+      return algo == FDOT_ALGO_DELAYED || algo == FDOT_ALGO_PERTERM ||
+             algo == FDOT_ALGO_OVERFLOW || algo == FDOT_ALGO_HYBRID;
+    case FDOT_REP_FP64: return algo == FDOT_ALGO_DELAYED || algo == FDOT_ALGO_PERTERM;
+    case FDOT_REP_ZECH_U16: return algo == FDOT_ALGO_ZECH_EXP || algo == FDOT_ALGO_ZECH_TPLUS1;
+    case FDOT_REP_CENTRED_I8: return algo == FDOT_ALGO_DELAYED;
+  }
+  return false;
+}
+
+bool fd_canonical_host(const fdot_field_s* f, const void* value) {
+  const uint64_t q = f->degree > 1 ? f->info.q : f->info.p;
+  switch (f->info.rep) {
+    case FDOT_REP_ZPZ_U32:
+    case FDOT_REP_MONT_U32: return *(const uint32_t*)value < f->info.p;
+    case FDOT_REP_FP64: {
+      const double v = *(const double*)value;
+      return v >= 0.0 && v < (double)f->info.p && v == floor(v);
+    }
+    case FDOT_REP_ZECH_U16: return *(const uint16_t*)value < q;
+    case FDOT_REP_CENTRED_I8: {
+      const int v = *(const int8_t*)value;
+      const int h = (int)((f->info.p - 1) / 2);
+      return v >= -h && v <= h;
+    }
+  }
+  return false;
+}
+
 extern "C" {
 
 fdot_status_t fdot_field_params(uint64_t p, fdot_rep_t rep, fdot_field_info_t* out) {
@@ -309,16 +356,27 @@ fdot_status_t fdot_zech_tables(uint64_t p, uint16_t* value, uint16_t* index, uin
   return fd_zech_build(p, fd_primitive_root(p), value, index, plus1) == 0 ? FDOT_OK : FDOT_E_NOMEM;
 }
 
-fdot_status_t fdot_field_create(uint64_t p, fdot_rep_t rep, fdot_field_t* out) {
+fdot_status_t fdot_field_create(uint64_t p, fdot_rep_t rep, const fdot_options_t* opt,
+                                fdot_field_t* out) {
   if (!out) return FDOT_E_INVALID_ARG;
   *out = nullptr;
   fdot_field_info_t I;
   fdot_status_t st = fd_fill_params(p, rep, &I);
   if (st != FDOT_OK) return st;
+  fdot_options_t o;
+  memset(&o, 0, sizeof o);
+  if (opt) {
+    o = *opt;
+    if (o.reserved[0] || o.reserved[1]) return FDOT_E_INVALID_ARG;
+    if (o.algo < FDOT_ALGO_AUTO || o.algo > FDOT_ALGO_HYBRID) return FDOT_E_INVALID_ARG;
+    if (!algo_allowed(I.rep, o.algo)) return FDOT_E_UNSUPPORTED;
+    if (o.block > delayed_lambda(I)) return FDOT_E_BOUND;
+  }
   fdot_field_s* f = new (std::nothrow) fdot_field_s;
   if (!f) return FDOT_E_NOMEM;
   memset(f, 0, sizeof(*f));
   f->info = I;
+  f->opt = o;
   f->degree = 1;
   fd_fieldk_from_info(&I, &f->k);
   if (hipGetDevice(&f->device) != hipSuccess) { delete f; return FDOT_E_DEVICE; }

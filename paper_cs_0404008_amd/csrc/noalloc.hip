@@ -86,6 +86,12 @@ extern "C" fdot_status_t fdot_modp_many_noalloc(fdot_field_t f, fdot_algo_t algo
   w.units = (uint32_t*)(base + kAccBytes + kFirstBytes);
   w.start = (uint32_t*)(base + kAccBytes + kFirstBytes + kUnitsBytes);
   w.tq = (uint64_t*)(base + kAccBytes + kFirstBytes + kUnitsBytes + kStartBytes);
+  if (f->opt.validate) {
+    // the check word of the fixed array: no workspace is taken
+    st = fd_validate_call(f, (hipStream_t)stream, nullptr, 0, desc, count,
+                          (unsigned long long*)(w.tq + kTqCheckWord));
+    if (st != FDOT_OK) return st;
+  }
   // The combination words must start at zero.  The kernels return each word
   // to zero when its pair completes, but the array is shared by every call on
   // this GPU: clear this batch's words with a kernel (not a memset node, so

@@ -202,6 +202,7 @@ const char* fdot_status_string(int status) {
     case FDOT_E_NOMEM: return "out of memory";
     case FDOT_E_BUSY: return "busy";
     case FDOT_E_NOT_FOUND: return "not found";
+    case FDOT_E_NONCANON: return "input not canonical in its representation";
   }
   return "unknown status";
 }
@@ -300,6 +301,16 @@ fdot_status_t fdot_elementwise(fdot_field_t f, fdot_ew_op_t op, size_t n, const 
   if (!x || !r || !aligned_to(x, es) || !aligned_to(r, es)) return FDOT_E_INVALID_ARG;
   if (needs_y && (!y || !aligned_to(y, es))) return FDOT_E_INVALID_ARG;
   if (needs_a && !alpha) return FDOT_E_INVALID_ARG;
+  if (f->opt.validate) {
+    if (needs_a && !fd_canonical_host(f, alpha)) return FDOT_E_NONCANON;
+    FdCheck c[3];
+    int k = 0;
+    c[k++] = {x, 1, n, n};
+    if (needs_y) c[k++] = {y, 1, n, n};
+    if (op == FDOT_EW_AXPYIN) c[k++] = {r, 1, n, n};
+    const fdot_status_t st = fd_validate_call(f, (hipStream_t)stream, c, k, nullptr, 0, nullptr);
+    if (st != FDOT_OK) return st;
+  }
   return fd_launch_elementwise(f, op, n, needs_a ? alpha : nullptr, x, needs_y ? y : nullptr, r,
                                (hipStream_t)stream);
 }
@@ -312,6 +323,11 @@ fdot_status_t fdot_modp_algo(fdot_field_t f, fdot_algo_t algo, const void* x, co
   const size_t es = f->info.elem_bytes;
   if (!aligned_to(result, es)) return FDOT_E_INVALID_ARG;
   if (n && (!x || !y || !aligned_to(x, es) || !aligned_to(y, es))) return FDOT_E_INVALID_ARG;
+  if (f->opt.validate && n) {
+    const FdCheck c[2] = {{x, 1, n, n}, {y, 1, n, n}};
+    const fdot_status_t st = fd_validate_call(f, (hipStream_t)stream, c, 2, nullptr, 0, nullptr);
+    if (st != FDOT_OK) return st;
+  }
   if (f->degree > 1) {
     bool xv = false;
     const fdot_status_t st = ext_schedule(f, algo, &xv);
@@ -344,6 +360,11 @@ fdot_status_t fdot_modp_many_algo(fdot_field_t f, fdot_algo_t algo, size_t count
   if (!desc || !results || !aligned_to(desc, 8) || !aligned_to(results, f->info.elem_bytes))
     return FDOT_E_INVALID_ARG;
   if (count > (1ull << 31)) return FDOT_E_INVALID_ARG;
+  if (f->opt.validate) {
+    const fdot_status_t st =
+        fd_validate_call(f, (hipStream_t)stream, nullptr, 0, desc, count, nullptr);
+    if (st != FDOT_OK) return st;
+  }
   if (f->degree > 1)
     return fd_launch_ext_many(f, xv, count, desc, (uint16_t*)results, (hipStream_t)stream);
   Workspace* w = nullptr;
@@ -383,6 +404,11 @@ fdot_status_t fgemv_modp(fdot_field_t f, size_t m, size_t n, const void* A, size
   if (!A || !y || (n && !x) || lda < n) return FDOT_E_INVALID_ARG;
   if (!aligned_to(A, es) || !aligned_to(y, es) || (x && !aligned_to(x, es)))
     return FDOT_E_INVALID_ARG;
+  if (f->opt.validate && n) {
+    const FdCheck c[2] = {{A, m, n, lda}, {x, 1, n, n}};
+    const fdot_status_t st = fd_validate_call(f, (hipStream_t)stream, c, 2, nullptr, 0, nullptr);
+    if (st != FDOT_OK) return st;
+  }
   return fd_launch_gemv(f, m, n, A, lda, x, y, (hipStream_t)stream);
 }
 
@@ -396,6 +422,11 @@ fdot_status_t fgemm_modp(fdot_field_t f, size_t M, size_t N, size_t K, const voi
   if (!C || ldc < N || (K && (!A || !B || lda < K || ldb < N))) return FDOT_E_INVALID_ARG;
   if (!aligned_to(C, es) || (A && !aligned_to(A, es)) || (B && !aligned_to(B, es)))
     return FDOT_E_INVALID_ARG;
+  if (f->opt.validate && K) {
+    const FdCheck c[2] = {{A, M, K, lda}, {B, K, N, ldb}};
+    const fdot_status_t st = fd_validate_call(f, (hipStream_t)stream, c, 2, nullptr, 0, nullptr);
+    if (st != FDOT_OK) return st;
+  }
   return fd_launch_gemm(f, M, N, K, A, lda, B, ldb, C, ldc, (hipStream_t)stream);
 }
 

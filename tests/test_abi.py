@@ -43,7 +43,18 @@ def test_bad_arguments_fail_synchronously():
     assert L.fgemv_modp(null, 1, 1, null, 1, null, null, null) == -1
     assert L.fdot_field_destroy(null) == -1
     out = ctypes.c_void_p()
-    assert L.fdot_field_create(32751, 0, ctypes.byref(out)) == -2
-    assert L.fdot_field_create(32749, 9, ctypes.byref(out)) == -1
-    assert L.fdot_field_create(65537, 3, ctypes.byref(out)) == -3
+    assert L.fdot_field_create(32751, 0, None, ctypes.byref(out)) == -2
+    assert L.fdot_field_create(32749, 9, None, ctypes.byref(out)) == -1
+    assert L.fdot_field_create(65537, 3, None, ctypes.byref(out)) == -3
+    # options checked before any device work: a block above lambda, a
+    # schedule the representation lacks, nonzero reserved words
+    O = fd.Options
+    assert L.fdot_field_create(67108859, 2, ctypes.byref(O(0, 0, 3)), ctypes.byref(out)) == -3
+    assert L.fdot_field_create(67108859, 2, ctypes.byref(O(0, 3, 0)), ctypes.byref(out)) == -4
+    assert L.fdot_field_create(251, 4, ctypes.byref(O(0, 4, 0)), ctypes.byref(out)) == -4
+    assert L.fdot_field_create(32749, 0, ctypes.byref(O(0, 9, 0)), ctypes.byref(out)) == -1
+    bad = O(0, 0, 0)
+    bad.reserved[1] = 1
+    assert L.fdot_field_create(32749, 0, ctypes.byref(bad), ctypes.byref(out)) == -1
+    assert L.fdot_validate(null, null, 0, null, null) == -1
     assert L.fdot_tune_set(None, 1) == -1
