@@ -65,7 +65,10 @@ typedef enum {
   FDOT_REP_MONT_U32 = 1,
   FDOT_REP_FP64 = 2,
   FDOT_REP_ZECH_U16 = 3,
-  FDOT_REP_CENTRED_I8 = 4
+  FDOT_REP_CENTRED_I8 = 4,
+  FDOT_REP_FORCE_INT32 = 0x7fffffff /* not a representation: every int32 value is a
+                                       valid fdot_rep_t, so an unknown one can be
+                                       checked and refused */
 } fdot_rep_t;
 
 /* Accumulation schedules of Sec. 3 (every one returns the same result). */
@@ -83,12 +86,13 @@ typedef enum {
                                 Zech addition through the plus-one table */
   FDOT_ALGO_ZECH_EXP = 5,    /* Sec. 2.4 + 3.1: products by index addition,
                                 then the value table and a delayed integer sum */
-  FDOT_ALGO_HYBRID = 6       /* Sec. 3.4: blocks of lambda products with
+  FDOT_ALGO_HYBRID = 6,      /* Sec. 3.4: blocks of lambda products with
                                 lambda p (p-1) < 2^64 (Eq. 2, strict reading)
                                 added without a test, one wrap test and CORR
                                 per block; ZPZ_U32 and MONT_U32 (one extra
                                 reduction at the end); where lambda < 2 the
                                 same as OVERFLOW */
+  FDOT_ALGO_FORCE_INT32 = 0x7fffffff /* not a schedule (32-bit range, as above) */
 } fdot_algo_t;
 
 /* Accumulator kinds for the bound calculator. */
@@ -100,7 +104,8 @@ typedef enum {
   FDOT_ACC_F64_CENTRED = 4, /* double, centred operands: |sum| <= 2^53        */
   FDOT_ACC_MONT_REDC = 5,   /* products summed before one Montgomery reduction
                                with B = 2^32: sum < p*B          (Sec. 2.2)   */
-  FDOT_ACC_U64_HYBRID = 6   /* Eq. 2 strict: lambda*p*(p-1) < 2^64 (Sec. 3.4) */
+  FDOT_ACC_U64_HYBRID = 6,  /* Eq. 2 strict: lambda*p*(p-1) < 2^64 (Sec. 3.4) */
+  FDOT_ACC_FORCE_INT32 = 0x7fffffff
 } fdot_acc_t;
 
 /* Prime bounds printed by the paper, for the bound calculator. */
@@ -108,7 +113,8 @@ typedef enum {
   FDOT_BOUND_AXPY_SIGNED = 0,   /* p(p-1) <= 2^(m-1)-1            (Sec. 2.1) */
   FDOT_BOUND_AXPY_UNSIGNED = 1, /* p(p-1) <= 2^m-1                (Sec. 2.1) */
   FDOT_BOUND_MONTGOMERY = 2,    /* (p-1)^2 + p(B-1) < B^2, B=2^m  (Sec. 2.2) */
-  FDOT_BOUND_ZECH_INDEX = 3     /* 2(p-1) <= 2^(m-1)-1            (Sec. 2.4) */
+  FDOT_BOUND_ZECH_INDEX = 3,    /* 2(p-1) <= 2^(m-1)-1            (Sec. 2.4) */
+  FDOT_BOUND_FORCE_INT32 = 0x7fffffff
 } fdot_bound_t;
 
 /* Fold primitives (the reductions of Sec. 2), for host-side checks. */
@@ -116,8 +122,9 @@ typedef enum {
   FDOT_FOLD_REMAINDER = 0, /* T mod p by a precomputed reciprocal (2-by-1
                               division by an invariant divisor), any T < 2^64 */
   FDOT_FOLD_REDC = 1,      /* Montgomery: T * 2^-32 mod p, T < p*2^32 (Sec. 2.2) */
-  FDOT_FOLD_FP64 = 2       /* T - floor(T*invP)*P with one +-P correction,
+  FDOT_FOLD_FP64 = 2,      /* T - floor(T*invP)*P with one +-P correction,
                               T <= 2^53 (Sec. 2.3) */
+  FDOT_FOLD_FORCE_INT32 = 0x7fffffff
 } fdot_fold_t;
 
 /* Constants of a field (all host values). */
@@ -298,7 +305,8 @@ typedef enum {
   FDOT_EW_MUL = 3,    /* r = x * y */
   FDOT_EW_DIV = 4,    /* r = x / y; a zero divisor gives the zero element */
   FDOT_EW_AXPY = 5,   /* r = a * x + y */
-  FDOT_EW_AXPYIN = 6  /* r = a * x + r */
+  FDOT_EW_AXPYIN = 6, /* r = a * x + r */
+  FDOT_EW_FORCE_INT32 = 0x7fffffff
 } fdot_ew_op_t;
 
 /* r[i] = op(x[i], y[i]) for i < n over GF(p) in the field's representation
@@ -458,7 +466,8 @@ fdot_status_t fdot_tune_get(const char* key, int64_t* value);
  * submitted, or the request names a HIP event (ready) that its launch
  * waits for. */
 
-typedef enum { FDOT_OP_DOT = 0, FDOT_OP_GEMV = 1, FDOT_OP_GEMM = 2 } fdot_op_t;
+typedef enum { FDOT_OP_DOT = 0, FDOT_OP_GEMV = 1, FDOT_OP_GEMM = 2,
+               FDOT_OP_FORCE_INT32 = 0x7fffffff } fdot_op_t;
 
 typedef struct {
   int32_t op;          /* fdot_op_t */

@@ -16,7 +16,8 @@ import numpy as np
 from . import bounds  # noqa: F401  (re-exported)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB names another build of oracle.c (the sanitizer run's)
+LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "oracle.c")
 
 REPS = {"zpz": 0, "mont": 1, "fp64": 2, "zech": 3, "centred": 4}
@@ -29,6 +30,8 @@ _lib = None
 
 def build(force: bool = False) -> str:
     """Compile oracle.c into liboracle.so with the host C compiler."""
+    if os.environ.get("ORACLE_LIB"):
+        return LIB_PATH  # built elsewhere
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC",

@@ -14,7 +14,9 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfdot.so")
+# FDOT_LIB names another build of the same library (the host-instrumented
+# copy the sanitizer run uses)
+LIB_PATH = os.environ.get("FDOT_LIB") or os.path.join(_HERE, "libfdot.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(

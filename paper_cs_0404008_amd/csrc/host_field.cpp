@@ -158,6 +158,7 @@ fdot_status_t fd_fill_params(uint64_t p, fdot_rep_t rep, fdot_field_info_t* out)
       I.elem_bytes = 1;
       if (p < 3 || p > 255) return FDOT_E_BOUND;  // odd p, |a| <= 127
       break;
+    default: return FDOT_E_INVALID_ARG;
   }
   I.degree = 1;
   I.q = p;
@@ -285,6 +286,7 @@ fdot_status_t fdot_max_prime(fdot_bound_t kind, uint32_t bits, uint64_t* out) {
         return (x - 1) * (x - 1) + x * (B - 1) < B * B;
       }
       case FDOT_BOUND_ZECH_INDEX: return 2 * (x - 1) <= ((((u128)1) << (bits - 1)) - 1);
+      default: break;
     }
     return false;
   };
@@ -346,6 +348,7 @@ fdot_status_t fdot_host_fold(const fdot_field_info_t* info, fdot_fold_t kind, ui
       if (T > (1ull << 53)) return FDOT_E_INVALID_ARG;
       *out = (uint64_t)fold_f64((double)T, k);
       return FDOT_OK;
+    default: break;
   }
   return FDOT_E_INVALID_ARG;
 }
