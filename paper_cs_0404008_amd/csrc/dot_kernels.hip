@@ -363,6 +363,7 @@ struct PZechExp {
   static constexpr int VW = 8;
   static constexpr int U = 2;
   static constexpr bool kTable = true;
+  static constexpr bool kPrefetch = true;
   static constexpr bool kFolds = true;
   uint32_t s0, s1;
   uint64_t tot;
@@ -404,6 +405,7 @@ struct PZechTplus1 {
   static constexpr int VW = 8;
   static constexpr int U = 2;
   static constexpr bool kTable = true;
+  static constexpr bool kPrefetch = true;
   uint32_t z[8];
   const uint16_t* tab;  // plus-one table in LDS
   __device__ void init(const FieldK&) {
@@ -441,6 +443,121 @@ struct PZechTplus1 {
   }
 };
 
+// The same Zech addition for p <= 32768, two accumulators per register.
+// Codes then fit 15 bits, so the index arithmetic of two codes runs in one
+// packed 16-bit instruction (a sum of two codes stays below 2^16), and the
+// tests for the zero element become bit masks instead of per-code selects:
+//  * product: s = a + b; (s - 1) mod q' = min(s - 1, s - 1 - q') in 16-bit
+//    wrap-around arithmetic (q' = p - 1), code ((s - 1) mod q') + 1, and a
+//    mask that is all ones in each half where neither factor is zero;
+//  * sum g^u + g^t = g^(u + h) with g^h = 1 + g^k, k = t - u: first
+//    k - 1 = (t - 1 - u) mod q' by the same minimum, then the shifted
+//    plus-one table in LDS, tab[k - 1] = h - 1, or 0x8000 where 1 + g^k = 0;
+//    the code of the sum is ((u + h - 1) mod q') + 1 (one more minimum),
+//    zeroed where the table holds the 0x8000 mark; a zero accumulator takes
+//    the product, a zero product leaves the accumulator as it is.
+// Every table index lies in [0, q' - 1] for any codes in [0, q'].
+//
+// The packed 16-bit ALU instructions are written out one per statement (so
+// that the compiler can still interleave the four accumulators' chains): it
+// otherwise turns the mask arithmetic back into per-half compares and
+// selects.  They are pure register operations, no memory access.
+#define FD_PK(op, d, a, b) asm(op " %0, %1, %2" : "=v"(d) : "v"(a), "v"(b))
+// the same with a wave-uniform operand in a scalar register (second, or first)
+#define FD_PKS(op, d, a, b) asm(op " %0, %1, %2" : "=v"(d) : "v"(a), "s"(b))
+#define FD_PKS1(op, d, a, b) asm(op " %0, %1, %2" : "=v"(d) : "s"(a), "v"(b))
+// 0 - a in both halves: all ones where a half is 1, zero where it is 0
+#define FD_PKNEG(d, a) asm("v_pk_sub_u16 %0, 0, %1" : "=v"(d) : "v"(a))
+
+struct PZechTplus1P {
+  using E = uint16_t;
+  static constexpr int VW = 8;
+  static constexpr int U = 2;
+  static constexpr bool kTable = true;
+  static constexpr bool kPrefetch = true;
+  static constexpr bool kShiftedPlus1 = true;
+  uint32_t z[4];   // accumulators 2j (low half) and 2j+1 (high half)
+  uint32_t zt;     // accumulator of the scalar head and tail
+  const uint16_t* tab;
+  uint32_t k1, q1, qq, f15;  // packed constants: 1, q' + 1, q', 15 in both halves
+  __device__ void init(const FieldK& F) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) z[j] = 0;
+    zt = 0;
+    k1 = 0x00010001u;
+    qq = F.qbar | (F.qbar << 16);
+    q1 = (F.qbar + 1) | ((F.qbar + 1) << 16);
+    f15 = 0x000F000Fu;
+  }
+  __device__ __forceinline__ uint32_t step(uint32_t zw, uint32_t aw, uint32_t bw) const {
+    uint32_t S, Sa, Sb, R, mn, m1, mp, Pc, D, Dq, K, K2, S1, S1q, Wm, W, hs, keep, mz, mu;
+    FD_PK("v_pk_add_u16", S, aw, bw);
+    FD_PKS("v_pk_sub_u16", Sa, S, k1);
+    FD_PKS("v_pk_sub_u16", Sb, S, q1);
+    FD_PK("v_pk_min_u16", R, Sa, Sb);        // (s - 1) mod q'
+    FD_PK("v_pk_min_u16", mn, aw, bw);
+    FD_PKS("v_pk_min_u16", m1, mn, k1);
+    FD_PKNEG(mp, m1);                        // ones where the product is nonzero
+    const uint32_t Pm = R & mp;              // product code - 1 (0 if zero)
+    FD_PKS("v_pk_add_u16", Pc, Pm, k1);      // product code
+    FD_PK("v_pk_sub_u16", D, Pm, zw);
+    FD_PKS("v_pk_add_u16", Dq, D, qq);
+    FD_PK("v_pk_min_u16", K, D, Dq);         // k - 1 in [0, q' - 1]
+    FD_PK("v_pk_add_u16", K2, K, K);         // byte offsets of the two table entries
+    const char* tb = (const char*)tab;
+    const uint32_t hw = (uint32_t)*(const uint16_t*)(tb + (K2 & 0xFFFFu)) |
+                        ((uint32_t)*(const uint16_t*)(tb + (K2 >> 16)) << 16);
+    FD_PK("v_pk_add_u16", S1, zw, hw);       // u + h - 1
+    FD_PKS("v_pk_sub_u16", S1q, S1, qq);
+    FD_PK("v_pk_min_u16", Wm, S1, S1q);
+    FD_PKS("v_pk_add_u16", W, Wm, k1);       // code of the sum
+    FD_PKS1("v_pk_lshrrev_b16", hs, f15, hw);
+    FD_PKS("v_pk_sub_u16", keep, hs, k1);    // zero where the sum is 0
+    FD_PKS("v_pk_min_u16", mz, zw, k1);
+    FD_PKNEG(mu, mz);                        // ones where u != 0
+    const uint32_t r1 = W & keep;
+    const uint32_t r2 = (r1 & mu) | (Pc & ~mu);
+    return (r2 & mp) | (zw & ~mp);
+  }
+  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK&) {
+    z[0] = step(z[0], a.x, b.x);
+    z[1] = step(z[1], a.y, b.y);
+    z[2] = step(z[2], a.z, b.z);
+    z[3] = step(z[3], a.w, b.w);
+  }
+  __device__ void one(E a, E b, const FieldK&, const Job&) {
+    zt = step(zt, a, b) & 0xFFFFu;  // low half only: the high half adds zero
+  }
+  __device__ uint32_t finish(const FieldK& F) {
+    uint32_t s = F.zval[zt];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s += F.zval[z[j] & 0xFFFFu] + F.zval[z[j] >> 16];
+    return mod_u64(s, F);
+  }
+  __device__ static void store(void* out, uint64_t k, uint32_t r, const FieldK& F) {
+    ((uint16_t*)out)[k] = F.zidx[r];
+  }
+};
+
+// LDS entry i of a table policy: the value table, the plus-one table, or for
+// the packed policy the plus-one table shifted by one index with its zero
+// mark (entries past q' - 1 are never read).
+template <class Pol, class = void>
+struct ShiftedPlus1 { static constexpr bool value = false; };
+template <class P>
+struct ShiftedPlus1<P, decltype((void)P::kShiftedPlus1)> { static constexpr bool value = P::kShiftedPlus1; };
+
+template <class Pol>
+__device__ __forceinline__ uint16_t table_entry(const FieldK& F, uint32_t i) {
+  if constexpr (std::is_same<Pol, PZechExp>::value) return F.zval[i];
+  if constexpr (ShiftedPlus1<Pol>::value) {
+    if (i + 1 >= F.p32) return 0;
+    const uint16_t h = F.zplus1[i + 1];
+    return h == 0 ? (uint16_t)0x8000u : (uint16_t)(h - 1);
+  }
+  return F.zplus1[i];
+}
+
 // Centred residues in int8 (Sec. 3.2.2): four-way int8 dot products into a
 // 32-bit accumulator, flushed to 64 bits every lambda_i32c products.
 struct PCentred {
@@ -473,6 +590,11 @@ template <class P, class = void>
 struct HasTable { static constexpr bool value = false; };
 template <class P>
 struct HasTable<P, decltype((void)P::kTable)> { static constexpr bool value = P::kTable; };
+
+template <class P, class = void>
+struct Prefetch { static constexpr bool value = false; };
+template <class P>
+struct Prefetch<P, decltype((void)P::kPrefetch)> { static constexpr bool value = P::kPrefetch; };
 
 template <class P, class = void>
 struct Folds { static constexpr bool value = false; };
@@ -525,7 +647,46 @@ __device__ __forceinline__ void wave_range(Pol& L, const typename Pol::E* x,
   const uint64_t step = (uint64_t)S * W;  // vectors from one block of this slice to the next
   uint64_t i = (uint64_t)slice * W + lane;
   uint32_t pending = 0;                   // vectors taken since the last fold
-  if (!kF || fv >= (uint32_t)U) {
+  if constexpr (Prefetch<Pol>::value) {
+    // the next step's loads are issued before this step is consumed, so
+    // that a policy with a long per-vector computation keeps its loads in
+    // flight while it computes
+    if (i + (uint64_t)(U - 1) * step < nv) {
+      u32x4 a[U], b[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        a[u] = load_nt(xv + i + (uint64_t)u * step);
+        b[u] = load_nt(yv + i + (uint64_t)u * step);
+      }
+      for (;;) {
+        const uint64_t in = i + (uint64_t)U * step;
+        const bool more = in + (uint64_t)(U - 1) * step < nv;
+        u32x4 an[U], bn[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          an[u] = load_nt(more ? xv + in + (uint64_t)u * step : g_zero16);
+          bn[u] = load_nt(more ? yv + in + (uint64_t)u * step : g_zero16);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) L.vec(a[u], b[u], F);
+        if constexpr (kF) {
+          pending += U;
+          if (pending > fv - U) {
+            L.fold(F);
+            pending = 0;
+          }
+        }
+        i = in;
+        if (!more) break;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          a[u] = an[u];
+          b[u] = bn[u];
+        }
+      }
+    }
+  } else if (!kF || fv >= (uint32_t)U) {
     for (; i + (uint64_t)(U - 1) * step < nv; i += (uint64_t)U * step) {
       u32x4 a[U], b[U];
 #pragma unroll
@@ -603,8 +764,7 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
 // workgroup.
 template <class Pol, int NTH>
 __device__ __forceinline__ void load_table(const FieldK& F, uint16_t* s_tab) {
-  const uint16_t* src = std::is_same<Pol, PZechExp>::value ? F.zval : F.zplus1;
-  for (uint32_t i = threadIdx.x; i < F.p32; i += NTH) s_tab[i] = src[i];
+  for (uint32_t i = threadIdx.x; i < F.p32; i += NTH) s_tab[i] = table_entry<Pol>(F, i);
   __syncthreads();
 }
 
@@ -1031,8 +1191,7 @@ __global__ __launch_bounds__(256) void gemv_kernel(const FieldK F, const Job J, 
   extern __shared__ uint16_t s_tab[];
   constexpr bool kTab = HasTable<Pol>::value;
   if constexpr (kTab) {
-    const uint16_t* src = std::is_same<Pol, PZechExp>::value ? F.zval : F.zplus1;
-    for (uint32_t i = threadIdx.x; i < F.p32; i += 256) s_tab[i] = src[i];
+    for (uint32_t i = threadIdx.x; i < F.p32; i += 256) s_tab[i] = table_entry<Pol>(F, i);
     __syncthreads();
   }
   const uint64_t row = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -1067,8 +1226,7 @@ __global__ __launch_bounds__(256) void gemv_rows_kernel(const FieldK F, const Jo
   extern __shared__ uint16_t s_tab[];
   constexpr bool kTab = HasTable<Pol>::value;
   if constexpr (kTab) {
-    const uint16_t* src = std::is_same<Pol, PZechExp>::value ? F.zval : F.zplus1;
-    for (uint32_t i = threadIdx.x; i < F.p32; i += 256) s_tab[i] = src[i];
+    for (uint32_t i = threadIdx.x; i < F.p32; i += 256) s_tab[i] = table_entry<Pol>(F, i);
     __syncthreads();
   }
   const uint64_t wv = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -1159,7 +1317,7 @@ __global__ void x_phase_copies_kernel(const E* x, uint64_t n, uint8_t* xbase, ui
 // ---------------------------------------------------------------- launching
 enum class Kind {
   ZpzDelayed, ZpzPerTerm, ZpzOverflow, ZpzHybrid, MontDelayed, MontPerTerm, MontOverflow,
-  MontHybrid, F64, ZechExp, ZechTplus1, Centred
+  MontHybrid, F64, ZechExp, ZechTplus1, ZechTplus1P, Centred
 };
 
 // Sec. 3.4, Eq. 2 (strict reading): largest lambda with lambda p (p-1) < 2^64.
@@ -1230,7 +1388,13 @@ static fdot_status_t make_plan_lambda(const fdot_field_s* f, fdot_algo_t algo, P
       return FDOT_OK;
     case FDOT_REP_ZECH_U16:
       pl->lds = (size_t)I.p * 2;
-      if (algo == FDOT_ALGO_ZECH_TPLUS1) { pl->kind = Kind::ZechTplus1; return FDOT_OK; }
+      if (algo == FDOT_ALGO_ZECH_TPLUS1) {
+        // two codes per packed 16-bit instruction where a sum of two codes
+        // fits 16 bits (tune key zech.packed = 0 keeps one code per lane)
+        const bool packed = I.p <= 32768 && fd_tune("zech.packed", 1) != 0;
+        pl->kind = packed ? Kind::ZechTplus1P : Kind::ZechTplus1;
+        return FDOT_OK;
+      }
       if (algo != FDOT_ALGO_ZECH_EXP) return FDOT_E_UNSUPPORTED;
       pl->kind = Kind::ZechExp;
       // each 32-bit sum takes four values below p per vector
@@ -1372,6 +1536,7 @@ static fdot_status_t dispatch(const Plan& pl, const Launch& A0) {
     case Kind::F64: return launch_t<PF64, 256>(A);
     case Kind::ZechExp: return launch_t<PZechExp, 1024>(A);
     case Kind::ZechTplus1: return launch_t<PZechTplus1, 1024>(A);
+    case Kind::ZechTplus1P: return launch_t<PZechTplus1P, 1024>(A);
     case Kind::Centred: return launch_t<PCentred, 256>(A);
   }
   return FDOT_E_UNSUPPORTED;
@@ -1634,6 +1799,7 @@ fdot_status_t fd_launch_gemv(const fdot_field_s* f, size_t m, size_t n, const vo
     case Kind::F64: return launch_gemv_t<PF64>(f, J, m, n, A, lda, x, y, 0, s);
     case Kind::ZechExp: return launch_gemv_t<PZechExp>(f, J, m, n, A, lda, x, y, pl.lds, s);
     case Kind::ZechTplus1: return launch_gemv_t<PZechTplus1>(f, J, m, n, A, lda, x, y, pl.lds, s);
+    case Kind::ZechTplus1P: return launch_gemv_t<PZechTplus1P>(f, J, m, n, A, lda, x, y, pl.lds, s);
     case Kind::Centred: return launch_gemv_t<PCentred>(f, J, m, n, A, lda, x, y, 0, s);
   }
   return FDOT_E_UNSUPPORTED;
