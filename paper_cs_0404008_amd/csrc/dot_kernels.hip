@@ -32,6 +32,7 @@
 #include <utility>
 
 #include "fdot_internal.h"
+#include "zech_packed.h"
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -443,32 +444,10 @@ struct PZechTplus1 {
   }
 };
 
-// The same Zech addition for p <= 32768, two accumulators per register.
-// Codes then fit 15 bits, so the index arithmetic of two codes runs in one
-// packed 16-bit instruction (a sum of two codes stays below 2^16), and the
-// tests for the zero element become bit masks instead of per-code selects:
-//  * product: s = a + b; (s - 1) mod q' = min(s - 1, s - 1 - q') in 16-bit
-//    wrap-around arithmetic (q' = p - 1), code ((s - 1) mod q') + 1, and a
-//    mask that is all ones in each half where neither factor is zero;
-//  * sum g^u + g^t = g^(u + h) with g^h = 1 + g^k, k = t - u: first
-//    k - 1 = (t - 1 - u) mod q' by the same minimum, then the shifted
-//    plus-one table in LDS, tab[k - 1] = h - 1, or 0x8000 where 1 + g^k = 0;
-//    the code of the sum is ((u + h - 1) mod q') + 1 (one more minimum),
-//    zeroed where the table holds the 0x8000 mark; a zero accumulator takes
-//    the product, a zero product leaves the accumulator as it is.
-// Every table index lies in [0, q' - 1] for any codes in [0, q'].
-//
-// The packed 16-bit ALU instructions are written out one per statement (so
-// that the compiler can still interleave the four accumulators' chains): it
-// otherwise turns the mask arithmetic back into per-half compares and
-// selects.  They are pure register operations, no memory access.
-#define FD_PK(op, d, a, b) asm(op " %0, %1, %2" : "=v"(d) : "v"(a), "v"(b))
-// the same with a wave-uniform operand in a scalar register (second, or first)
-#define FD_PKS(op, d, a, b) asm(op " %0, %1, %2" : "=v"(d) : "v"(a), "s"(b))
-#define FD_PKS1(op, d, a, b) asm(op " %0, %1, %2" : "=v"(d) : "s"(a), "v"(b))
-// 0 - a in both halves: all ones where a half is 1, zero where it is 0
-#define FD_PKNEG(d, a) asm("v_pk_sub_u16 %0, 0, %1" : "=v"(d) : "v"(a))
-
+// The same Zech addition for p <= 32768 with two accumulators per register:
+// the packed step of zech_packed.h (index arithmetic of two codes per 16-bit
+// instruction, the zero element by bit masks) on the plus-one table shifted
+// by one index with a mark where 1 + g^k = 0.
 struct PZechTplus1P {
   using E = uint16_t;
   static constexpr int VW = 8;
@@ -479,45 +458,15 @@ struct PZechTplus1P {
   uint32_t z[4];   // accumulators 2j (low half) and 2j+1 (high half)
   uint32_t zt;     // accumulator of the scalar head and tail
   const uint16_t* tab;
-  uint32_t k1, q1, qq, f15;  // packed constants: 1, q' + 1, q', 15 in both halves
+  ZechPacked C;
   __device__ void init(const FieldK& F) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) z[j] = 0;
     zt = 0;
-    k1 = 0x00010001u;
-    qq = F.qbar | (F.qbar << 16);
-    q1 = (F.qbar + 1) | ((F.qbar + 1) << 16);
-    f15 = 0x000F000Fu;
+    C = zech_packed_constants(F);
   }
   __device__ __forceinline__ uint32_t step(uint32_t zw, uint32_t aw, uint32_t bw) const {
-    uint32_t S, Sa, Sb, R, mn, m1, mp, Pc, D, Dq, K, K2, S1, S1q, Wm, W, hs, keep, mz, mu;
-    FD_PK("v_pk_add_u16", S, aw, bw);
-    FD_PKS("v_pk_sub_u16", Sa, S, k1);
-    FD_PKS("v_pk_sub_u16", Sb, S, q1);
-    FD_PK("v_pk_min_u16", R, Sa, Sb);        // (s - 1) mod q'
-    FD_PK("v_pk_min_u16", mn, aw, bw);
-    FD_PKS("v_pk_min_u16", m1, mn, k1);
-    FD_PKNEG(mp, m1);                        // ones where the product is nonzero
-    const uint32_t Pm = R & mp;              // product code - 1 (0 if zero)
-    FD_PKS("v_pk_add_u16", Pc, Pm, k1);      // product code
-    FD_PK("v_pk_sub_u16", D, Pm, zw);
-    FD_PKS("v_pk_add_u16", Dq, D, qq);
-    FD_PK("v_pk_min_u16", K, D, Dq);         // k - 1 in [0, q' - 1]
-    FD_PK("v_pk_add_u16", K2, K, K);         // byte offsets of the two table entries
-    const char* tb = (const char*)tab;
-    const uint32_t hw = (uint32_t)*(const uint16_t*)(tb + (K2 & 0xFFFFu)) |
-                        ((uint32_t)*(const uint16_t*)(tb + (K2 >> 16)) << 16);
-    FD_PK("v_pk_add_u16", S1, zw, hw);       // u + h - 1
-    FD_PKS("v_pk_sub_u16", S1q, S1, qq);
-    FD_PK("v_pk_min_u16", Wm, S1, S1q);
-    FD_PKS("v_pk_add_u16", W, Wm, k1);       // code of the sum
-    FD_PKS1("v_pk_lshrrev_b16", hs, f15, hw);
-    FD_PKS("v_pk_sub_u16", keep, hs, k1);    // zero where the sum is 0
-    FD_PKS("v_pk_min_u16", mz, zw, k1);
-    FD_PKNEG(mu, mz);                        // ones where u != 0
-    const uint32_t r1 = W & keep;
-    const uint32_t r2 = (r1 & mu) | (Pc & ~mu);
-    return (r2 & mp) | (zw & ~mp);
+    return zech_step2(zw, aw, bw, (const char*)tab, C);
   }
   __device__ void vec(const u32x4& a, const u32x4& b, const FieldK&) {
     z[0] = step(z[0], a.x, b.x);
@@ -550,11 +499,7 @@ struct ShiftedPlus1<P, decltype((void)P::kShiftedPlus1)> { static constexpr bool
 template <class Pol>
 __device__ __forceinline__ uint16_t table_entry(const FieldK& F, uint32_t i) {
   if constexpr (std::is_same<Pol, PZechExp>::value) return F.zval[i];
-  if constexpr (ShiftedPlus1<Pol>::value) {
-    if (i + 1 >= F.p32) return 0;
-    const uint16_t h = F.zplus1[i + 1];
-    return h == 0 ? (uint16_t)0x8000u : (uint16_t)(h - 1);
-  }
+  if constexpr (ShiftedPlus1<Pol>::value) return zech_shifted_entry(F, i);
   return F.zplus1[i];
 }
 

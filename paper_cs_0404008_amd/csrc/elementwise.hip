@@ -12,14 +12,19 @@
 //     sums and differences modulo q-1, negation adds the index of -1,
 //     addition goes through the plus-one table, g^i + g^j = g^i (1 + g^(j-i));
 //   centred residues (Sec. 3.2.2): sums with one correction each way,
-//     products by a signed remainder.
+//     products by the nearest quotient in single precision (below).
 //
-// Division multiplies by the inverse.  Except for discrete logarithms, the
-// inverse is b^(p-2) (Fermat), by square-and-multiply with the
+// Division multiplies by the inverse.  For classical, Montgomery and double
+// residues the inverse is b^(p-2) (Fermat), by square-and-multiply with the
 // representation's own product: the same instruction stream for every lane,
 // where the extended Euclidean algorithm of Sec. 2.1 would branch per lane.
 // On the vector path one exponentiation serves all the divisors of a lane's
-// 16 bytes (simultaneous inversion).  A zero divisor gives the zero element.
+// 16 bytes (simultaneous inversion).  Centred residues (p < 2^8) read their
+// inverses from a 256-entry table built at field creation.  A zero divisor
+// gives the zero element.
+//
+// Discrete-log addition, subtraction and AXPY over fields of at most 32768
+// elements run two codes per packed 16-bit step (zech_packed.h).
 //
 // Every lane handles 16 bytes of each operand (one vector load) when all
 // pointers are 16-byte aligned, else one element, with as many workgroups as
@@ -31,6 +36,7 @@
 #include <type_traits>
 
 #include "fdot_internal.h"
+#include "zech_packed.h"
 
 namespace {
 
@@ -123,16 +129,20 @@ struct RCentred {
   static __device__ E add(E a, E b, const FieldK& F) { return centre((int32_t)a + b, F); }
   static __device__ E sub(E a, E b, const FieldK& F) { return centre((int32_t)a - b, F); }
   static __device__ E neg(E a, const FieldK&) { return (E)-a; }
-  // |v| <= h^2 + h, so v + p (h + 1) is positive and below p^2 < p 2^32:
-  // one 2-by-1 remainder
-  static __device__ E signed_rem(int32_t v, const FieldK& F) {
-    const uint32_t t = (uint32_t)(v + (int32_t)F.p32 * (F.half + 1));
-    const int32_t r = (int32_t)mod_small(t, F);
-    return (E)(r > F.half ? r - (int32_t)F.p32 : r);
+  // Centred remainder of |v| <= h^2 + h < 2^14 (a product, or a x + y):
+  // v - p rint(v / p), the quotient rounded to nearest from v * RN(1/p) in
+  // single precision.  Exact: the computed quotient is within 2^-17 of v/p,
+  // and v/p (p odd) is never closer than 1/(2p) to a half-integer, so the
+  // rounding picks the nearest integer and the remainder lies in [-h, h]
+  // (the same FMA-free remainder as Sec. 2.3's doubles, in a format whose
+  // 24-bit mantissa holds these values exactly).
+  static __device__ E centre_mod(int32_t v, const FieldK& F) {
+    const float q = __builtin_rintf((float)v * F.invPf);
+    return (E)(v - (int32_t)F.p32 * (int32_t)q);
   }
-  static __device__ E mul(E a, E b, const FieldK& F) { return signed_rem((int32_t)a * b, F); }
+  static __device__ E mul(E a, E b, const FieldK& F) { return centre_mod((int32_t)a * b, F); }
   static __device__ E axpy(E a, E x, E y, const FieldK& F) {
-    return signed_rem((int32_t)a * x + y, F);
+    return centre_mod((int32_t)a * x + y, F);
   }
   static __device__ bool is_zero(E a) { return a == 0; }
 };
@@ -182,6 +192,9 @@ template <class R>
 __device__ typename R::E divide(typename R::E a, typename R::E b, const FieldK& F) {
   if constexpr (std::is_same<R, RZech>::value) {
     return R::div(a, b, F);
+  } else if constexpr (std::is_same<R, RCentred>::value) {
+    // the table of inverses (in LDS), inverse of 0 stored as 0
+    return R::mul(a, F.cinv[(int32_t)b + 128], F);
   } else {
     if (R::is_zero(b)) return R::zero();
     if (F.p == 2) return a;  // the only nonzero divisor is 1
@@ -241,6 +254,12 @@ __global__ __launch_bounds__(NT) void ew_kernel(const FieldK Fin, uint64_t n,
                                                 typename R::E a) {
   using E = typename R::E;
   FieldK F = Fin;
+  if constexpr (std::is_same<R, RCentred>::value && OP == FDOT_EW_DIV) {
+    __shared__ int8_t s_inv[256];
+    for (uint32_t i = threadIdx.x; i < 256; i += NT) s_inv[i] = Fin.cinv[i];
+    __syncthreads();
+    F.cinv = s_inv;
+  }
   if constexpr (table_in_lds<R, OP>()) {
     extern __shared__ uint16_t s_plus1[];
     for (uint32_t i = threadIdx.x; i < (uint32_t)Fin.p; i += NT) s_plus1[i] = Fin.zplus1[i];
@@ -259,7 +278,8 @@ __global__ __launch_bounds__(NT) void ew_kernel(const FieldK Fin, uint64_t n,
       V yv = {};
       if constexpr (reads_y<OP>()) yv = load16((const V*)y + v);
       V out;
-      if constexpr (OP == FDOT_EW_DIV && !std::is_same<R, RZech>::value) {
+      if constexpr (OP == FDOT_EW_DIV && !std::is_same<R, RZech>::value &&
+                    !std::is_same<R, RCentred>::value) {
         divide_vec<R, W>(xv.e, yv.e, out.e, F);
       } else {
 #pragma unroll
@@ -275,12 +295,77 @@ __global__ __launch_bounds__(NT) void ew_kernel(const FieldK Fin, uint64_t n,
   }
 }
 
+// Discrete-log addition, subtraction and AXPY for fields of at most 32768
+// elements: each is z + a b per code (zech_packed.h) -- x + y with a = 1,
+// x - y = x + (-1) y, a x + y -- on two codes per packed step, with the
+// shifted plus-one table in LDS.  aw: the code of a in both halves.
+template <int OP, bool VEC, int NT>
+__global__ __launch_bounds__(NT) void ew_zech2_kernel(const FieldK F, uint64_t n, const uint16_t* x,
+                                                      const uint16_t* y, uint16_t* r, uint32_t aw) {
+  extern __shared__ uint16_t s_tab[];
+  for (uint32_t i = threadIdx.x; i < F.p32; i += NT) s_tab[i] = zech_shifted_entry(F, i);
+  __syncthreads();
+  const ZechPacked C = zech_packed_constants(F);
+  const char* tb = (const char*)s_tab;
+  // SUB accumulates into x (z = x, b = y); ADD and AXPY into y (z = y, b = x)
+  const uint16_t* zs = OP == FDOT_EW_SUB ? x : y;
+  const uint16_t* bs = OP == FDOT_EW_SUB ? y : x;
+  const uint64_t tid = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * NT;
+  uint64_t done = 0;
+  if constexpr (VEC) {
+    const uint64_t nv = n / 8;
+    for (uint64_t v = tid; v < nv; v += stride) {
+      const v4u zv = load16((const v4u*)zs + v);
+      const v4u bv = load16((const v4u*)bs + v);
+      v4u out;
+      out.x = zech_step2(zv.x, aw, bv.x, tb, C);
+      out.y = zech_step2(zv.y, aw, bv.y, tb, C);
+      out.z = zech_step2(zv.z, aw, bv.z, tb, C);
+      out.w = zech_step2(zv.w, aw, bv.w, tb, C);
+      store16((v4u*)r + v, out);
+    }
+    done = nv * 8;
+  }
+  for (uint64_t i = done + tid; i < n; i += stride)  // low half only
+    r[i] = (uint16_t)zech_step2(zs[i], aw & 0xFFFFu, bs[i], tb, C);
+}
+
+template <int OP>
+fdot_status_t launch_zech2(const fdot_field_s* f, uint64_t n, uint16_t a, const void* x,
+                           const void* y, void* r, hipStream_t s) {
+  constexpr int NT = 1024;
+  const FieldK& F = f->k;
+  uint32_t code = a;                                  // AXPY
+  if (OP == FDOT_EW_ADD) code = F.qbar;               // 1
+  if (OP == FDOT_EW_SUB) code = F.half ? (uint32_t)F.half : F.qbar;  // -1 (= 1 in characteristic 2)
+  const uint32_t aw = code | (code << 16);
+  const bool vec = (((uintptr_t)x | (uintptr_t)y | (uintptr_t)r) & 15u) == 0;
+  const uint64_t work = vec ? (n + 7) / 8 : n;
+  const size_t lds = (size_t)F.p * sizeof(uint16_t);  // q entries
+  const uint64_t per_cu = std::max<uint64_t>(1, (160u * 1024u) / lds);
+  const unsigned grid = (unsigned)std::max<uint64_t>(
+      1, std::min<uint64_t>((work + NT - 1) / NT, (uint64_t)fd_cu_count() * per_cu));
+  if (vec)
+    hipLaunchKernelGGL((ew_zech2_kernel<OP, true, NT>), dim3(grid), dim3(NT), lds, s, F, n,
+                       (const uint16_t*)x, (const uint16_t*)y, (uint16_t*)r, aw);
+  else
+    hipLaunchKernelGGL((ew_zech2_kernel<OP, false, NT>), dim3(grid), dim3(NT), lds, s, F, n,
+                       (const uint16_t*)x, (const uint16_t*)y, (uint16_t*)r, aw);
+  return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
+}
+
 template <class R, int OP>
 fdot_status_t launch_op(const fdot_field_s* f, uint64_t n, const void* alpha, const void* x,
                         const void* y, void* r, hipStream_t s) {
   using E = typename R::E;
   E a{};
   if (alpha) memcpy(&a, alpha, sizeof(E));
+  if constexpr (table_in_lds<R, OP>()) {
+    // q <= 32768: two codes per packed step (tune key zech.packed = 0: one per lane)
+    if (f->k.p <= 32768 && fd_tune("zech.packed", 1) != 0)
+      return launch_zech2<OP>(f, n, (uint16_t)a, x, y, r, s);
+  }
   const uintptr_t bits = (uintptr_t)x | (uintptr_t)r | (reads_y<OP>() ? (uintptr_t)y : 0);
   const bool vec = (bits & 15u) == 0;
   const uint64_t per = vec ? 16 / sizeof(E) : 1;

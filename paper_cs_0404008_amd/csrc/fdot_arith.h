@@ -32,6 +32,9 @@ struct FieldK {
   const uint16_t* zval;    // Zech code -> value, p entries (zval[0] = 0)
   const uint16_t* zplus1;  // Zech plus-one table, p entries
   const uint16_t* zidx;    // value -> Zech code, p entries
+  const int8_t* cinv;      // centred residues (p < 2^8): inverse of c at c + 128, 256 entries
+  float invPf;             // 1/p in single precision (centred residues)
+  uint32_t pad2;
 };
 
 // Remainder of the two-word number u1*2^32 + u0 by a normalised divisor d

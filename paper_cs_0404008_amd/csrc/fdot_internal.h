@@ -19,6 +19,7 @@ struct fdot_field_s {
   uint16_t* d_zval;     // Zech tables on the device (owned)
   uint16_t* d_zplus1;
   uint16_t* d_zidx;
+  int8_t* d_cinv;       // centred residues: table of inverses (owned)
 };
 
 // Most ranges of one batched launch (one per group of resident wavefronts).

@@ -179,6 +179,7 @@ void fd_fieldk_from_info(const fdot_field_info_t* I, FieldK* k) {
   k->n_im = I->n_im;
   k->qbar = (uint32_t)(I->p - 1);
   k->half = (int32_t)((I->p - 1) / 2);
+  k->invPf = (float)I->inv_p;
 }
 
 // Zech tables for the generator g (Sec. 2.4).  Codes: 0 for the zero element,
@@ -402,6 +403,25 @@ fdot_status_t fdot_field_create(uint64_t p, fdot_rep_t rep, const fdot_options_t
     f->k.zidx = f->d_zidx;
     f->k.zplus1 = f->d_zplus1;
   }
+  if (rep == FDOT_REP_CENTRED_I8) {
+    // inverses of the centred residues, for elementwise division: c * c^-1
+    // = 1 mod p, found by trying every candidate (p < 2^8); 0 maps to 0
+    int8_t h[256];
+    memset(h, 0, sizeof h);
+    const int64_t pp = (int64_t)p, half = (pp - 1) / 2;
+    for (int64_t c = -half; c <= half; ++c) {
+      if (c == 0) continue;
+      for (int64_t d = -half; d <= half; ++d)
+        if ((((c * d) % pp) + pp) % pp == 1) { h[c + 128] = (int8_t)d; break; }
+    }
+    int8_t* d = nullptr;
+    if (hipMalloc((void**)&d, sizeof h) != hipSuccess) { delete f; return FDOT_E_NOMEM; }
+    if (hipMemcpy(d, h, sizeof h, hipMemcpyHostToDevice) != hipSuccess) {
+      hipFree(d); delete f; return FDOT_E_DEVICE;
+    }
+    f->d_cinv = d;
+    f->k.cinv = d;
+  }
   *out = f;
   return FDOT_OK;
 }
@@ -520,6 +540,7 @@ fdot_status_t fdot_field_create_ext(uint64_t p, uint32_t d, fdot_field_t* out) {
 fdot_status_t fdot_field_destroy(fdot_field_t f) {
   if (!f) return FDOT_E_INVALID_ARG;
   if (f->d_zval) hipFree(f->d_zval);
+  if (f->d_cinv) hipFree(f->d_cinv);
   delete f;
   return FDOT_OK;
 }

@@ -156,3 +156,45 @@ def test_centred_products_exhaustive(p):
     for op, alpha in (("mul", None), ("axpy", np.int8(h)), ("axpy", np.int8(-h))):
         got = run(F, op, x, y, y, alpha)
         assert same(got, want(p, "centred", op, x, y, y, alpha)), (p, op, alpha)
+
+
+@pytest.mark.parametrize("p", [251, 241, 3, 5, 127])
+def test_centred_division_exhaustive(p):
+    """Centred division reads the inverse of each divisor from a table built
+    at field creation: every quotient x / y over all pairs of residues (zero
+    divisors give zero), on the vector path and the misaligned one."""
+    F = field(p, "centred")
+    h = (p - 1) // 2
+    vals = np.arange(-h, h + 1, dtype=np.int8)
+    x = np.repeat(vals, vals.size)
+    y = np.tile(vals, vals.size)
+    for offset in (0, 3):
+        got = run(F, "div", x, y, x, None, offset=offset)
+        assert same(got, want(p, "centred", "div", x, y, x, None)), (p, offset)
+
+
+@pytest.mark.parametrize("p", [3, 5, 7, 11, 257, 4099])
+def test_zech_sums_exhaustive(p):
+    """Discrete-log sums, differences and AXPY over fields of at most 32768
+    elements (two codes per packed step): every pair of codes (0 = the zero
+    element, q - 1 = the unit), sampled pairs for q = 4099, with the
+    multipliers 0, 1, -1 and a generic one, aligned and misaligned."""
+    F = field(p, "zech")
+    if p <= 257:
+        c = np.arange(p, dtype=np.uint16)
+        x, y = np.repeat(c, p), np.tile(c, p)
+    else:
+        x, y = stored(p, "zech", 300007, 96, 0), stored(p, "zech", 300007, 96, 1)
+        x[:p], y[:p] = np.arange(p, dtype=np.uint16), np.arange(p, dtype=np.uint16)[::-1]
+    r = y.copy()
+    half = (p - 1) // 2
+    alphas = sorted({0, p - 1, half if half else p - 1, min(p - 1, 2)})
+    for offset in (0, 1):
+        for op in ("add", "sub"):
+            got = run(F, op, x, y, r, None, offset=offset)
+            assert same(got, want(p, "zech", op, x, y, r, None)), (p, op, offset)
+        for a in alphas:
+            alpha = np.uint16(a)
+            for op in ("axpy", "axpyin"):
+                got = run(F, op, x, y, r, alpha, offset=offset)
+                assert same(got, want(p, "zech", op, x, y, r, alpha)), (p, op, a, offset)

@@ -165,3 +165,22 @@ def test_ext_unsupported_forms():
         fd.Field(2, "zech", degree=17)         # q > 65536
     with pytest.raises(fd.FdotError):
         fd.Field(4, "zech", degree=2)          # p not prime
+
+
+@pytest.mark.parametrize("p,d", [(2, 2), (2, 8), (3, 2), (3, 5)], ids=str)
+def test_ext_sums_exhaustive(p, d):
+    """Sums, differences and AXPY over small extension fields (two codes per
+    packed step, -1 = 1 in characteristic 2): every pair of codes."""
+    F = field(p, d)
+    q = p ** d
+    c = np.arange(q, dtype=np.uint16)
+    x, y = np.repeat(c, q), np.tile(c, q)
+    r = codes(q, x.size, 65, 0)
+    for op in ("add", "sub", "axpy", "axpyin"):
+        for alpha in ((None,) if op in ("add", "sub") else (0, 1, q - 1, (q - 1) // 2 or 1)):
+            ins_y = y if op != "axpyin" else None
+            out = to_dev(r) if op == "axpyin" else None
+            got = F.elementwise(op, to_dev(x), to_dev(ins_y) if ins_y is not None else None,
+                                alpha=alpha, out=out)
+            want = oracle.ext_elementwise(p, d, op, x, ins_y, alpha, r if op == "axpyin" else None)
+            assert same(to_host(got), want), (p, d, op, alpha)
