@@ -488,19 +488,19 @@ struct PZechTplus1P {
   }
 };
 
-// LDS entry i of a table policy: the value table, the plus-one table, or for
-// the packed policy the plus-one table shifted by one index with its zero
-// mark (entries past q' - 1 are never read).
+// The table a table policy stages in LDS: the value table, the plus-one
+// table, or for the packed policy the plus-one table shifted by one index
+// with its zero mark.
 template <class Pol, class = void>
 struct ShiftedPlus1 { static constexpr bool value = false; };
 template <class P>
 struct ShiftedPlus1<P, decltype((void)P::kShiftedPlus1)> { static constexpr bool value = P::kShiftedPlus1; };
 
 template <class Pol>
-__device__ __forceinline__ uint16_t table_entry(const FieldK& F, uint32_t i) {
-  if constexpr (std::is_same<Pol, PZechExp>::value) return F.zval[i];
-  if constexpr (ShiftedPlus1<Pol>::value) return zech_shifted_entry(F, i);
-  return F.zplus1[i];
+__device__ __forceinline__ const uint16_t* table_source(const FieldK& F) {
+  if constexpr (std::is_same<Pol, PZechExp>::value) return F.zval;
+  if constexpr (ShiftedPlus1<Pol>::value) return F.zsh1;
+  return F.zplus1;
 }
 
 // Centred residues in int8 (Sec. 3.2.2): four-way int8 dot products into a
@@ -709,8 +709,7 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
 // workgroup.
 template <class Pol, int NTH>
 __device__ __forceinline__ void load_table(const FieldK& F, uint16_t* s_tab) {
-  for (uint32_t i = threadIdx.x; i < F.p32; i += NTH) s_tab[i] = table_entry<Pol>(F, i);
-  __syncthreads();
+  fd_table_to_lds<NTH>(s_tab, table_source<Pol>(F), F.p32);
 }
 
 // Adds a unit's residue to its pair's combination word.  The returned old
@@ -1136,8 +1135,7 @@ __global__ __launch_bounds__(256) void gemv_kernel(const FieldK F, const Job J, 
   extern __shared__ uint16_t s_tab[];
   constexpr bool kTab = HasTable<Pol>::value;
   if constexpr (kTab) {
-    for (uint32_t i = threadIdx.x; i < F.p32; i += 256) s_tab[i] = table_entry<Pol>(F, i);
-    __syncthreads();
+    fd_table_to_lds<256>(s_tab, table_source<Pol>(F), F.p32);
   }
   const uint64_t row = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= m) return;
@@ -1171,8 +1169,7 @@ __global__ __launch_bounds__(256) void gemv_rows_kernel(const FieldK F, const Jo
   extern __shared__ uint16_t s_tab[];
   constexpr bool kTab = HasTable<Pol>::value;
   if constexpr (kTab) {
-    for (uint32_t i = threadIdx.x; i < F.p32; i += 256) s_tab[i] = table_entry<Pol>(F, i);
-    __syncthreads();
+    fd_table_to_lds<256>(s_tab, table_source<Pol>(F), F.p32);
   }
   const uint64_t wv = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const uint64_t c = wv % P, q = wv / P;

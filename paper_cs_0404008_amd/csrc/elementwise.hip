@@ -262,8 +262,7 @@ __global__ __launch_bounds__(NT) void ew_kernel(const FieldK Fin, uint64_t n,
   }
   if constexpr (table_in_lds<R, OP>()) {
     extern __shared__ uint16_t s_plus1[];
-    for (uint32_t i = threadIdx.x; i < (uint32_t)Fin.p; i += NT) s_plus1[i] = Fin.zplus1[i];
-    __syncthreads();
+    fd_table_to_lds<NT>(s_plus1, Fin.zplus1, (uint32_t)Fin.p);
     F.zplus1 = s_plus1;
   }
   const uint64_t tid = (uint64_t)blockIdx.x * NT + threadIdx.x;
@@ -295,6 +294,79 @@ __global__ __launch_bounds__(NT) void ew_kernel(const FieldK Fin, uint64_t n,
   }
 }
 
+// Division for classical, Montgomery and double residues on 16-byte aligned
+// operands: each lane takes NE elements (NE / W vectors, NT vectors apart so
+// that the loads stay coalesced) and inverts their divisors with one
+// exponentiation (simultaneous inversion, as divide_vec, over NE elements
+// instead of one vector's W): about 4 products per element plus an NE-th of
+// an exponentiation.  A zero divisor counts as one in the product and gives
+// zero.  The n mod W last elements are divided one by one.
+template <class R, int NT, int NE>
+__global__ __launch_bounds__(NT) void ew_div_kernel(const FieldK F, uint64_t n,
+                                                    const typename R::E* x,
+                                                    const typename R::E* y, typename R::E* r) {
+  using E = typename R::E;
+  constexpr int W = 16 / (int)sizeof(E);
+  constexpr int G = NE / W;
+  static_assert(G * W == NE, "whole vectors per lane");
+  struct alignas(16) V { E e[W]; };
+  const uint64_t nv = n / W;
+  const uint64_t span = (uint64_t)NT * G;
+  for (uint64_t b0 = (uint64_t)blockIdx.x * span; b0 < nv; b0 += (uint64_t)gridDim.x * span) {
+    E a[NE], d[NE];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const uint64_t v = b0 + (uint64_t)g * NT + threadIdx.x;
+      V xv = {}, yv = {};
+      if (v < nv) {
+        xv = load16((const V*)x + v);
+        yv = load16((const V*)y + v);
+      }
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        a[g * W + k] = xv.e[k];
+        d[g * W + k] = yv.e[k];
+      }
+    }
+    E pre[NE];
+    pre[0] = R::is_zero(d[0]) ? R::one(F) : d[0];
+#pragma unroll
+    for (int k = 1; k < NE; ++k) pre[k] = R::mul(pre[k - 1], R::is_zero(d[k]) ? R::one(F) : d[k], F);
+    E inv = inverse<R>(pre[NE - 1], F);  // of the divisors 0 .. k while peeling
+#pragma unroll
+    for (int k = NE - 1; k > 0; --k) {
+      const E ik = R::mul(inv, pre[k - 1], F);
+      inv = R::mul(inv, R::is_zero(d[k]) ? R::one(F) : d[k], F);
+      a[k] = R::is_zero(d[k]) ? R::zero() : R::mul(a[k], ik, F);
+    }
+    a[0] = R::is_zero(d[0]) ? R::zero() : R::mul(a[0], inv, F);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const uint64_t v = b0 + (uint64_t)g * NT + threadIdx.x;
+      if (v < nv) {
+        V out;
+#pragma unroll
+        for (int k = 0; k < W; ++k) out.e[k] = a[g * W + k];
+        store16((V*)r + v, out);
+      }
+    }
+  }
+  if (blockIdx.x == 0)
+    for (uint64_t i = nv * W + threadIdx.x; i < n; i += NT) r[i] = divide<R>(x[i], y[i], F);
+}
+
+template <class R, int NE>
+fdot_status_t launch_div(const fdot_field_s* f, uint64_t n, const void* x, const void* y, void* r,
+                         hipStream_t s) {
+  using E = typename R::E;
+  constexpr int NT = 256, W = 16 / (int)sizeof(E);
+  const uint64_t blocks = (n / W + (uint64_t)NT * (NE / W) - 1) / ((uint64_t)NT * (NE / W));
+  const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (1ull << 31) - 1));
+  hipLaunchKernelGGL((ew_div_kernel<R, NT, NE>), dim3(grid), dim3(NT), 0, s, f->k, n,
+                     (const E*)x, (const E*)y, (E*)r);
+  return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
+}
+
 // Discrete-log addition, subtraction and AXPY for fields of at most 32768
 // elements: each is z + a b per code (zech_packed.h) -- x + y with a = 1,
 // x - y = x + (-1) y, a x + y -- on two codes per packed step, with the
@@ -303,8 +375,7 @@ template <int OP, bool VEC, int NT>
 __global__ __launch_bounds__(NT) void ew_zech2_kernel(const FieldK F, uint64_t n, const uint16_t* x,
                                                       const uint16_t* y, uint16_t* r, uint32_t aw) {
   extern __shared__ uint16_t s_tab[];
-  for (uint32_t i = threadIdx.x; i < F.p32; i += NT) s_tab[i] = zech_shifted_entry(F, i);
-  __syncthreads();
+  fd_table_to_lds<NT>(s_tab, F.zsh1, F.p32);
   const ZechPacked C = zech_packed_constants(F);
   const char* tb = (const char*)s_tab;
   // SUB accumulates into x (z = x, b = y); ADD and AXPY into y (z = y, b = x)
@@ -314,17 +385,26 @@ __global__ __launch_bounds__(NT) void ew_zech2_kernel(const FieldK F, uint64_t n
   const uint64_t stride = (uint64_t)gridDim.x * NT;
   uint64_t done = 0;
   if constexpr (VEC) {
+    // two vectors per lane per step, all four loads issued before the table
+    // lookups: the resident workgroups are few (the LDS holds few tables), so
+    // each lane keeps more bytes in flight
     const uint64_t nv = n / 8;
-    for (uint64_t v = tid; v < nv; v += stride) {
-      const v4u zv = load16((const v4u*)zs + v);
-      const v4u bv = load16((const v4u*)bs + v);
+    auto step4 = [&](const v4u& zv, const v4u& bv) {
       v4u out;
       out.x = zech_step2(zv.x, aw, bv.x, tb, C);
       out.y = zech_step2(zv.y, aw, bv.y, tb, C);
       out.z = zech_step2(zv.z, aw, bv.z, tb, C);
       out.w = zech_step2(zv.w, aw, bv.w, tb, C);
-      store16((v4u*)r + v, out);
+      return out;
+    };
+    uint64_t v = tid;
+    for (; v + stride < nv; v += 2 * stride) {
+      const v4u z0 = load16((const v4u*)zs + v), b0 = load16((const v4u*)bs + v);
+      const v4u z1 = load16((const v4u*)zs + v + stride), b1 = load16((const v4u*)bs + v + stride);
+      store16((v4u*)r + v, step4(z0, b0));
+      store16((v4u*)r + v + stride, step4(z1, b1));
     }
+    if (v < nv) store16((v4u*)r + v, step4(load16((const v4u*)zs + v), load16((const v4u*)bs + v)));
     done = nv * 8;
   }
   for (uint64_t i = done + tid; i < n; i += stride)  // low half only
@@ -368,6 +448,13 @@ fdot_status_t launch_op(const fdot_field_s* f, uint64_t n, const void* alpha, co
   }
   const uintptr_t bits = (uintptr_t)x | (uintptr_t)r | (reads_y<OP>() ? (uintptr_t)y : 0);
   const bool vec = (bits & 15u) == 0;
+  if constexpr (OP == FDOT_EW_DIV && !std::is_same<R, RZech>::value &&
+                !std::is_same<R, RCentred>::value) {
+    // NE = 16 elements per exponentiation (tune key ew.div_elems: 16 or 32)
+    if (vec)
+      return fd_tune("ew.div_elems", 16) == 32 ? launch_div<R, 32>(f, n, x, y, r, s)
+                                                : launch_div<R, 16>(f, n, x, y, r, s);
+  }
   const uint64_t per = vec ? 16 / sizeof(E) : 1;
   const uint64_t work = (n + per - 1) / per;
   if constexpr (table_in_lds<R, OP>()) {

@@ -20,6 +20,7 @@
 #include <algorithm>
 
 #include "fdot_internal.h"
+#include "zech_packed.h"
 
 namespace {
 
@@ -151,8 +152,7 @@ __global__ __launch_bounds__(NT) void ext_dot_kernel(const FieldK F, const uint1
   extern __shared__ uint16_t s_tab[];
   __shared__ uint32_t s_part[NT / 64];
   const uint16_t* tab = table_of<XOR>(F);
-  for (uint32_t i = threadIdx.x; i < (uint32_t)F.p; i += NT) s_tab[i] = tab[i];
-  __syncthreads();
+  fd_table_to_lds<NT>(s_tab, tab, (uint32_t)F.p);
   const uint32_t qbar = F.qbar;
   const uint64_t tid = (uint64_t)blockIdx.x * NT + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * NT;
@@ -193,8 +193,7 @@ __global__ __launch_bounds__(NT) void ext_many_kernel(const FieldK F, const fdot
   extern __shared__ uint16_t s_tab[];
   __shared__ uint32_t s_part[NT / 64];
   const uint16_t* tab = table_of<XOR>(F);
-  for (uint32_t i = threadIdx.x; i < (uint32_t)F.p; i += NT) s_tab[i] = tab[i];
-  __syncthreads();
+  fd_table_to_lds<NT>(s_tab, tab, (uint32_t)F.p);
   const uint32_t qbar = F.qbar;
   for (uint64_t k = blockIdx.x; k < count; k += gridDim.x) {
     const fdot_desc_t d = desc[k];

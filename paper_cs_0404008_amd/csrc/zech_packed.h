@@ -13,7 +13,7 @@
 //  * sum g^u + g^t = g^(u + h) with g^h = 1 + g^k, k = t - u: first
 //    k - 1 = (t - 1 - u) mod q' by the same minimum, then the plus-one table
 //    shifted by one index, tab[k - 1] = h - 1, or 0x8000 where 1 + g^k = 0
-//    (zech_shifted_entry); the code of the sum is ((u + h - 1) mod q') + 1,
+//    (built at field creation, FieldK::zsh1); the code of the sum is ((u + h - 1) mod q') + 1,
 //    zeroed where the table holds the 0x8000 mark; a zero accumulator takes
 //    the product, a zero product leaves the accumulator as it is.
 // Every table index lies in [0, q' - 1] for any codes in [0, q'].
@@ -49,12 +49,19 @@ __device__ __forceinline__ ZechPacked zech_packed_constants(const FieldK& F) {
   return c;
 }
 
-// Entry i of the shifted plus-one table (entries from q' - 1 on are never
-// read); F.p holds q.
-__device__ __forceinline__ uint16_t zech_shifted_entry(const FieldK& F, uint32_t i) {
-  if (i + 1 >= F.p32) return 0;
-  const uint16_t h = F.zplus1[i + 1];
-  return h == 0 ? (uint16_t)0x8000u : (uint16_t)(h - 1);
+// Copies n table entries from device memory into LDS (all threads of the
+// workgroup, NTH of them), 16 bytes at a time when both sides are 16-byte
+// aligned, and waits for the workgroup.
+template <int NTH>
+__device__ __forceinline__ void fd_table_to_lds(uint16_t* s, const uint16_t* g, uint32_t n) {
+  uint32_t done = 0;
+  if ((((uintptr_t)s | (uintptr_t)g) & 15u) == 0) {
+    const uint32_t nv = n / 8;
+    for (uint32_t i = threadIdx.x; i < nv; i += NTH) ((uint4*)s)[i] = ((const uint4*)g)[i];
+    done = nv * 8;
+  }
+  for (uint32_t i = done + threadIdx.x; i < n; i += NTH) s[i] = g[i];
+  __syncthreads();
 }
 
 // z + a b per 16-bit half; tb: the shifted table (bytes, in LDS).

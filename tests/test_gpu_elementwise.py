@@ -198,3 +198,29 @@ def test_zech_sums_exhaustive(p):
             for op in ("axpy", "axpyin"):
                 got = run(F, op, x, y, r, alpha, offset=offset)
                 assert same(got, want(p, "zech", op, x, y, r, alpha)), (p, op, a, offset)
+
+
+@pytest.mark.parametrize("p,rep", [(32749, "zpz"), (4294967291, "zpz"), (2147483647, "mont"),
+                                   (67108859, "fp64"), (2, "fp64")], ids=str)
+@pytest.mark.parametrize("elems", [16, 32])
+def test_division_batched_inversion(p, rep, elems):
+    """The aligned division kernel inverts the divisors of 16 or 32 elements
+    per lane (whole vectors a workgroup's width apart) with one
+    exponentiation: about one divisor in ten zero, lengths that leave a
+    partial last workgroup, partial vectors and a ragged tail, in place."""
+    F = field(p, rep)
+    rng = np.random.default_rng(97)
+    fd.tune_set("ew.div_elems", elems)
+    try:
+        for n in (1, 7, 4096 * 3 + 11, (1 << 20) + 5):
+            x = stored(p, rep, n, 98, 0)
+            canon = oracle.decode(p, rep, stored(p, rep, n, 98, 1)).astype(np.int64)
+            canon[rng.random(n) < 0.1] = 0
+            y = oracle.encode(p, rep, canon)
+            expect = want(p, rep, "div", x, y, x, None)
+            assert same(run(F, "div", x, y, x, None), expect), (p, rep, n)
+            xd, yd = to_dev(x), to_dev(y)
+            F.elementwise("div", xd, yd, out=xd)
+            assert same(to_host(xd), expect), (p, rep, n, "in place")
+    finally:
+        fd.tune_set("ew.div_elems", None)
