@@ -446,27 +446,31 @@ struct PZechTplus1 {
 
 // The same Zech addition for p <= 32768 with two accumulators per register:
 // the packed step of zech_packed.h (index arithmetic of two codes per 16-bit
-// instruction, the zero element by bit masks) on the plus-one table shifted
-// by one index with a mark where 1 + g^k = 0.
+// instruction, the zero element by bit masks) on a plus-one table with a mark
+// where 1 + g^k = 0; the accumulators stay in the step's running form.
 struct PZechTplus1P {
   using E = uint16_t;
   static constexpr int VW = 8;
   static constexpr int U = 2;
   static constexpr bool kTable = true;
   static constexpr bool kPrefetch = true;
-  static constexpr bool kShiftedPlus1 = true;
-  uint32_t z[4];   // accumulators 2j (low half) and 2j+1 (high half)
+  static constexpr bool kPackedPlus1 = true;
+  static constexpr bool kStepVecs = true;
+  // accumulators in the running form of zech_acc2 (code - 1, zero as
+  // 0xFFFF), two per register; one set of 8 per vector of a step, so that
+  // the U vectors' dependent table reads overlap
+  uint32_t z[4 * U];
   uint32_t zt;     // accumulator of the scalar head and tail
   const uint16_t* tab;
   ZechPacked C;
   __device__ void init(const FieldK& F) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) z[j] = 0;
-    zt = 0;
+    for (int j = 0; j < 4 * U; ++j) z[j] = 0xFFFFFFFFu;
+    zt = 0xFFFFFFFFu;
     C = zech_packed_constants(F);
   }
-  __device__ __forceinline__ uint32_t step(uint32_t zw, uint32_t aw, uint32_t bw) const {
-    return zech_step2(zw, aw, bw, (const char*)tab, C);
+  __device__ __forceinline__ uint32_t step(uint32_t zv, uint32_t aw, uint32_t bw) const {
+    return zech_acc2(zv, aw, bw, (const char*)tab, C);
   }
   __device__ void vec(const u32x4& a, const u32x4& b, const FieldK&) {
     z[0] = step(z[0], a.x, b.x);
@@ -474,13 +478,24 @@ struct PZechTplus1P {
     z[2] = step(z[2], a.z, b.z);
     z[3] = step(z[3], a.w, b.w);
   }
-  __device__ void one(E a, E b, const FieldK&, const Job&) {
-    zt = step(zt, a, b) & 0xFFFFu;  // low half only: the high half adds zero
-  }
-  __device__ uint32_t finish(const FieldK& F) {
-    uint32_t s = F.zval[zt];
+  __device__ void vecs(const u32x4* a, const u32x4* b, const FieldK&) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) s += F.zval[z[j] & 0xFFFFu] + F.zval[z[j] >> 16];
+    for (int u = 0; u < U; ++u) {
+      z[4 * u + 0] = step(z[4 * u + 0], a[u].x, b[u].x);
+      z[4 * u + 1] = step(z[4 * u + 1], a[u].y, b[u].y);
+      z[4 * u + 2] = step(z[4 * u + 2], a[u].z, b[u].z);
+      z[4 * u + 3] = step(z[4 * u + 3], a[u].w, b[u].w);
+    }
+  }
+  __device__ void one(E a, E b, const FieldK&, const Job&) {
+    zt = step(zt, a, b);  // low half only: the high half adds zero and stays zero
+  }
+  // stored code of a running form: v + 1 (0xFFFF -> 0)
+  __device__ static uint32_t code(uint32_t v) { return (v + 1) & 0xFFFFu; }
+  __device__ uint32_t finish(const FieldK& F) {
+    uint32_t s = F.zval[code(zt)];
+#pragma unroll
+    for (int j = 0; j < 4 * U; ++j) s += F.zval[code(z[j])] + F.zval[code(z[j] >> 16)];
     return mod_u64(s, F);
   }
   __device__ static void store(void* out, uint64_t k, uint32_t r, const FieldK& F) {
@@ -489,17 +504,16 @@ struct PZechTplus1P {
 };
 
 // The table a table policy stages in LDS: the value table, the plus-one
-// table, or for the packed policy the plus-one table shifted by one index
-// with its zero mark.
+// table, or for the packed policy its plus-one table with the zero mark.
 template <class Pol, class = void>
-struct ShiftedPlus1 { static constexpr bool value = false; };
+struct PackedPlus1 { static constexpr bool value = false; };
 template <class P>
-struct ShiftedPlus1<P, decltype((void)P::kShiftedPlus1)> { static constexpr bool value = P::kShiftedPlus1; };
+struct PackedPlus1<P, decltype((void)P::kPackedPlus1)> { static constexpr bool value = P::kPackedPlus1; };
 
 template <class Pol>
 __device__ __forceinline__ const uint16_t* table_source(const FieldK& F) {
   if constexpr (std::is_same<Pol, PZechExp>::value) return F.zval;
-  if constexpr (ShiftedPlus1<Pol>::value) return F.zsh1;
+  if constexpr (PackedPlus1<Pol>::value) return F.zpk;
   return F.zplus1;
 }
 
@@ -540,6 +554,13 @@ template <class P, class = void>
 struct Prefetch { static constexpr bool value = false; };
 template <class P>
 struct Prefetch<P, decltype((void)P::kPrefetch)> { static constexpr bool value = P::kPrefetch; };
+
+// A policy that takes all U vectors of a step at once (vecs), e.g. to keep
+// one accumulator set per vector.
+template <class P, class = void>
+struct StepVecs { static constexpr bool value = false; };
+template <class P>
+struct StepVecs<P, decltype((void)P::kStepVecs)> { static constexpr bool value = P::kStepVecs; };
 
 template <class P, class = void>
 struct Folds { static constexpr bool value = false; };
@@ -613,8 +634,12 @@ __device__ __forceinline__ void wave_range(Pol& L, const typename Pol::E* x,
           bn[u] = load_nt(more ? yv + in + (uint64_t)u * step : g_zero16);
         }
         __builtin_amdgcn_sched_barrier(0);
+        if constexpr (StepVecs<Pol>::value) {
+          L.vecs(a, b, F);
+        } else {
 #pragma unroll
-        for (int u = 0; u < U; ++u) L.vec(a[u], b[u], F);
+          for (int u = 0; u < U; ++u) L.vec(a[u], b[u], F);
+        }
         if constexpr (kF) {
           pending += U;
           if (pending > fv - U) {

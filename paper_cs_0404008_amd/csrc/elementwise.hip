@@ -370,12 +370,12 @@ fdot_status_t launch_div(const fdot_field_s* f, uint64_t n, const void* x, const
 // Discrete-log addition, subtraction and AXPY for fields of at most 32768
 // elements: each is z + a b per code (zech_packed.h) -- x + y with a = 1,
 // x - y = x + (-1) y, a x + y -- on two codes per packed step, with the
-// shifted plus-one table in LDS.  aw: the code of a in both halves.
+// packed step's plus-one table in LDS.  aw: the code of a in both halves.
 template <int OP, bool VEC, int NT>
 __global__ __launch_bounds__(NT) void ew_zech2_kernel(const FieldK F, uint64_t n, const uint16_t* x,
                                                       const uint16_t* y, uint16_t* r, uint32_t aw) {
   extern __shared__ uint16_t s_tab[];
-  fd_table_to_lds<NT>(s_tab, F.zsh1, F.p32);
+  fd_table_to_lds<NT>(s_tab, F.zpk, F.p32);
   const ZechPacked C = zech_packed_constants(F);
   const char* tb = (const char*)s_tab;
   // SUB accumulates into x (z = x, b = y); ADD and AXPY into y (z = y, b = x)

@@ -35,10 +35,11 @@ struct FieldK {
   const int8_t* cinv;      // centred residues (p < 2^8): inverse of c at c + 128, 256 entries
   float invPf;             // 1/p in single precision (centred residues)
   uint32_t pad2;
-  // Zech, q <= 32768: the plus-one table shifted by one index, entry i =
-  // (code of 1 + g^(i+1)) - 1, or 0x8000 where that sum is zero; q entries,
-  // zero-padded to a multiple of 8, 16-byte aligned (null for larger q)
-  const uint16_t* zsh1;
+  // Zech, q <= 32768: the plus-one table of the packed step, entry k = code
+  // of 1 + g^k (k = 0 and k = q - 1 both for g^0), or 0xFFFF where that sum
+  // is zero; q entries, zero-padded to a multiple of 8, 16-byte aligned
+  // (null for larger q)
+  const uint16_t* zpk;
 };
 
 // Remainder of the two-word number u1*2^32 + u0 by a normalised divisor d

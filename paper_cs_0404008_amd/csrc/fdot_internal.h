@@ -19,7 +19,7 @@ struct fdot_field_s {
   uint16_t* d_zval;     // Zech tables on the device (owned)
   uint16_t* d_zplus1;
   uint16_t* d_zidx;
-  uint16_t* d_zsh1;     // Zech, q <= 32768: shifted plus-one table (owned)
+  uint16_t* d_zpk;     // Zech, q <= 32768: plus-one table of the packed step (owned)
   int8_t* d_cinv;       // centred residues: table of inverses (owned)
 };
 
@@ -70,8 +70,8 @@ uint32_t fd_primitive_root(uint64_t p);
 fdot_status_t fd_fill_params(uint64_t p, fdot_rep_t rep, fdot_field_info_t* out);
 void fd_fieldk_from_info(const fdot_field_info_t* info, FieldK* k);
 int fd_zech_build(uint64_t p, uint32_t g, uint16_t* value, uint16_t* index, uint16_t* plus1);
-uint64_t fd_zech_shifted_bytes(uint64_t q);
-fdot_status_t fd_zech_shifted_upload(const uint16_t* plus1, uint32_t q, fdot_field_s* f);
+uint64_t fd_zech_packed_bytes(uint64_t q);
+fdot_status_t fd_zech_packed_upload(const uint16_t* plus1, uint32_t q, fdot_field_s* f);
 
 // Runtime (runtime.cpp).
 fdot_status_t fd_workspace_get(hipStream_t s, size_t count, Workspace** out);

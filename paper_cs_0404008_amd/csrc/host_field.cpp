@@ -152,7 +152,7 @@ fdot_status_t fd_fill_params(uint64_t p, fdot_rep_t rep, fdot_field_info_t* out)
       I.elem_bytes = 2;
       if (p < 3 || p > 65536) return FDOT_E_BOUND;  // codes 0..p-1 in 16 bits
       I.g = fd_primitive_root(p);
-      I.table_bytes = 3ull * p * sizeof(uint16_t) + fd_zech_shifted_bytes(p);
+      I.table_bytes = 3ull * p * sizeof(uint16_t) + fd_zech_packed_bytes(p);
       break;
     case FDOT_REP_CENTRED_I8:
       I.elem_bytes = 1;
@@ -241,24 +241,25 @@ static bool algo_allowed(int rep, int algo) {
   return false;
 }
 
-// Bytes of the shifted plus-one table (q <= 32768, padded to 16 bytes).
-uint64_t fd_zech_shifted_bytes(uint64_t q) {
+// Bytes of the packed step's plus-one table (q <= 32768, padded to 16 bytes).
+uint64_t fd_zech_packed_bytes(uint64_t q) {
   return q <= 32768 ? ((q + 7) & ~7ull) * sizeof(uint16_t) : 0;
 }
 
-// The shifted plus-one table of the packed discrete-log step, from the
-// plus-one table (host copy, q entries): entry i = plus1[i+1] - 1, or 0x8000
-// where 1 + g^(i+1) = 0; the entry past q' - 1 and the padding are 0.
-// Uploaded to f->d_zsh1 / f->k.zsh1; nothing for q > 32768.
-fdot_status_t fd_zech_shifted_upload(const uint16_t* plus1, uint32_t q, fdot_field_s* f) {
-  const uint64_t bytes = fd_zech_shifted_bytes(q);
+// The plus-one table of the packed discrete-log step, from the plus-one
+// table indexed by code (host copy, q entries; code q - 1 is g^0): entry k =
+// plus1[k] for k in [1, q - 1], entry 0 = plus1[q - 1] (1 + g^0), and 0xFFFF
+// in place of the zero code (1 + g^k = 0); the padding is 0.  Uploaded to
+// f->d_zpk / f->k.zpk; nothing for q > 32768.
+fdot_status_t fd_zech_packed_upload(const uint16_t* plus1, uint32_t q, fdot_field_s* f) {
+  const uint64_t bytes = fd_zech_packed_bytes(q);
   if (!bytes) return FDOT_OK;
   const uint64_t n = bytes / sizeof(uint16_t);
   uint16_t* h = new (std::nothrow) uint16_t[n];
   if (!h) return FDOT_E_NOMEM;
   for (uint64_t i = 0; i < n; ++i) {
-    const uint16_t v = i + 1 < q ? plus1[i + 1] : 1;
-    h[i] = i + 1 >= q ? 0 : v == 0 ? (uint16_t)0x8000u : (uint16_t)(v - 1);
+    const uint16_t v = i == 0 ? plus1[q - 1] : i < q ? plus1[i] : 1;
+    h[i] = i >= q ? 0 : v == 0 ? (uint16_t)0xFFFFu : v;
   }
   uint16_t* d = nullptr;
   fdot_status_t st = FDOT_OK;
@@ -269,8 +270,8 @@ fdot_status_t fd_zech_shifted_upload(const uint16_t* plus1, uint32_t q, fdot_fie
   }
   delete[] h;
   if (st == FDOT_OK) {
-    f->d_zsh1 = d;
-    f->k.zsh1 = d;
+    f->d_zpk = d;
+    f->k.zpk = d;
   }
   return st;
 }
@@ -429,7 +430,7 @@ fdot_status_t fdot_field_create(uint64_t p, fdot_rep_t rep, const fdot_options_t
     if (hipMemcpy(d, h, 3 * p * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess) {
       hipFree(d); delete[] h; delete f; return FDOT_E_DEVICE;
     }
-    const fdot_status_t st = fd_zech_shifted_upload(h + 2 * p, p, f);
+    const fdot_status_t st = fd_zech_packed_upload(h + 2 * p, p, f);
     delete[] h;
     if (st != FDOT_OK) { hipFree(d); delete f; return st; }
     f->d_zval = d;
@@ -541,7 +542,7 @@ fdot_status_t fdot_field_create_ext(uint64_t p, uint32_t d, fdot_field_t* out) {
   f->info.p = p;
   f->info.rep = FDOT_REP_ZECH_U16;
   f->info.elem_bytes = 2;
-  f->info.table_bytes = 3ull * q * sizeof(uint16_t) + fd_zech_shifted_bytes(q);
+  f->info.table_bytes = 3ull * q * sizeof(uint16_t) + fd_zech_packed_bytes(q);
   f->info.degree = d;
   f->info.q = q;
   uint64_t pd = 1;
@@ -562,7 +563,7 @@ fdot_status_t fdot_field_create_ext(uint64_t p, uint32_t d, fdot_field_t* out) {
   if (hipMemcpy(dev, h, 3 * q * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess) {
     hipFree(dev); delete[] h; delete f; return FDOT_E_DEVICE;
   }
-  const fdot_status_t ust = fd_zech_shifted_upload(h + 2 * q, (uint32_t)q, f);
+  const fdot_status_t ust = fd_zech_packed_upload(h + 2 * q, (uint32_t)q, f);
   delete[] h;
   if (ust != FDOT_OK) { hipFree(dev); delete f; return ust; }
   f->d_zval = dev;
@@ -579,7 +580,7 @@ fdot_status_t fdot_field_destroy(fdot_field_t f) {
   if (!f) return FDOT_E_INVALID_ARG;
   if (f->d_zval) hipFree(f->d_zval);
   if (f->d_cinv) hipFree(f->d_cinv);
-  if (f->d_zsh1) hipFree(f->d_zsh1);
+  if (f->d_zpk) hipFree(f->d_zpk);
   delete f;
   return FDOT_OK;
 }

@@ -5,18 +5,21 @@
 // element become bit masks instead of per-code selects.
 //
 // Codes (as stored): 0 is the zero element, c in [1, q'] is g^c, q' = q - 1
-// (q' itself codes g^0 = 1).  zech_step2(z, a, b) returns, per half, the code
-// of z + a b:
-//  * product: s = a + b; (s - 1) mod q' = min(s - 1, s - 1 - q') in 16-bit
-//    wrap-around arithmetic; its code is that plus one, with a mask that is
-//    all ones in each half where neither factor is zero;
-//  * sum g^u + g^t = g^(u + h) with g^h = 1 + g^k, k = t - u: first
-//    k - 1 = (t - 1 - u) mod q' by the same minimum, then the plus-one table
-//    shifted by one index, tab[k - 1] = h - 1, or 0x8000 where 1 + g^k = 0
-//    (built at field creation, FieldK::zsh1); the code of the sum is ((u + h - 1) mod q') + 1,
-//    zeroed where the table holds the 0x8000 mark; a zero accumulator takes
-//    the product, a zero product leaves the accumulator as it is.
-// Every table index lies in [0, q' - 1] for any codes in [0, q'].
+// (q' itself codes g^0 = 1).  A running sum is held as v = code - 1 in
+// [0, q' - 1], and the zero element as 0xFFFF (the stored code minus one,
+// modulo 2^16).  zech_acc2(v, a, b) returns, per half, the running form of
+// v + a b for codes a, b:
+//  * product: s = a + b; its running form is (s - 1) mod q', the minimum of
+//    s - 1 (saturating at 0) and s - 1 - q' in 16-bit wrap-around arithmetic;
+//    a mask is all ones in each half where neither factor is zero;
+//  * sum g^u + g^t = g^(u + h) with g^h = 1 + g^k, k = t - u: k is the
+//    difference of the two running forms reduced the same way, the table
+//    gives h (the code of 1 + g^k) or the mark 0xFFFF where 1 + g^k = 0, and
+//    the running form of the sum is (v + h) mod q';
+//  * the mark makes the result 0xFFFF (the sum is zero); a zero running sum
+//    takes the product, a zero product leaves the running sum as it is.
+// Every table index lies in [0, q'] (q' only for a zero running sum, whose
+// lookup is discarded), so the table needs q entries.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,6 +37,16 @@
 #define FD_PKS1(op, d, a, b) asm(op " %0, %1, %2" : "=v"(d) : "s"(a), "v"(b))
 // 0 - a in both halves: all ones where a half is 1, zero where it is 0
 #define FD_PKNEG(d, a) asm("v_pk_sub_u16 %0, 0, %1" : "=v"(d) : "v"(a))
+
+typedef unsigned short fd_u16x2 __attribute__((ext_vector_type(2)));
+
+// a - b per 16-bit half, saturating at 0 (the compiler's own saturating
+// subtraction, one packed instruction).
+__device__ __forceinline__ uint32_t fd_pk_sub_sat(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t,
+                            __builtin_elementwise_sub_sat(__builtin_bit_cast(fd_u16x2, a),
+                                                          __builtin_bit_cast(fd_u16x2, b)));
+}
 
 // Packed constants: 1, q' + 1, q' and 15 in both halves.
 struct ZechPacked {
@@ -64,34 +77,40 @@ __device__ __forceinline__ void fd_table_to_lds(uint16_t* s, const uint16_t* g, 
   __syncthreads();
 }
 
-// z + a b per 16-bit half; tb: the shifted table (bytes, in LDS).
-__device__ __forceinline__ uint32_t zech_step2(uint32_t zw, uint32_t aw, uint32_t bw,
-                                               const char* tb, const ZechPacked& C) {
-  uint32_t S, Sa, Sb, R, mn, m1, mp, Pc, D, Dq, K, K2, S1, S1q, Wm, W, hs, keep, mz, mu;
+// Running form v + a b per 16-bit half; tb: the packed step's plus-one
+// table (FieldK::zpk, bytes, in LDS).
+__device__ __forceinline__ uint32_t zech_acc2(uint32_t v, uint32_t aw, uint32_t bw,
+                                              const char* tb, const ZechPacked& C) {
+  uint32_t S, Sb, R, mn, m1, mp, D, Dq, K, K2, S1, S1q, Wm, hs, hz;
   FD_PK("v_pk_add_u16", S, aw, bw);
-  FD_PKS("v_pk_sub_u16", Sa, S, C.k1);
+  const uint32_t Sa = fd_pk_sub_sat(S, C.k1);
   FD_PKS("v_pk_sub_u16", Sb, S, C.q1);
-  FD_PK("v_pk_min_u16", R, Sa, Sb);        // (s - 1) mod q'
+  FD_PK("v_pk_min_u16", R, Sa, Sb);        // product, running form
   FD_PK("v_pk_min_u16", mn, aw, bw);
   FD_PKS("v_pk_min_u16", m1, mn, C.k1);
   FD_PKNEG(mp, m1);                        // ones where the product is nonzero
-  const uint32_t Pm = R & mp;              // product code - 1 (0 if zero)
-  FD_PKS("v_pk_add_u16", Pc, Pm, C.k1);    // product code
-  FD_PK("v_pk_sub_u16", D, Pm, zw);
+  FD_PK("v_pk_sub_u16", D, R, v);
   FD_PKS("v_pk_add_u16", Dq, D, C.qq);
-  FD_PK("v_pk_min_u16", K, D, Dq);         // k - 1 in [0, q' - 1]
+  FD_PK("v_pk_min_u16", K, D, Dq);         // k in [0, q']
   FD_PK("v_pk_add_u16", K2, K, K);         // byte offsets of the two table entries
   const uint32_t hw = (uint32_t)*(const uint16_t*)(tb + (K2 & 0xFFFFu)) |
                       ((uint32_t)*(const uint16_t*)(tb + (K2 >> 16)) << 16);
-  FD_PK("v_pk_add_u16", S1, zw, hw);       // u + h - 1
+  FD_PK("v_pk_add_u16", S1, v, hw);
   FD_PKS("v_pk_sub_u16", S1q, S1, C.qq);
-  FD_PK("v_pk_min_u16", Wm, S1, S1q);
-  FD_PKS("v_pk_add_u16", W, Wm, C.k1);     // code of the sum
-  FD_PKS1("v_pk_lshrrev_b16", hs, C.f15, hw);
-  FD_PKS("v_pk_sub_u16", keep, hs, C.k1);  // zero where the sum is 0
-  FD_PKS("v_pk_min_u16", mz, zw, C.k1);
-  FD_PKNEG(mu, mz);                        // ones where u != 0
-  const uint32_t r1 = W & keep;
-  const uint32_t r2 = (r1 & mu) | (Pc & ~mu);
-  return (r2 & mp) | (zw & ~mp);
+  FD_PK("v_pk_min_u16", Wm, S1, S1q);      // running form of the sum
+  FD_PKS1("v_pk_ashrrev_i16", hs, C.f15, hw);  // ones where the sum is zero
+  FD_PKS1("v_pk_ashrrev_i16", hz, C.f15, v);   // ones where the running sum is zero
+  const uint32_t r1 = Wm | hs;
+  const uint32_t r2 = (R & hz) | (r1 & ~hz);
+  return (r2 & mp) | (v & ~mp);
+}
+
+// Stored code z + a b per 16-bit half (codes in, code out).
+__device__ __forceinline__ uint32_t zech_step2(uint32_t zw, uint32_t aw, uint32_t bw,
+                                               const char* tb, const ZechPacked& C) {
+  uint32_t v, out;
+  FD_PKS("v_pk_sub_u16", v, zw, C.k1);
+  const uint32_t r = zech_acc2(v, aw, bw, tb, C);
+  FD_PKS("v_pk_add_u16", out, r, C.k1);
+  return out;
 }
