@@ -590,14 +590,15 @@ def extras_elementwise(fd):
 
 def extras_ext_fields(fd):
     """Dot products over extension fields in discrete logarithms (Sec. 2.4.2)
-    at 2^28 codes per operand (1 GiB per call): GF(2^8), GF(3^10), GF(2^16),
-    against the prime field GF(65521) in the same representation.  Plus-one
-    table accumulation everywhere; in characteristic 2 also the value XOR
-    schedule (the default there)."""
+    at 2^28 codes per operand (1 GiB per call): GF(2^8), GF(7^5), GF(3^10),
+    GF(2^16), against the prime field GF(65521) in the same representation.
+    Plus-one table accumulation everywhere (two codes per packed step where
+    q <= 32768); in characteristic 2 also the value XOR schedule (the default
+    there)."""
     import synth
     n = 1 << 28
     out = {}
-    for p, d in [(2, 8), (3, 10), (2, 16), (65521, 1)]:
+    for p, d in [(2, 8), (7, 5), (3, 10), (2, 16), (65521, 1)]:
         F = fd.Field(p, "zech", degree=d)
         q = p ** d
         x = torch.empty(n, dtype=torch.uint16, device="cuda")

@@ -18,6 +18,7 @@
 // plus-one chain; the final value goes back to a code through the index
 // table.  That is about a third of the vector instructions per term.
 #include <algorithm>
+#include <type_traits>
 
 #include "fdot_internal.h"
 #include "zech_packed.h"
@@ -60,7 +61,7 @@ struct Acc<false> {
     z[0] = zadd(z[0], zmul(a, b, qbar), qbar, tab);
   }
   __device__ __forceinline__ void vec(const v4u& a, const v4u& b, uint32_t qbar,
-                                      const uint16_t* tab) {
+                                      const uint16_t* tab, int) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       z[2 * j] = zadd(z[2 * j], zmul(a[j] & 0xFFFFu, b[j] & 0xFFFFu, qbar), qbar, tab);
@@ -82,7 +83,7 @@ struct Acc<true> {
     v0 ^= tab[zmul(a, b, qbar)];  // the zero code's value is 0
   }
   __device__ __forceinline__ void vec(const v4u& a, const v4u& b, uint32_t qbar,
-                                      const uint16_t* tab) {
+                                      const uint16_t* tab, int) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       v0 ^= tab[zmul(a[j] & 0xFFFFu, b[j] & 0xFFFFu, qbar)];
@@ -90,6 +91,50 @@ struct Acc<true> {
     }
   }
   __device__ __forceinline__ uint32_t total(uint32_t, const uint16_t*) const { return v0 ^ v1; }
+};
+
+// Packed accumulators for q <= 32768 (zech_packed.h): two codes per register
+// in the running form, one set of eight per vector of a step, so the EU
+// vectors' dependent table reads overlap; the step's plus-one table (with its
+// zero mark) is in LDS.  total() folds the sets into one register with the
+// same step (adding a running sum s to another is one step with a = the
+// code of s, b = the code of 1) and returns the table sum of its two codes.
+struct AccP {
+  uint32_t z[EU][4];
+  const char* tb;
+  ZechPacked C;
+  __device__ __forceinline__ void init(const FieldK& F, const uint16_t* s_tab) {
+#pragma unroll
+    for (int u = 0; u < EU; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) z[u][j] = 0xFFFFFFFFu;
+    tb = (const char*)s_tab;
+    C = zech_packed_constants(F);
+  }
+  __device__ __forceinline__ void one(uint32_t a, uint32_t b, uint32_t, const uint16_t*) {
+    z[0][0] = zech_acc2(z[0][0], a, b, tb, C);  // high halves: zero codes, a zero product
+  }
+  __device__ __forceinline__ void vec(const v4u& a, const v4u& b, uint32_t, const uint16_t*,
+                                      int u) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) z[u][j] = zech_acc2(z[u][j], a[j], b[j], tb, C);
+  }
+  __device__ __forceinline__ uint32_t add(uint32_t v, uint32_t w) const {
+    uint32_t code;
+    FD_PKS("v_pk_add_u16", code, w, C.k1);  // running form -> code (0xFFFF -> 0)
+    return zech_acc2(v, code, C.qq, tb, C);
+  }
+  __device__ __forceinline__ uint32_t total(uint32_t qbar, const uint16_t* plus1) const {
+    uint32_t r[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      r[j] = z[0][j];
+#pragma unroll
+      for (int u = 1; u < EU; ++u) r[j] = add(r[j], z[u][j]);
+    }
+    const uint32_t v = add(add(r[0], r[1]), add(r[2], r[3]));
+    return zadd((v + 1) & 0xFFFFu, ((v >> 16) + 1) & 0xFFFFu, qbar, plus1);
+  }
 };
 
 // Combines two lane or workgroup sums: table addition of codes, or XOR of
@@ -104,9 +149,9 @@ __device__ __forceinline__ uint32_t combine(uint32_t a, uint32_t b, uint32_t qba
 // Streams vectors v0, v0 + step, ... below nv of x and y into z, EU vector
 // pairs loaded before any is consumed, so that enough bytes are in flight to
 // cover the memory latency.
-template <bool XOR>
+template <class AccT>
 __device__ __forceinline__ void stream_vectors(const v4u* x, const v4u* y, uint64_t v0,
-                                               uint64_t step, uint64_t nv, Acc<XOR>& A,
+                                               uint64_t step, uint64_t nv, AccT& A,
                                                uint32_t qbar, const uint16_t* tab) {
   uint64_t v = v0;
   for (; v + (uint64_t)(EU - 1) * step < nv; v += (uint64_t)EU * step) {
@@ -117,12 +162,12 @@ __device__ __forceinline__ void stream_vectors(const v4u* x, const v4u* y, uint6
       b[u] = __builtin_nontemporal_load(y + v + (uint64_t)u * step);
     }
 #pragma unroll
-    for (int u = 0; u < EU; ++u) A.vec(a[u], b[u], qbar, tab);
+    for (int u = 0; u < EU; ++u) A.vec(a[u], b[u], qbar, tab, u);
   }
   for (; v < nv; v += step) {
     const v4u a = __builtin_nontemporal_load(x + v);
     const v4u b = __builtin_nontemporal_load(y + v);
-    A.vec(a, b, qbar, tab);
+    A.vec(a, b, qbar, tab, 0);
   }
 }
 
@@ -145,26 +190,45 @@ __device__ __forceinline__ const uint16_t* table_of(const FieldK& F) {
   return XOR ? F.zval : F.zplus1;
 }
 
-template <bool XOR>
-__global__ __launch_bounds__(NT) void ext_dot_kernel(const FieldK F, const uint16_t* x,
+// The lane accumulator of a schedule: PK, the packed plus-one step
+// (q <= 32768); otherwise table addition of codes or XOR of values.  The
+// table staged in LDS is the step's own; sums across lanes and workgroups
+// (combine) read the plus-one table indexed by code, which for PK is the
+// one in device memory.
+template <bool XOR, bool PK>
+using AccOf = typename std::conditional<PK, AccP, Acc<XOR>>::type;
+
+template <bool XOR, bool PK>
+__device__ __forceinline__ const uint16_t* staged_table(const FieldK& F) {
+  return PK ? F.zpk : table_of<XOR>(F);
+}
+
+template <bool XOR, bool PK>
+__device__ __forceinline__ void init_acc(AccOf<XOR, PK>& A, const FieldK& F, const uint16_t* s_tab) {
+  if constexpr (PK) A.init(F, s_tab);
+}
+
+template <bool XOR, bool PK>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void ext_dot_kernel(const FieldK F, const uint16_t* x,
                                                      const uint16_t* y, uint64_t n, int vec,
                                                      uint16_t* partial) {
   extern __shared__ uint16_t s_tab[];
   __shared__ uint32_t s_part[NT / 64];
-  const uint16_t* tab = table_of<XOR>(F);
-  fd_table_to_lds<NT>(s_tab, tab, (uint32_t)F.p);
+  fd_table_to_lds<NT>(s_tab, staged_table<XOR, PK>(F), (uint32_t)F.p);
+  const uint16_t* ctab = PK ? F.zplus1 : s_tab;  // for combine
   const uint32_t qbar = F.qbar;
   const uint64_t tid = (uint64_t)blockIdx.x * NT + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * NT;
-  Acc<XOR> A;
+  AccOf<XOR, PK> A;
+  init_acc<XOR, PK>(A, F, s_tab);
   uint64_t done = 0;
   if (vec) {
     const uint64_t nv = n / 8;
-    stream_vectors<XOR>((const v4u*)x, (const v4u*)y, tid, stride, nv, A, qbar, s_tab);
+    stream_vectors((const v4u*)x, (const v4u*)y, tid, stride, nv, A, qbar, s_tab);
     done = nv * 8;
   }
   for (uint64_t i = done + tid; i < n; i += stride) A.one(x[i], y[i], qbar, s_tab);
-  const uint32_t s = block_sum<XOR>(A.total(qbar, s_tab), qbar, s_tab, s_part);
+  const uint32_t s = block_sum<XOR>(A.total(qbar, ctab), qbar, ctab, s_part);
   if (threadIdx.x == 0) partial[blockIdx.x] = (uint16_t)s;
 }
 
@@ -187,30 +251,46 @@ __global__ __launch_bounds__(NT) void ext_sum_kernel(const FieldK F, uint16_t* p
 // Batched form: resident workgroups take whole pairs in turn (pair k goes to
 // workgroup k mod grid), each reducing its pair with all its lanes and the
 // table copied into LDS once.
-template <bool XOR>
+template <bool XOR, bool PK>
 __global__ __launch_bounds__(NT) void ext_many_kernel(const FieldK F, const fdot_desc_t* desc,
                                                       uint64_t count, uint16_t* results) {
   extern __shared__ uint16_t s_tab[];
   __shared__ uint32_t s_part[NT / 64];
-  const uint16_t* tab = table_of<XOR>(F);
-  fd_table_to_lds<NT>(s_tab, tab, (uint32_t)F.p);
+  fd_table_to_lds<NT>(s_tab, staged_table<XOR, PK>(F), (uint32_t)F.p);
+  const uint16_t* ctab = PK ? F.zplus1 : s_tab;  // for combine
   const uint32_t qbar = F.qbar;
   for (uint64_t k = blockIdx.x; k < count; k += gridDim.x) {
     const fdot_desc_t d = desc[k];
     const uint16_t* x = (const uint16_t*)d.x;
     const uint16_t* y = (const uint16_t*)d.y;
-    Acc<XOR> A;
+    AccOf<XOR, PK> A;
+    init_acc<XOR, PK>(A, F, s_tab);
     uint64_t done = 0;
     if (((((uintptr_t)x) | ((uintptr_t)y)) & 15u) == 0) {
       const uint64_t nv = d.n / 8;
-      stream_vectors<XOR>((const v4u*)x, (const v4u*)y, threadIdx.x, NT, nv, A, qbar, s_tab);
+      stream_vectors((const v4u*)x, (const v4u*)y, threadIdx.x, NT, nv, A, qbar, s_tab);
       done = nv * 8;
     }
     for (uint64_t i = done + threadIdx.x; i < d.n; i += NT) A.one(x[i], y[i], qbar, s_tab);
-    const uint32_t sum = block_sum<XOR>(A.total(qbar, s_tab), qbar, s_tab, s_part);
+    const uint32_t sum = block_sum<XOR>(A.total(qbar, ctab), qbar, ctab, s_part);
     if (threadIdx.x == 0) results[k] = XOR ? F.zidx[sum] : (uint16_t)sum;
     __syncthreads();  // s_part is reused by the next pair
   }
+}
+
+}  // namespace
+
+namespace {
+
+// q <= 32768 (tune key zech.packed = 0: one code per lane)
+bool use_packed(const fdot_field_s* f, bool xor_values) {
+  return !xor_values && f->k.zpk != nullptr && fd_tune("zech.packed", 1) != 0;
+}
+
+template <class Fn>
+void set_lds_limit(Fn* fn) {
+  (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            128 * 1024);
 }
 
 }  // namespace
@@ -224,18 +304,20 @@ fdot_status_t fd_launch_ext_many(const fdot_field_s* f, bool xor_values, uint64_
       1, std::min<uint64_t>(count, (uint64_t)fd_cu_count() * std::min<uint64_t>(per_cu, 2)));
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)ext_many_kernel<false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-    (void)hipFuncSetAttribute((const void*)ext_many_kernel<true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    set_lds_limit(ext_many_kernel<false, false>);
+    set_lds_limit(ext_many_kernel<true, false>);
+    set_lds_limit(ext_many_kernel<false, true>);
     attr_set = true;
   }
   if (xor_values)
-    hipLaunchKernelGGL(ext_many_kernel<true>, dim3(grid), dim3(NT), lds, s, f->k, desc, count,
-                       results);
+    hipLaunchKernelGGL((ext_many_kernel<true, false>), dim3(grid), dim3(NT), lds, s, f->k, desc,
+                       count, results);
+  else if (use_packed(f, xor_values))
+    hipLaunchKernelGGL((ext_many_kernel<false, true>), dim3(grid), dim3(NT), lds, s, f->k, desc,
+                       count, results);
   else
-    hipLaunchKernelGGL(ext_many_kernel<false>, dim3(grid), dim3(NT), lds, s, f->k, desc, count,
-                       results);
+    hipLaunchKernelGGL((ext_many_kernel<false, false>), dim3(grid), dim3(NT), lds, s, f->k, desc,
+                       count, results);
   return hipGetLastError() == hipSuccess ? FDOT_OK : FDOT_E_DEVICE;
 }
 
@@ -257,23 +339,28 @@ fdot_status_t fd_launch_ext_dot(const fdot_field_s* f, bool xor_values, const ui
   uint16_t* partial = (uint16_t*)w->acc;
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)ext_dot_kernel<false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-    (void)hipFuncSetAttribute((const void*)ext_dot_kernel<true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    set_lds_limit(ext_dot_kernel<false, false>);
+    set_lds_limit(ext_dot_kernel<true, false>);
+    set_lds_limit(ext_dot_kernel<false, true>);
     attr_set = true;
   }
   const uint32_t parts = n > 0 ? grid : 0u;
+  const int v = vec ? 1 : 0;
   if (xor_values) {
     if (n > 0)
-      hipLaunchKernelGGL(ext_dot_kernel<true>, dim3(grid), dim3(NT), lds, s, f->k, x, y, n,
-                         vec ? 1 : 0, partial);
+      hipLaunchKernelGGL((ext_dot_kernel<true, false>), dim3(grid), dim3(NT), lds, s, f->k, x, y,
+                         n, v, partial);
     hipLaunchKernelGGL(ext_sum_kernel<true>, dim3(1), dim3(NT), 0, s, f->k, partial, parts,
                        result);
   } else {
-    if (n > 0)
-      hipLaunchKernelGGL(ext_dot_kernel<false>, dim3(grid), dim3(NT), lds, s, f->k, x, y, n,
-                         vec ? 1 : 0, partial);
+    if (n > 0) {
+      if (use_packed(f, xor_values))
+        hipLaunchKernelGGL((ext_dot_kernel<false, true>), dim3(grid), dim3(NT), lds, s, f->k, x,
+                           y, n, v, partial);
+      else
+        hipLaunchKernelGGL((ext_dot_kernel<false, false>), dim3(grid), dim3(NT), lds, s, f->k, x,
+                           y, n, v, partial);
+    }
     hipLaunchKernelGGL(ext_sum_kernel<false>, dim3(1), dim3(NT), 0, s, f->k, partial, parts,
                        result);
   }
