@@ -483,6 +483,51 @@ def extras_gemm(fd):
     return out
 
 
+I8_TILES = {  # tune key gemm.i8.tile -> the int8 kernel and workgroup tiling it selects
+    8: "256x256, 8 waves of 128x64, direct-to-LDS loads, K-tiles of 128, 2 stages (default)",
+    9: "256x256, 4 waves of 128x128, direct-to-LDS loads, K-tiles of 128, 2 stages",
+    7: "256x256, 8 waves of 128x64, direct-to-LDS loads, K-tiles of 64, 4 stages",
+    6: "256x256, 4 waves of 128x128, direct-to-LDS loads, K-tiles of 64, 4 stages",
+    5: "256x128, 4 waves of 128x64, direct-to-LDS loads, K-tiles of 64, 3 stages",
+    3: "256x256, 4 waves of 128x128, register-staged, 2 LDS buffers",
+    4: "256x128, 4 waves of 128x64, register-staged, 2 LDS buffers",
+    2: "128x128, 4 waves of 64x64, register-staged, folds in the loop",
+}
+
+
+def extras_gemm_tiles(fd):
+    """The int8 product at p = 251, 8192 x 8192 times 8192 x 4096, once per
+    workgroup tiling of the int8 kernel (tune key gemm.i8.tile): the same
+    operands and result, so the kernels' counters can be compared."""
+    import synth
+    M, K, N = 8192, 8192, 4096
+    F = fd.Field(251, "centred")
+    A = torch.empty((M, K), dtype=torch.int8, device="cuda")
+    B = torch.empty((K, N), dtype=torch.int8, device="cuda")
+    synth.fill_device(A, 4, 0, 251, -125)
+    synth.fill_device(B, 4, 1, 251, -125)
+    C = torch.empty((M, N), dtype=torch.int8, device="cuda")
+    ref = None
+    out = {}
+    try:
+        for tile, what in I8_TILES.items():
+            fd.tune_set("gemm.i8.tile", tile)
+            F.gemm(A, B, out=C)
+            if ref is None:
+                ref = C.clone()
+            same = bool(torch.equal(C, ref))
+            t = time_events(lambda: F.gemm(A, B, out=C), 3)
+            out[str(tile)] = {"tiling": what, "ms": round(t * 1e3, 3),
+                              "TOPS": round(2.0 * M * N * K / t / 1e12, 1),
+                              "frac_of_peak": round(2.0 * M * N * K / t / 5e15, 4),
+                              "same_result_as_default": same}
+    finally:
+        fd.tune_set("gemm.i8.tile", None)
+    del A, B, C, ref
+    torch.cuda.empty_cache()
+    return out
+
+
 SERVED_PRIMES = {251: ("zpz", "centred"), 32749: ("zpz", "zpz"), 65521: ("zpz", "zpz"),
                  67108859: ("fp64", "fp64"), 2147483647: ("mont", "mont")}
 SERVED_DT = {"zpz": torch.uint32, "mont": torch.uint32, "fp64": torch.float64,
@@ -738,7 +783,8 @@ def extras_served(fd, n_req=10000):
 
 EXTRAS = {  # name -> function of the library module (plain_vs_batched also takes a batch)
     "plain_vs_batched": None, "single_dot": extras_single, "config3": extras_config3,
-    "fgemv": extras_gemv, "fgemm_config4": extras_gemm, "served_config5": extras_served,
+    "fgemv": extras_gemv, "fgemm_config4": extras_gemm, "fgemm_int8_tiles": extras_gemm_tiles,
+    "served_config5": extras_served,
     "prime_sweep": extras_prime_sweep, "elementwise": extras_elementwise,
     "ext_fields": extras_ext_fields,
 }
