@@ -157,6 +157,7 @@ fdot_status_t fd_fill_params(uint64_t p, fdot_rep_t rep, fdot_field_info_t* out)
     case FDOT_REP_CENTRED_I8:
       I.elem_bytes = 1;
       if (p < 3 || p > 255) return FDOT_E_BOUND;  // odd p, |a| <= 127
+      I.table_bytes = 256;                          // inverses, for division
       break;
     default: return FDOT_E_INVALID_ARG;
   }

@@ -188,3 +188,16 @@ def test_choose_rep_model_and_tuned_override():
         for k in ("auto.rep.b8", "auto.rep.b8.n6", "auto.rep.b17"):
             fd.tune_set(k, None)
     assert fd.choose_rep(251) == "centred"
+
+
+def test_table_bytes_per_representation():
+    """Device bytes of a field's tables: discrete logs hold the value, index
+    and plus-one tables (2 bytes per code each, Sec. 2.4) and, for q <= 32768,
+    the packed step's plus-one table (padded to 16 bytes); centred residues
+    hold 256 inverses; the other representations none."""
+    assert fd.field_params(65521, "zech")["table_bytes"] == 3 * 2 * 65521
+    assert fd.field_params(32749, "zech")["table_bytes"] == 3 * 2 * 32749 + 2 * 32752
+    assert fd.field_params(3, "zech")["table_bytes"] == 3 * 2 * 3 + 16
+    assert fd.field_params(251, "centred")["table_bytes"] == 256
+    for p, rep in ((65521, "zpz"), (2147483647, "mont"), (67108859, "fp64")):
+        assert fd.field_params(p, rep)["table_bytes"] == 0
