@@ -81,7 +81,7 @@ __device__ __forceinline__ void fd_table_to_lds(uint16_t* s, const uint16_t* g, 
 // table (FieldK::zpk, bytes, in LDS).
 __device__ __forceinline__ uint32_t zech_acc2(uint32_t v, uint32_t aw, uint32_t bw,
                                               const char* tb, const ZechPacked& C) {
-  uint32_t S, Sb, R, mn, m1, mp, D, Dq, K, Alo, Ahi, S1, S1q, Wm, hs, hz;
+  uint32_t S, Sb, R, mn, m1, mp, D, Dq, K, K2, S1, S1q, Wm, hs, hz;
   FD_PK("v_pk_add_u16", S, aw, bw);
   const uint32_t Sa = fd_pk_sub_sat(S, C.k1);
   FD_PKS("v_pk_sub_u16", Sb, S, C.q1);
@@ -92,13 +92,9 @@ __device__ __forceinline__ uint32_t zech_acc2(uint32_t v, uint32_t aw, uint32_t 
   FD_PK("v_pk_sub_u16", D, R, v);
   FD_PKS("v_pk_add_u16", Dq, D, C.qq);
   FD_PK("v_pk_min_u16", K, D, Dq);         // k in [0, q']
-  // LDS byte addresses of the two entries, base + 2k per half (one
-  // multiply-add each, the half chosen by op_sel)
-  typedef __attribute__((address_space(3))) const uint16_t lds_u16;
-  const uint32_t base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const char*)tb;
-  asm("v_mad_u32_u16 %0, %1, 2, %2" : "=v"(Alo) : "v"(K), "s"(base));
-  asm("v_mad_u32_u16 %0, %1, 2, %2 op_sel:[1,0,0,0]" : "=v"(Ahi) : "v"(K), "s"(base));
-  const uint32_t hw = (uint32_t)*(lds_u16*)(uintptr_t)Alo | ((uint32_t)*(lds_u16*)(uintptr_t)Ahi << 16);
+  FD_PK("v_pk_add_u16", K2, K, K);         // byte offsets of the two table entries
+  const uint32_t hw = (uint32_t)*(const uint16_t*)(tb + (K2 & 0xFFFFu)) |
+                      ((uint32_t)*(const uint16_t*)(tb + (K2 >> 16)) << 16);
   FD_PK("v_pk_add_u16", S1, v, hw);
   FD_PKS("v_pk_sub_u16", S1q, S1, C.qq);
   FD_PK("v_pk_min_u16", Wm, S1, S1q);      // running form of the sum
