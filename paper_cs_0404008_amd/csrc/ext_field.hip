@@ -56,22 +56,24 @@ struct Acc;
 
 template <>
 struct Acc<false> {
-  uint32_t z[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // one per 16-bit slot of a vector
+  // running forms (zech_acc1), one per 16-bit slot of a vector; the staged
+  // table's entry 0 is entry q' (see the kernels)
+  uint32_t z[8] = {~0u, ~0u, ~0u, ~0u, ~0u, ~0u, ~0u, ~0u};
   __device__ __forceinline__ void one(uint32_t a, uint32_t b, uint32_t qbar, const uint16_t* tab) {
-    z[0] = zadd(z[0], zmul(a, b, qbar), qbar, tab);
+    z[0] = zech_acc1(z[0], a, b, tab, qbar);
   }
   __device__ __forceinline__ void vec(const v4u& a, const v4u& b, uint32_t qbar,
                                       const uint16_t* tab, int) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      z[2 * j] = zadd(z[2 * j], zmul(a[j] & 0xFFFFu, b[j] & 0xFFFFu, qbar), qbar, tab);
-      z[2 * j + 1] = zadd(z[2 * j + 1], zmul(a[j] >> 16, b[j] >> 16, qbar), qbar, tab);
+      z[2 * j] = zech_acc1(z[2 * j], a[j] & 0xFFFFu, b[j] & 0xFFFFu, tab, qbar);
+      z[2 * j + 1] = zech_acc1(z[2 * j + 1], a[j] >> 16, b[j] >> 16, tab, qbar);
     }
   }
   __device__ __forceinline__ uint32_t total(uint32_t qbar, const uint16_t* tab) const {
     uint32_t acc = 0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc = zadd(acc, z[j], qbar, tab);
+    for (int j = 0; j < 8; ++j) acc = zadd(acc, z[j] + 1u, qbar, tab);  // codes
     return acc;
   }
 };
@@ -215,6 +217,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   extern __shared__ uint16_t s_tab[];
   __shared__ uint32_t s_part[NT / 64];
   fd_table_to_lds<NT>(s_tab, staged_table<XOR, PK>(F), (uint32_t)F.p);
+  if constexpr (!XOR && !PK) {
+    // the one-code step reads entry 0 for g^0 (zadd never reads it)
+    if (threadIdx.x == 0) s_tab[0] = s_tab[F.qbar];
+    __syncthreads();
+  }
   const uint16_t* ctab = PK ? F.zplus1 : s_tab;  // for combine
   const uint32_t qbar = F.qbar;
   const uint64_t tid = (uint64_t)blockIdx.x * NT + threadIdx.x;
@@ -257,6 +264,11 @@ __global__ __launch_bounds__(NT) void ext_many_kernel(const FieldK F, const fdot
   extern __shared__ uint16_t s_tab[];
   __shared__ uint32_t s_part[NT / 64];
   fd_table_to_lds<NT>(s_tab, staged_table<XOR, PK>(F), (uint32_t)F.p);
+  if constexpr (!XOR && !PK) {
+    // the one-code step reads entry 0 for g^0 (zadd never reads it)
+    if (threadIdx.x == 0) s_tab[0] = s_tab[F.qbar];
+    __syncthreads();
+  }
   const uint16_t* ctab = PK ? F.zplus1 : s_tab;  // for combine
   const uint32_t qbar = F.qbar;
   for (uint64_t k = blockIdx.x; k < count; k += gridDim.x) {

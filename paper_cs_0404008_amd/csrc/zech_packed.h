@@ -105,6 +105,26 @@ __device__ __forceinline__ uint32_t zech_acc2(uint32_t v, uint32_t aw, uint32_t 
   return (r2 & mp) | (v & ~mp);
 }
 
+// The same step on one code per 32-bit lane, for q <= 65536 (codes up to
+// 65535, so no two share a register): running form v = code - 1, the zero
+// element as 0xFFFFFFFF; tab is the plus-one table indexed by code with entry
+// 0 replaced by entry q' (both stand for g^0 here), a zero entry marking
+// 1 + g^k = 0.  Every index lies in [0, q'].
+__device__ __forceinline__ uint32_t zech_acc1(uint32_t v, uint32_t a, uint32_t b,
+                                              const uint16_t* tab, uint32_t qq) {
+  const uint32_t S = a + b;
+  const uint32_t Sa = __builtin_elementwise_sub_sat(S, 1u);
+  const uint32_t R = min(Sa, S - (qq + 1));     // product, running form
+  const uint32_t D = R - v;
+  const uint32_t K = min(D, D + qq);
+  const uint32_t h = tab[K];
+  const uint32_t S1 = v + h;
+  const uint32_t W = min(S1, S1 - qq);          // running form of the sum
+  const uint32_t r1 = h == 0 ? 0xFFFFFFFFu : W;
+  const uint32_t r2 = (int32_t)v < 0 ? R : r1;  // a zero running sum takes the product
+  return (a == 0 || b == 0) ? v : r2;           // a zero product changes nothing
+}
+
 // Stored code z + a b per 16-bit half (codes in, code out).
 __device__ __forceinline__ uint32_t zech_step2(uint32_t zw, uint32_t aw, uint32_t bw,
                                                const char* tb, const ZechPacked& C) {
