@@ -392,14 +392,19 @@ class Field:
 
     @staticmethod
     def make_desc(xs, ys, device=None) -> torch.Tensor:
-        """Device descriptor array {x, y, n} for a batch of tensor pairs."""
+        """Device descriptor array {x, y, n} for a batch of tensor pairs.  The
+        returned tensor keeps references to the operand tensors, so that their
+        memory outlives the descriptors that point into it."""
         rows = []
+        xs, ys = list(xs), list(ys)
         for x, y in zip(xs, ys):
             if x.numel() != y.numel():
                 raise ValueError("length mismatch")
             rows.append([x.data_ptr(), y.data_ptr(), x.numel()])
         dev = device or (xs[0].device if len(xs) else "cuda")
-        return torch.tensor(rows, dtype=torch.int64).reshape(-1, 3).to(dev)
+        desc = torch.tensor(rows, dtype=torch.int64).reshape(-1, 3).to(dev)
+        desc._fdot_operands = (xs, ys)
+        return desc
 
     def dot_many(self, desc: torch.Tensor, out: torch.Tensor | None = None, algo: str = "auto",
                  stream=None) -> torch.Tensor:

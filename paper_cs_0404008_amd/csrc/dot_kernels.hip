@@ -407,24 +407,16 @@ struct PZechTplus1 {
   static constexpr int U = 2;
   static constexpr bool kTable = true;
   static constexpr bool kPrefetch = true;
+  static constexpr bool kEntry0 = true;
+  // running forms of zech_acc1 (code - 1, zero as 0xFFFFFFFF)
   uint32_t z[8];
-  const uint16_t* tab;  // plus-one table in LDS
+  const uint16_t* tab;  // plus-one table in LDS, entry 0 = entry q'
   __device__ void init(const FieldK&) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) z[j] = 0;
-  }
-  __device__ uint32_t zadd(uint32_t u, uint32_t t, const FieldK& F) {
-    int k = (int)t - (int)u;
-    k += (k <= 0) ? (int)F.qbar : 0;  // in [0, q-1] always; [1, q-1] when u, t != 0
-    const uint32_t h = tab[k];
-    uint32_t w = u + h;
-    w = w > F.qbar ? w - F.qbar : w;
-    w = (h == 0u) ? 0u : w;
-    w = (u == 0u) ? t : w;
-    return (t == 0u) ? u : w;
+    for (int j = 0; j < 8; ++j) z[j] = 0xFFFFFFFFu;
   }
   __device__ void term(int j, uint32_t a, uint32_t b, const FieldK& F) {
-    z[j] = zadd(z[j], zech_mul(a, b, F.qbar), F);
+    z[j] = zech_acc1(z[j], a, b, tab, F.qbar);
   }
   __device__ void vec(const u32x4& a, const u32x4& b, const FieldK& F) {
     term(0, lo16(a.x), lo16(b.x), F); term(1, hi16(a.x), hi16(b.x), F);
@@ -436,7 +428,7 @@ struct PZechTplus1 {
   __device__ uint32_t finish(const FieldK& F) {
     uint32_t s = 0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) s += F.zval[z[j]];
+    for (int j = 0; j < 8; ++j) s += F.zval[z[j] + 1u];  // stored codes (0xFFFFFFFF -> 0)
     return mod_u64(s, F);
   }
   __device__ static void store(void* out, uint64_t k, uint32_t r, const FieldK& F) {
@@ -509,6 +501,12 @@ template <class Pol, class = void>
 struct PackedPlus1 { static constexpr bool value = false; };
 template <class P>
 struct PackedPlus1<P, decltype((void)P::kPackedPlus1)> { static constexpr bool value = P::kPackedPlus1; };
+
+// A policy whose staged plus-one table has entry q' copied to entry 0.
+template <class Pol, class = void>
+struct Entry0 { static constexpr bool value = false; };
+template <class P>
+struct Entry0<P, decltype((void)P::kEntry0)> { static constexpr bool value = P::kEntry0; };
 
 template <class Pol>
 __device__ __forceinline__ const uint16_t* table_source(const FieldK& F) {
@@ -735,6 +733,11 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
 template <class Pol, int NTH>
 __device__ __forceinline__ void load_table(const FieldK& F, uint16_t* s_tab) {
   fd_table_to_lds<NTH>(s_tab, table_source<Pol>(F), F.p32);
+  if constexpr (Entry0<Pol>::value) {
+    // the one-code step reads entry 0 for g^0, as entry q'
+    if (threadIdx.x == 0) s_tab[0] = s_tab[F.qbar];
+    __syncthreads();
+  }
 }
 
 // Adds a unit's residue to its pair's combination word.  The returned old
@@ -1160,7 +1163,7 @@ __global__ __launch_bounds__(256) void gemv_kernel(const FieldK F, const Job J, 
   extern __shared__ uint16_t s_tab[];
   constexpr bool kTab = HasTable<Pol>::value;
   if constexpr (kTab) {
-    fd_table_to_lds<256>(s_tab, table_source<Pol>(F), F.p32);
+    load_table<Pol, 256>(F, s_tab);
   }
   const uint64_t row = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= m) return;
@@ -1194,7 +1197,7 @@ __global__ __launch_bounds__(256) void gemv_rows_kernel(const FieldK F, const Jo
   extern __shared__ uint16_t s_tab[];
   constexpr bool kTab = HasTable<Pol>::value;
   if constexpr (kTab) {
-    fd_table_to_lds<256>(s_tab, table_source<Pol>(F), F.p32);
+    load_table<Pol, 256>(F, s_tab);
   }
   const uint64_t wv = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const uint64_t c = wv % P, q = wv / P;

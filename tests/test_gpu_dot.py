@@ -285,3 +285,47 @@ def test_single_form_spread_combination(spread):
     finally:
         for k, v in old.items():
             fd.tune_set(k, v)
+
+
+@pytest.mark.parametrize("p", [3, 5, 251, 32749, 65521])
+def test_one_code_plus_one_step(p):
+    """The plus-one schedule with one code per lane (the form every q above
+    32768 takes, and small q with tune key zech.packed = 0): single and
+    batched dot products, random and maximal codes, lengths with ragged
+    tails; and the matrix-vector product of a field created for the plus-one
+    schedule, which stages the same table."""
+    fd.tune_set("zech.packed", 0)
+    try:
+        F = fd.Field(p, "zech", algo="zech_tplus1")
+        for k, n in enumerate((1, 7, 4099, 3 * 16384 + 17, 300007)):
+            for pattern in ("random", "maxprod"):
+                x = stored(p, "zech", n, 120 + k, 0, pattern)
+                y = stored(p, "zech", n, 120 + k, 1, pattern)
+                got = to_host(F.dot(to_dev(x), to_dev(y)))[0]
+                assert same(got, oracle.dot(p, "zech", x, y)), (p, n, pattern)
+        xs = [stored(p, "zech", n, 130 + n, 0) for n in (0, 1, 63, 1000, 70001)]
+        ys = [stored(p, "zech", n, 130 + n, 1) for n in (0, 1, 63, 1000, 70001)]
+        xd, yd = [to_dev(v) for v in xs], [to_dev(v) for v in ys]
+        got = to_host(F.dot_many(fd.Field.make_desc(xd, yd)))
+        assert same(got, oracle.dot_many(p, "zech", xs, ys)), p
+        A = stored(p, "zech", 37 * 1003, 131, 0).reshape(37, 1003)
+        v = stored(p, "zech", 1003, 131, 1)
+        assert same(to_host(F.gemv(to_dev(A), to_dev(v))), oracle.gemv(p, "zech", A, v)), p
+    finally:
+        fd.tune_set("zech.packed", None)
+
+
+def test_make_desc_keeps_operands():
+    """A descriptor built from temporary tensors keeps them alive: the batch
+    (with empty pairs among short ones) still reads its operands after other
+    allocations that could have reused their memory."""
+    p, rep = 65521, "zpz"
+    F = field(p, rep)
+    lens = (3, 0, 1, 0, 0, 5, 64, 65)
+    xs = [stored(p, rep, n, 150 + k, 0) for k, n in enumerate(lens)]
+    ys = [stored(p, rep, n, 150 + k, 1) for k, n in enumerate(lens)]
+    desc = fd.Field.make_desc([to_dev(v) for v in xs], [to_dev(v) for v in ys])
+    filler = [torch.full((n + 1,), 7, dtype=torch.uint32, device="cuda") for n in lens]
+    got = to_host(F.dot_many(desc))
+    assert same(got, oracle.dot_many(p, rep, xs, ys))
+    del filler
