@@ -23,13 +23,15 @@
 // inverses from a 256-entry table built at field creation.  A zero divisor
 // gives the zero element.
 //
-// Discrete-log addition, subtraction and AXPY over fields of at most 32768
-// elements run two codes per packed 16-bit step (zech_packed.h).
+// Discrete-log addition, subtraction and AXPY are all z + a b (a = 1, a = -1,
+// a = alpha): over fields of at most 32768 elements two codes per packed
+// 16-bit step, above that one code per lane (zech_packed.h).
 //
 // Every lane handles 16 bytes of each operand (one vector load) when all
 // pointers are 16-byte aligned, else one element, with as many workgroups as
-// that takes.  The kernels are bound by HBM except division (ALU-bound: one
-// exponentiation, about 1.5 log2 p products, per vector of divisors).
+// that takes (the discrete-log sums: resident workgroups with the table in
+// LDS).  The kernels are bound by HBM except division for large primes
+// (ALU-bound: one exponentiation, about 1.5 log2 p products, per 16 divisors).
 #include <string.h>
 
 #include <algorithm>
@@ -107,14 +109,16 @@ struct RZech {
   static __device__ E neg(E a, const FieldK& F) {
     return a == 0 ? (E)0 : idx_add(a, (uint32_t)F.half, F);
   }
-  static __device__ E add(E a, E b, const FieldK& F) {
-    if (a == 0) return b;
-    if (b == 0) return a;
-    const E t = F.zplus1[idx_sub(b, a, F)];  // code of 1 + g^(j - i)
-    return t == 0 ? (E)0 : idx_add(a, t, F);
+  // z + a b by the one-code step of zech_packed.h (running form code - 1);
+  // F.zplus1 is the plus-one table staged in LDS with entry 0 = entry q'
+  static __device__ E fma(E z, E a, E b, const FieldK& F) {
+    return (E)(zech_acc1((uint32_t)z - 1u, a, b, F.zplus1, F.qbar) + 1u);
   }
-  static __device__ E sub(E a, E b, const FieldK& F) { return add(a, neg(b, F), F); }
-  static __device__ E axpy(E a, E x, E y, const FieldK& F) { return add(mul(a, x, F), y, F); }
+  static __device__ E add(E a, E b, const FieldK& F) { return fma(a, b, (E)F.qbar, F); }
+  static __device__ E sub(E a, E b, const FieldK& F) {
+    return fma(a, (E)(F.half ? (uint32_t)F.half : F.qbar), b, F);  // a + (-1) b
+  }
+  static __device__ E axpy(E a, E x, E y, const FieldK& F) { return fma(y, a, x, F); }
   static __device__ bool is_zero(E a) { return a == 0; }
 };
 
@@ -263,6 +267,8 @@ __global__ __launch_bounds__(NT) void ew_kernel(const FieldK Fin, uint64_t n,
   if constexpr (table_in_lds<R, OP>()) {
     extern __shared__ uint16_t s_plus1[];
     fd_table_to_lds<NT>(s_plus1, Fin.zplus1, (uint32_t)Fin.p);
+    if (threadIdx.x == 0) s_plus1[0] = s_plus1[Fin.qbar];  // g^0, for the one-code step
+    __syncthreads();
     F.zplus1 = s_plus1;
   }
   const uint64_t tid = (uint64_t)blockIdx.x * NT + threadIdx.x;

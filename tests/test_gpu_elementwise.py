@@ -173,12 +173,23 @@ def test_centred_division_exhaustive(p):
         assert same(got, want(p, "centred", "div", x, y, x, None)), (p, offset)
 
 
+@pytest.mark.parametrize("packed", [1, 0])
 @pytest.mark.parametrize("p", [3, 5, 7, 11, 257, 4099])
-def test_zech_sums_exhaustive(p):
+def test_zech_sums_exhaustive(p, packed):
     """Discrete-log sums, differences and AXPY over fields of at most 32768
-    elements (two codes per packed step): every pair of codes (0 = the zero
-    element, q - 1 = the unit), sampled pairs for q = 4099, with the
-    multipliers 0, 1, -1 and a generic one, aligned and misaligned."""
+    elements, on the packed step (two codes per instruction) and on the
+    one-code step every larger field uses (tune key zech.packed = 0): every
+    pair of codes (0 = the zero element, q - 1 = the unit), sampled pairs for
+    q = 4099, with the multipliers 0, 1, -1 and a generic one, aligned and
+    misaligned."""
+    fd.tune_set("zech.packed", packed)
+    try:
+        _zech_sums(p)
+    finally:
+        fd.tune_set("zech.packed", None)
+
+
+def _zech_sums(p):
     F = field(p, "zech")
     if p <= 257:
         c = np.arange(p, dtype=np.uint16)
