@@ -397,6 +397,66 @@ struct PZechExp {
   }
 };
 
+// The value table with two codes per register, for q <= 32768 (every code
+// fits 15 bits, a sum of two fits 16): the product's index (a + b) mod q' is
+// the minimum of s and s - q' in packed 16-bit arithmetic, in [0, q'], with
+// the staged table's entry 0 set to entry q' (the value 1 of g^0); a zero
+// factor is masked out of the loaded pair of values by a bit mask.  The
+// values still go into two 32-bit sums (low and high halves), folded as
+// PZechExp's.
+struct PZechExpP {
+  using E = uint16_t;
+  static constexpr int VW = 8;
+  static constexpr int U = 2;
+  static constexpr bool kTable = true;
+  static constexpr bool kPrefetch = true;
+  static constexpr bool kFolds = true;
+  static constexpr bool kEntry0 = true;
+  uint32_t s0, s1;
+  uint64_t tot;
+  const uint16_t* tab;  // value table in LDS, entry 0 = entry q'
+  ZechPacked C;
+  __device__ void init(const FieldK& F) {
+    s0 = s1 = 0;
+    tot = 0;
+    C = zech_packed_constants(F);
+  }
+  __device__ __forceinline__ void term2(uint32_t aw, uint32_t bw) {
+    uint32_t S, Sq, t, t2, mn, m1, mp;
+    FD_PK("v_pk_add_u16", S, aw, bw);
+    FD_PKS("v_pk_sub_u16", Sq, S, C.qq);
+    FD_PK("v_pk_min_u16", t, S, Sq);        // (a + b) mod q', in [0, q']
+    FD_PK("v_pk_add_u16", t2, t, t);        // byte offsets of the two values
+    FD_PK("v_pk_min_u16", mn, aw, bw);
+    FD_PKS("v_pk_min_u16", m1, mn, C.k1);
+    FD_PKNEG(mp, m1);                       // ones where the product is nonzero
+    const char* tb = (const char*)tab;
+    const uint32_t vw = ((uint32_t)*(const uint16_t*)(tb + (t2 & 0xFFFFu)) |
+                         ((uint32_t)*(const uint16_t*)(tb + (t2 >> 16)) << 16)) & mp;
+    s0 += vw & 0xFFFFu;
+    s1 += vw >> 16;
+  }
+  __device__ void vec(const u32x4& a, const u32x4& b, const FieldK&) {
+    term2(a.x, b.x);
+    term2(a.y, b.y);
+    term2(a.z, b.z);
+    term2(a.w, b.w);
+  }
+  __device__ void fold(const FieldK&) {
+    tot += (uint64_t)s0 + s1;
+    s0 = s1 = 0;
+  }
+  __device__ void one(E a, E b, const FieldK&, const Job&) {
+    term2(a, b);  // high halves: zero codes, masked
+    tot += (uint64_t)s0 + s1;
+    s0 = s1 = 0;
+  }
+  __device__ uint32_t finish(const FieldK& F) { return mod_u64(tot + s0 + s1, F); }
+  __device__ static void store(void* out, uint64_t k, uint32_t r, const FieldK& F) {
+    ((uint16_t*)out)[k] = F.zidx[r];
+  }
+};
+
 // Zech codes with Zech addition (Sec. 2.4): g^u + g^t = g^u (1 + g^(t-u)),
 // the exponent of 1 + g^k read from the plus-one table (in LDS), 0 when
 // 1 + g^k = 0.  Eight independent Zech accumulators per lane (one per
@@ -510,7 +570,8 @@ struct Entry0<P, decltype((void)P::kEntry0)> { static constexpr bool value = P::
 
 template <class Pol>
 __device__ __forceinline__ const uint16_t* table_source(const FieldK& F) {
-  if constexpr (std::is_same<Pol, PZechExp>::value) return F.zval;
+  if constexpr (std::is_same<Pol, PZechExp>::value || std::is_same<Pol, PZechExpP>::value)
+    return F.zval;
   if constexpr (PackedPlus1<Pol>::value) return F.zpk;
   return F.zplus1;
 }
@@ -1287,7 +1348,7 @@ __global__ void x_phase_copies_kernel(const E* x, uint64_t n, uint8_t* xbase, ui
 // ---------------------------------------------------------------- launching
 enum class Kind {
   ZpzDelayed, ZpzPerTerm, ZpzOverflow, ZpzHybrid, MontDelayed, MontPerTerm, MontOverflow,
-  MontHybrid, F64, ZechExp, ZechTplus1, ZechTplus1P, Centred
+  MontHybrid, F64, ZechExp, ZechExpP, ZechTplus1, ZechTplus1P, Centred
 };
 
 // Sec. 3.4, Eq. 2 (strict reading): largest lambda with lambda p (p-1) < 2^64.
@@ -1366,7 +1427,7 @@ static fdot_status_t make_plan_lambda(const fdot_field_s* f, fdot_algo_t algo, P
         return FDOT_OK;
       }
       if (algo != FDOT_ALGO_ZECH_EXP) return FDOT_E_UNSUPPORTED;
-      pl->kind = Kind::ZechExp;
+      pl->kind = I.p <= 32768 && fd_tune("zech.packed", 1) != 0 ? Kind::ZechExpP : Kind::ZechExp;
       // each 32-bit sum takes four values below p per vector
       pl->fold_vecs = clamp_vecs(0xFFFFFFFFull / (4 * (I.p - 1)));
       return FDOT_OK;
@@ -1391,7 +1452,8 @@ static fdot_status_t make_plan(const fdot_field_s* f, fdot_algo_t algo, Plan* pl
   uint64_t per = 2;
   switch (pl->kind) {
     case Kind::F64: per = 1; break;
-    case Kind::ZechExp: per = 4; break;
+    case Kind::ZechExp:
+    case Kind::ZechExpP: per = 4; break;
     case Kind::Centred: per = 16; break;
     default: break;
   }
@@ -1507,6 +1569,7 @@ static fdot_status_t dispatch(const Plan& pl, const Launch& A0) {
     case Kind::ZechExp: return launch_t<PZechExp, 1024>(A);
     case Kind::ZechTplus1: return launch_t<PZechTplus1, 1024>(A);
     case Kind::ZechTplus1P: return launch_t<PZechTplus1P, 1024>(A);
+    case Kind::ZechExpP: return launch_t<PZechExpP, 1024>(A);
     case Kind::Centred: return launch_t<PCentred, 256>(A);
   }
   return FDOT_E_UNSUPPORTED;
@@ -1770,6 +1833,7 @@ fdot_status_t fd_launch_gemv(const fdot_field_s* f, size_t m, size_t n, const vo
     case Kind::ZechExp: return launch_gemv_t<PZechExp>(f, J, m, n, A, lda, x, y, pl.lds, s);
     case Kind::ZechTplus1: return launch_gemv_t<PZechTplus1>(f, J, m, n, A, lda, x, y, pl.lds, s);
     case Kind::ZechTplus1P: return launch_gemv_t<PZechTplus1P>(f, J, m, n, A, lda, x, y, pl.lds, s);
+    case Kind::ZechExpP: return launch_gemv_t<PZechExpP>(f, J, m, n, A, lda, x, y, pl.lds, s);
     case Kind::Centred: return launch_gemv_t<PCentred>(f, J, m, n, A, lda, x, y, 0, s);
   }
   return FDOT_E_UNSUPPORTED;
