@@ -315,17 +315,30 @@ def test_one_code_plus_one_step(p):
         fd.tune_set("zech.packed", None)
 
 
-def test_make_desc_keeps_operands():
+@pytest.mark.parametrize("p,rep", [(65521, "zpz"), (2147483647, "mont"), (67108859, "fp64"),
+                                   (32749, "zech"), (65521, "zech"), (251, "centred")], ids=str)
+@pytest.mark.parametrize("fused", [None, 0])
+def test_make_desc_keeps_operands(p, rep, fused):
     """A descriptor built from temporary tensors keeps them alive: the batch
-    (with empty pairs among short ones) still reads its operands after other
-    allocations that could have reused their memory."""
-    p, rep = 65521, "zpz"
+    (with empty pairs among short ones, planned inside the batched kernel or
+    by a separate launch) still reads its operands after other allocations
+    that could have reused their memory."""
+    if fused is not None:
+        fd.tune_set(f"many.fused.{rep}", fused)
+    try:
+        _keeps_operands(p, rep)
+    finally:
+        if fused is not None:
+            fd.tune_set(f"many.fused.{rep}", None)
+
+
+def _keeps_operands(p, rep):
     F = field(p, rep)
     lens = (3, 0, 1, 0, 0, 5, 64, 65)
     xs = [stored(p, rep, n, 150 + k, 0) for k, n in enumerate(lens)]
     ys = [stored(p, rep, n, 150 + k, 1) for k, n in enumerate(lens)]
     desc = fd.Field.make_desc([to_dev(v) for v in xs], [to_dev(v) for v in ys])
-    filler = [torch.full((n + 1,), 7, dtype=torch.uint32, device="cuda") for n in lens]
+    filler = [torch.full((n + 1,), 7, dtype=torch.uint8, device="cuda") for n in lens]
     got = to_host(F.dot_many(desc))
     assert same(got, oracle.dot_many(p, rep, xs, ys))
     del filler
