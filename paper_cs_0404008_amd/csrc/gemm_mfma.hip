@@ -111,11 +111,14 @@ __device__ __forceinline__ void load_pair(const E* base, uint64_t off, bool in0,
 constexpr int FAP = FK + 1;    // A pitch in LDS (doubles): conflict-free column reads
 constexpr int FBP = FN + 2;    // B pitch in LDS (doubles): keeps 16-byte alignment
 constexpr size_t kF64Lds = (size_t)2 * (FM * FAP + FK * FBP) * sizeof(double);  // two buffers
+// With four wavefronts the register budget is held to two wavefronts per
+// SIMD (256 registers a lane), so that two workgroups share a CU; left to
+// itself the compiler takes about 340 and only one fits.
 template <typename E, bool CENTRE, bool VEC, bool SUBFOLD, int NW>
-__global__ __launch_bounds__(64 * NW) void gemm_f64_kernel(const FieldK F, int rep, uint32_t M,
-                                                       uint32_t N, uint32_t K, const E* A,
-                                                       uint64_t lda, const E* B, uint64_t ldb,
-                                                       void* C, uint64_t ldc, uint32_t fold_sub) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 4 ? 2 : 1)))
+void gemm_f64_kernel(const FieldK F, int rep, uint32_t M, uint32_t N, uint32_t K, const E* A,
+                     uint64_t lda, const E* B, uint64_t ldb, void* C, uint64_t ldc,
+                     uint32_t fold_sub) {
   extern __shared__ __attribute__((aligned(16))) double s_f64[];
   double* const As0 = s_f64;                   // [2][FM * FAP]
   double* const Bs0 = s_f64 + 2 * FM * FAP;    // [2][FK * FBP]
