@@ -15,11 +15,11 @@
 //     products by the nearest quotient in single precision (below).
 //
 // Division multiplies by the inverse.  For classical, Montgomery and double
-// residues the inverse is b^(p-2) (Fermat), by square-and-multiply with the
-// representation's own product: the same instruction stream for every lane,
+// residues the inverse is b^(p-2) (Fermat), by sliding-window powering with
+// the representation's own product: the same instruction stream for every lane,
 // where the extended Euclidean algorithm of Sec. 2.1 would branch per lane.
-// On the vector path one exponentiation serves all the divisors of a lane's
-// 16 bytes (simultaneous inversion).  Centred residues (p < 2^8) read their
+// On the vector path one exponentiation serves the divisors of 16 elements
+// per lane, 8 for doubles (simultaneous inversion).  Centred residues (p < 2^8) read their
 // inverses from a 256-entry table built at field creation.  A zero divisor
 // gives the zero element.
 //
@@ -31,7 +31,7 @@
 // pointers are 16-byte aligned, else one element, with as many workgroups as
 // that takes (the discrete-log sums: resident workgroups with the table in
 // LDS).  The kernels are bound by HBM except division for large primes
-// (ALU-bound: one exponentiation, about 1.5 log2 p products, per 16 divisors).
+// (ALU-bound: one exponentiation, about 1.3 log2 p products, per 16 divisors).
 #include <string.h>
 
 #include <algorithm>
@@ -179,15 +179,37 @@ constexpr bool table_in_lds() {
          (OP == FDOT_EW_ADD || OP == FDOT_EW_SUB || OP == FDOT_EW_AXPY);
 }
 
-// b^(p-2) by square-and-multiply from the top bit of p-2.
+// b^(p-2), left to right over the bits of p-2 with windows of up to three
+// bits that end in a one (sliding windows): each window is one product by
+// b, b^3, b^5 or b^7 (computed first, four products), after one squaring per
+// bit.  For p = 2^31-1 that is 30 squarings and 14 products, against 30 and
+// 30 bit by bit.  The exponent is the field's, the same for every lane, so
+// the loop and its branches are uniform.
 template <class R>
 __device__ typename R::E inverse(typename R::E b, const FieldK& F) {
   using E = typename R::E;
   const uint64_t e = F.p - 2;
-  E r = R::one(F);
-  for (int bit = 63 - __builtin_clzll(e | 1); bit >= 0; --bit) {
-    r = R::mul(r, r, F);
-    if ((e >> bit) & 1) r = R::mul(r, b, F);
+  if (e == 0) return R::one(F);  // p = 2: the only nonzero element is its own inverse
+  const E b2 = R::mul(b, b, F);
+  const E b3 = R::mul(b, b2, F), b5 = R::mul(b3, b2, F), b7 = R::mul(b5, b2, F);
+  auto odd_power = [&](uint32_t w) { return w == 1 ? b : w == 3 ? b3 : w == 5 ? b5 : b7; };
+  int bit = 63 - __builtin_clzll(e);
+  // the top window starts the result without squarings
+  int lo = bit >= 2 ? bit - 2 : 0;
+  while (!((e >> lo) & 1)) ++lo;
+  E r = odd_power((uint32_t)(e >> lo) & ((2u << (bit - lo)) - 1));
+  bit = lo - 1;
+  while (bit >= 0) {
+    if (!((e >> bit) & 1)) {
+      r = R::mul(r, r, F);
+      --bit;
+      continue;
+    }
+    lo = bit >= 2 ? bit - 2 : 0;
+    while (!((e >> lo) & 1)) ++lo;
+    for (int i = lo; i <= bit; ++i) r = R::mul(r, r, F);
+    r = R::mul(r, odd_power((uint32_t)(e >> lo) & ((2u << (bit - lo)) - 1)), F);
+    bit = lo - 1;
   }
   return r;
 }
@@ -456,10 +478,16 @@ fdot_status_t launch_op(const fdot_field_s* f, uint64_t n, const void* alpha, co
   const bool vec = (bits & 15u) == 0;
   if constexpr (OP == FDOT_EW_DIV && !std::is_same<R, RZech>::value &&
                 !std::is_same<R, RCentred>::value) {
-    // NE = 16 elements per exponentiation (tune key ew.div_elems: 16 or 32)
-    if (vec)
-      return fd_tune("ew.div_elems", 16) == 32 ? launch_div<R, 32>(f, n, x, y, r, s)
-                                                : launch_div<R, 16>(f, n, x, y, r, s);
+    // NE elements per exponentiation (tune key ew.div_elems: 8, 16 or 32):
+    // 8 for doubles (fewer registers, more resident waves: 0.70 -> 0.76 of
+    // HBM at p = 2^26-5), 16 for the 32-bit forms (8 measured 0.70 against
+    // 0.74 classical and 0.52 against 0.69 Montgomery)
+    if (vec) {
+      const int64_t ne = fd_tune("ew.div_elems", std::is_same<R, RF64>::value ? 8 : 16);
+      return ne == 32  ? launch_div<R, 32>(f, n, x, y, r, s)
+             : ne == 8 ? launch_div<R, 8>(f, n, x, y, r, s)
+                       : launch_div<R, 16>(f, n, x, y, r, s);
+    }
   }
   const uint64_t per = vec ? 16 / sizeof(E) : 1;
   const uint64_t work = (n + per - 1) / per;

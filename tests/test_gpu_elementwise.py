@@ -213,9 +213,9 @@ def _zech_sums(p):
 
 @pytest.mark.parametrize("p,rep", [(32749, "zpz"), (4294967291, "zpz"), (2147483647, "mont"),
                                    (67108859, "fp64"), (2, "fp64")], ids=str)
-@pytest.mark.parametrize("elems", [16, 32])
+@pytest.mark.parametrize("elems", [8, 16, 32])
 def test_division_batched_inversion(p, rep, elems):
-    """The aligned division kernel inverts the divisors of 16 or 32 elements
+    """The aligned division kernel inverts the divisors of 8, 16 or 32 elements
     per lane (whole vectors a workgroup's width apart) with one
     exponentiation: about one divisor in ten zero, lengths that leave a
     partial last workgroup, partial vectors and a ragged tail, in place."""
