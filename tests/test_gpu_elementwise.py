@@ -173,6 +173,23 @@ def test_centred_division_exhaustive(p):
         assert same(got, want(p, "centred", "div", x, y, x, None)), (p, offset)
 
 
+@pytest.mark.parametrize("rep", ["zpz", "mont", "fp64"])
+def test_powered_division_exhaustive(rep):
+    """The Fermat inverse b^(p-2) by sliding windows: every quotient x / y over
+    all pairs of residues for small primes whose exponents p - 2 take every
+    window shape (1, 11, 101, 1001, 1011, 1111, ... up to 255), on the vector
+    path (one exponentiation per lane's batch of divisors) and the
+    misaligned one (one exponentiation per element)."""
+    for p in (3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 61, 67, 127, 131, 251, 257):
+        F = field(p, rep)
+        vals = oracle.encode(p, rep, np.arange(p, dtype=np.int64))
+        x = np.repeat(vals, p)
+        y = np.tile(vals, p)
+        for offset in (0, 3):
+            got = run(F, "div", x, y, x, None, offset=offset)
+            assert same(got, want(p, rep, "div", x, y, x, None)), (p, rep, offset)
+
+
 @pytest.mark.parametrize("packed", [1, 0])
 @pytest.mark.parametrize("p", [3, 5, 7, 11, 257, 4099])
 def test_zech_sums_exhaustive(p, packed):
