@@ -479,10 +479,11 @@ struct PZechTplus1 {
     z[j] = zech_acc1(z[j], a, b, tab, F.qbar);
   }
   __device__ void vec(const u32x4& a, const u32x4& b, const FieldK& F) {
-    term(0, lo16(a.x), lo16(b.x), F); term(1, hi16(a.x), hi16(b.x), F);
-    term(2, lo16(a.y), lo16(b.y), F); term(3, hi16(a.y), hi16(b.y), F);
-    term(4, lo16(a.z), lo16(b.z), F); term(5, hi16(a.z), hi16(b.z), F);
-    term(6, lo16(a.w), lo16(b.w), F); term(7, hi16(a.w), hi16(b.w), F);
+    const uint32_t ca[8] = {lo16(a.x), hi16(a.x), lo16(a.y), hi16(a.y),
+                            lo16(a.z), hi16(a.z), lo16(a.w), hi16(a.w)};
+    const uint32_t cb[8] = {lo16(b.x), hi16(b.x), lo16(b.y), hi16(b.y),
+                            lo16(b.z), hi16(b.z), lo16(b.w), hi16(b.w)};
+    zech_acc1_x8(z, ca, cb, tab, F.qbar);  // the eight table reads overlap
   }
   __device__ void one(E a, E b, const FieldK& F, const Job&) { term(0, a, b, F); }
   __device__ uint32_t finish(const FieldK& F) {

@@ -64,11 +64,15 @@ struct Acc<false> {
   }
   __device__ __forceinline__ void vec(const v4u& a, const v4u& b, uint32_t qbar,
                                       const uint16_t* tab, int) {
+    uint32_t ca[8], cb[8];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      z[2 * j] = zech_acc1(z[2 * j], a[j] & 0xFFFFu, b[j] & 0xFFFFu, tab, qbar);
-      z[2 * j + 1] = zech_acc1(z[2 * j + 1], a[j] >> 16, b[j] >> 16, tab, qbar);
+      ca[2 * j] = a[j] & 0xFFFFu;
+      ca[2 * j + 1] = a[j] >> 16;
+      cb[2 * j] = b[j] & 0xFFFFu;
+      cb[2 * j + 1] = b[j] >> 16;
     }
+    zech_acc1_x8(z, ca, cb, tab, qbar);
   }
   __device__ __forceinline__ uint32_t total(uint32_t qbar, const uint16_t* tab) const {
     uint32_t acc = 0;

@@ -125,6 +125,36 @@ __device__ __forceinline__ uint32_t zech_acc1(uint32_t v, uint32_t a, uint32_t b
   return (a == 0 || b == 0) ? v : r2;           // a zero product changes nothing
 }
 
+// Eight independent running forms v[j] + a[j] b[j] of zech_acc1 at once: the
+// eight table indices first, then the eight table reads back to back, then
+// the eight sums, so that the reads' latencies overlap instead of each sum
+// waiting for its own read (the compiler otherwise keeps every step whole).
+__device__ __forceinline__ void zech_acc1_x8(uint32_t (&v)[8], const uint32_t (&a)[8],
+                                             const uint32_t (&b)[8], const uint16_t* tab,
+                                             uint32_t qq) {
+  uint32_t R[8], K[8], m[8], h[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const uint32_t S = a[j] + b[j];
+    R[j] = min(__builtin_elementwise_sub_sat(S, 1u), S - (qq + 1));
+    const uint32_t D = R[j] - v[j];
+    K[j] = min(D, D + qq);
+    m[j] = min(a[j], b[j]);  // 0 for a zero product
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) h[j] = tab[K[j]];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const uint32_t S1 = v[j] + h[j];
+    const uint32_t W = min(S1, S1 - qq);
+    const uint32_t r1 = h[j] == 0 ? 0xFFFFFFFFu : W;
+    const uint32_t r2 = (int32_t)v[j] < 0 ? R[j] : r1;
+    v[j] = m[j] == 0 ? v[j] : r2;
+  }
+}
+
 // Stored code z + a b per 16-bit half (codes in, code out).
 __device__ __forceinline__ uint32_t zech_step2(uint32_t zw, uint32_t aw, uint32_t bw,
                                                const char* tb, const ZechPacked& C) {
