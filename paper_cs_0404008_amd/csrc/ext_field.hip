@@ -90,11 +90,20 @@ struct Acc<true> {
   }
   __device__ __forceinline__ void vec(const v4u& a, const v4u& b, uint32_t qbar,
                                       const uint16_t* tab, int) {
+    // the eight products' codes, then their eight value reads back to back
+    // (so that the reads overlap), then the exclusive ors
+    uint32_t k[8], h[8];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      v0 ^= tab[zmul(a[j] & 0xFFFFu, b[j] & 0xFFFFu, qbar)];
-      v1 ^= tab[zmul(a[j] >> 16, b[j] >> 16, qbar)];
+      k[2 * j] = zmul(a[j] & 0xFFFFu, b[j] & 0xFFFFu, qbar);
+      k[2 * j + 1] = zmul(a[j] >> 16, b[j] >> 16, qbar);
     }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) h[j] = tab[k[j]];
+    __builtin_amdgcn_sched_barrier(0);
+    v0 ^= (h[0] ^ h[2]) ^ (h[4] ^ h[6]);
+    v1 ^= (h[1] ^ h[3]) ^ (h[5] ^ h[7]);
   }
   __device__ __forceinline__ uint32_t total(uint32_t, const uint16_t*) const { return v0 ^ v1; }
 };
