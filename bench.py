@@ -826,7 +826,7 @@ def main():
         print(json.dumps({"copy_bytes": x.numel() * 4, "copies": 3}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import paper_cs_0404008_amd as fd
