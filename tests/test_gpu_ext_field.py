@@ -152,6 +152,34 @@ def test_ext_batched_dot_matches_oracle(p, d):
             assert int(got[k]) == want[k], (p, d, k, ns[k], algo)
 
 
+@pytest.mark.parametrize("p,d", [(2, 2), (3, 2), (2, 8), (7, 5)], ids=str)
+def test_ext_one_code_step_small_fields(p, d):
+    """The one-code plus-one step (eight table reads of a vector grouped; the
+    form every field above 32768 elements takes) forced on small fields
+    (tune key zech.packed = 0), where running sums, products and sums of the
+    form 1 + g^k = 0 are frequent: single and batched dot products against
+    the oracle."""
+    q = p ** d
+    fd.tune_set("zech.packed", 0)
+    try:
+        F = fd.Field(p, "zech", degree=d)
+        for n in (8, 9, 1000, 100003):
+            x = codes(q, n, 68 + n % 7, 0)
+            y = codes(q, n, 68 + n % 7, 1)
+            x[::5] = 0                      # zero products
+            got = to_host(F.dot(to_dev(x), to_dev(y), algo="zech_tplus1"))[0]
+            assert int(got) == oracle.ext_dot(p, d, x, y), (p, d, n)
+        ns = [0, 1, 9, 4096, 20001]
+        hx = [codes(q, n, 69, 2 * k) for k, n in enumerate(ns)]
+        hy = [codes(q, n, 69, 2 * k + 1) for k, n in enumerate(ns)]
+        got = to_host(F.dot_many(fd.Field.make_desc([to_dev(v) for v in hx],
+                                                    [to_dev(v) for v in hy]), algo="zech_tplus1"))
+        for k in range(len(ns)):
+            assert int(got[k]) == oracle.ext_dot(p, d, hx[k], hy[k]), (p, d, k)
+    finally:
+        fd.tune_set("zech.packed", None)
+
+
 def test_ext_unsupported_forms():
     F = field(3, 2)
     x = torch.zeros(16, dtype=torch.uint16, device="cuda")
