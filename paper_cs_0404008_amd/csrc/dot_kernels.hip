@@ -1124,31 +1124,49 @@ __global__ __launch_bounds__(PLAN_NT) void plan_kernel(const fdot_desc_t* desc, 
                                                        uint64_t* first, uint32_t* units,
                                                        uint32_t* start, uint64_t* tq,
                                                        void* results, uint32_t elem_bytes) {
-  __shared__ uint64_t s[PLAN_NT];
-  const uint32_t t = threadIdx.x;
+  constexpr int kWaves = PLAN_NT / 64;
+  constexpr int kRegs = 8;  // pairs per thread whose lengths stay in registers
+  __shared__ uint64_t s_wave[kWaves];
+  const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
   const uint64_t seg = (count + PLAN_NT - 1) / PLAN_NT;
   const uint64_t b = t * seg < count ? t * seg : count;
   const uint64_t e = b + seg < count ? b + seg : count;
+  const bool in_regs = seg <= (uint64_t)kRegs;
+  uint64_t pn[kRegs];
   uint64_t local = 0;
-  for (uint64_t k = b; k < e; ++k) local += pad64(load_s(&desc[k].n));
-  s[t] = local;
-  __syncthreads();
-  for (uint32_t o = 1; o < PLAN_NT; o <<= 1) {  // inclusive scan
-    const uint64_t v = t >= o ? s[t - o] : 0;
-    __syncthreads();
-    s[t] += v;
-    __syncthreads();
+  if (in_regs) {
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) {  // independent loads, all in flight together
+      pn[j] = b + j < e ? pad64(load_s(&desc[b + j].n)) : 0;
+      local += pn[j];
+    }
+  } else {
+    for (uint64_t k = b; k < e; ++k) local += pad64(load_s(&desc[k].n));
   }
-  const uint64_t T = s[PLAN_NT - 1];
+  // inclusive scan of the segment totals: within each wavefront by shuffles,
+  // then the wavefront totals through LDS (one barrier)
+  unsigned long long incl = local;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long v = __shfl_up(incl, (unsigned)o, 64);
+    if (lane >= (uint32_t)o) incl += v;
+  }
+  if (lane == 63) s_wave[w] = incl;
+  __syncthreads();
+  uint64_t T = 0, before = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    const uint64_t v = s_wave[i];
+    before += (uint32_t)i < w ? v : 0;
+    T += v;
+  }
   uint64_t Q, R;
   batch_ranges(T, groups, q_target, max_ranges, &Q, &R);
-  uint64_t run = s[t] - local;
-  for (uint64_t k = b; k < e; ++k) {
-    const uint64_t n = load_s(&desc[k].n);
-    const uint64_t pn = pad64(n);
+  uint64_t run = before + incl - local;
+  auto place = [&](uint64_t k, uint64_t n_pad) {
     first[k] = run;
-    if (pn) {
-      const uint64_t r0 = run / Q, r1 = (run + pn - 1) / Q;
+    if (n_pad) {
+      const uint64_t r0 = run / Q, r1 = (run + n_pad - 1) / Q;
       units[k] = (uint32_t)((r1 - r0 + 1) * S);
       for (uint64_t r = (run + Q - 1) / Q; r <= r1; ++r) start[r] = (uint32_t)k;
     } else {
@@ -1156,7 +1174,14 @@ __global__ __launch_bounds__(PLAN_NT) void plan_kernel(const fdot_desc_t* desc, 
       uint8_t* res = (uint8_t*)results + k * elem_bytes;
       for (uint32_t i = 0; i < elem_bytes; ++i) res[i] = 0;
     }
-    run += pn;
+    run += n_pad;
+  };
+  if (in_regs) {
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j)
+      if (b + j < e) place(b + j, pn[j]);
+  } else {
+    for (uint64_t k = b; k < e; ++k) place(k, pad64(load_s(&desc[k].n)));
   }
   if (t == 0) {
     tq[0] = T;
