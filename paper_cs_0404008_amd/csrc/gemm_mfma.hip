@@ -106,7 +106,8 @@ __device__ __forceinline__ void load_pair(const E* base, uint64_t off, bool in0,
 // 64*(w%2).. as 4 x 4 blocks of 16 x 16.  K is staged through two LDS
 // buffers 16 at a time (A row-major with a padded pitch, B as stored),
 // consumed in 4 steps of one MFMA K (4); the next K-tile is fetched into
-// registers while the current one is multiplied.  The accumulators are folded after every fold_sub MFMA
+// registers while the current one is multiplied and staged into LDS halfway
+// through it.  The accumulators are folded after every fold_sub MFMA
 // steps (SUBFOLD, for block lengths below one K-tile) or K-tiles.
 constexpr int FAP = FK + 1;    // A pitch in LDS (doubles): conflict-free column reads
 constexpr int FBP = FN + 2;    // B pitch in LDS (doubles): keeps 16-byte alignment
@@ -240,8 +241,12 @@ void gemm_f64_kernel(const FieldK F, int rep, uint32_t M, uint32_t N, uint32_t K
         fold_all();
         sub = 0;
       }
+      // The next K-tile goes into the other buffer halfway through this
+      // one's products (nobody reads that buffer since the last barrier),
+      // so its waits and LDS writes overlap the remaining matrix products
+      // instead of sitting between the last product and the barrier.
+      if (s == 1 && k0 + FK < K) stage(buf ^ 1);
     }
-    if (k0 + FK < K) stage(buf ^ 1);
     __syncthreads();  // the other buffer is complete; nobody reads this one any more
     if (k0 + 2 * FK < K) fetch(k0 + 2 * FK);
     // Without SUBFOLD, fold_sub counts whole K-tiles.
