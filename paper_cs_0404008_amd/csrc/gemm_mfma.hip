@@ -360,8 +360,13 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(const FieldK F, uint32_t M
                                                       uint32_t* Cu = nullptr, uint64_t wgt = 0) {
   constexpr int TM = 64 * BI, TN = 64 * BJ;
   constexpr int NA = TM * IK / 16 / 256, NB = TN * IK / 16 / 256;  // 16-byte vectors per thread
-  __shared__ __attribute__((aligned(16))) int8_t As[TM][IK + IPAD];
-  __shared__ __attribute__((aligned(16))) int8_t Bs[TN][IK + IPAD];
+  // Two LDS buffers where both fit in 64 KiB: the next K-tile is written to
+  // the other buffer halfway through this one's products, one barrier per
+  // K-tile.  Otherwise one buffer, written between two barriers.
+  constexpr bool DB = 2 * (TM + TN) * (IK + IPAD) <= 65536;
+  constexpr int NBUF = DB ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) int8_t As[NBUF][TM][IK + IPAD];
+  __shared__ __attribute__((aligned(16))) int8_t Bs[NBUF][TN][IK + IPAD];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
   const uint32_t tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
   uint32_t tm, tn;
@@ -398,35 +403,53 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(const FieldK F, uint32_t M
     for (int j = 0; j < BJ; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
-  uint32_t steps = 0;
-  if (K > 0) fetch(0);
-  for (uint32_t k0 = 0; k0 < K; k0 += IK) {
-    __syncthreads();
+  auto stage = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       const uint32_t e = tid + 256u * q;
-      *(v4i*)&As[e / (IK / 16)][(e % (IK / 16)) * 16] = pa[q];
+      *(v4i*)&As[buf][e / (IK / 16)][(e % (IK / 16)) * 16] = pa[q];
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const uint32_t e = tid + 256u * q;
-      *(v4i*)&Bs[e / (IK / 16)][(e % (IK / 16)) * 16] = pb[q];
+      *(v4i*)&Bs[buf][e / (IK / 16)][(e % (IK / 16)) * 16] = pb[q];
     }
+  };
+  uint32_t steps = 0;
+  if (K > 0) fetch(0);
+  if (DB && K > 0) {
+    stage(0);
     __syncthreads();
-    if (k0 + IK < K) fetch(k0 + IK);
+    if (IK < K) fetch(IK);
+  }
+  uint32_t t = 0;
+  for (uint32_t k0 = 0; k0 < K; k0 += IK, ++t) {
+    const int buf = DB ? (int)(t & 1) : 0;
+    if (!DB) {
+      __syncthreads();
+      stage(0);
+      __syncthreads();
+      if (k0 + IK < K) fetch(k0 + IK);
+    }
 #pragma unroll
     for (int s = 0; s < IK / 32; ++s) {
       const uint32_t kc = 32 * s + 16 * (lane / 32);
       v4i a[BI], b[BJ];
 #pragma unroll
-      for (int i = 0; i < BI; ++i) a[i] = *(const v4i*)&As[wm + 32 * i + lane % 32][kc];
+      for (int i = 0; i < BI; ++i) a[i] = *(const v4i*)&As[buf][wm + 32 * i + lane % 32][kc];
 #pragma unroll
-      for (int j = 0; j < BJ; ++j) b[j] = *(const v4i*)&Bs[wn + 32 * j + lane % 32][kc];
+      for (int j = 0; j < BJ; ++j) b[j] = *(const v4i*)&Bs[buf][wn + 32 * j + lane % 32][kc];
 #pragma unroll
       for (int i = 0; i < BI; ++i)
 #pragma unroll
         for (int j = 0; j < BJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+      // the other buffer has had no reader since the last barrier
+      if (DB && s == IK / 64 && k0 + IK < K) stage(buf ^ 1);
+    }
+    if (DB) {
+      __syncthreads();  // the other buffer is complete; nobody reads this one any more
+      if (k0 + 2 * IK < K) fetch(k0 + 2 * IK);
     }
     if (++steps == fold_steps) {
 #pragma unroll

@@ -228,6 +228,37 @@ def test_gemm_int8_tile_variants(shape):
         fd.tune_set("gemm.i8.tile", None)
 
 
+@pytest.mark.parametrize("shape", [1, 2])
+def test_gemm_int8_double_buffered_ktile64(shape):
+    """The register-staged int8 tilings with K-tiles of 64, where two LDS
+    buffers fit (the next K-tile written halfway through the current one's
+    products): ragged shapes, K not a multiple of the tile, and K beyond one
+    fold block with maximal products, against the oracle."""
+    p, rep = 251, "centred"
+    F = field(p, rep)
+    fd.tune_set("gemm.i8.tile", shape)
+    fd.tune_set("gemm.i8.ktile", 64)
+    try:
+        for (M, N, K) in [(1100, 1030, 1024), (300, 257, 1001), (64, 64, 64), (70, 33, 65)]:
+            A = mat(p, rep, M, K, 72, 0, "random")
+            B = mat(p, rep, K, N, 72, 1, "random")
+            got = to_host(F.gemm(to_dev(A), to_dev(B)))
+            rows = synth.uniform_int(73, 0, 512, M)
+            cols = synth.uniform_int(73, 1, 512, N)
+            rows[:2] = [0, M - 1]
+            cols[:2] = [0, N - 1]
+            assert same(got[rows, cols], oracle.gemm_entries(p, rep, A, B, rows, cols)), (shape, M, N, K)
+        M, N, K = 40, 36, (1 << 18) + 3
+        for pattern in ("random", "maxprod"):
+            A = mat(p, rep, M, K, 74, 0, pattern)
+            B = mat(p, rep, K, N, 74, 1, pattern)
+            got = to_host(F.gemm(to_dev(A), to_dev(B)))
+            assert same(got, oracle.gemm(p, rep, A, B)), (shape, K, pattern)
+    finally:
+        fd.tune_set("gemm.i8.tile", None)
+        fd.tune_set("gemm.i8.ktile", None)
+
+
 @pytest.mark.parametrize("pad", [1, 0])
 def test_gemm_int8_zero_padded_operands(pad):
     """K not a multiple of 64 and A rows at an odd stride (a column slice of a
