@@ -311,7 +311,9 @@ __device__ __forceinline__ uint32_t mulmod_pre(uint32_t x, uint64_t wgt, const F
 }
 
 // Digit-product epilogue for one 32-row block of a wavefront's tile:
-// Cu = (Cu + acc * w) mod p for its 32 x 32*BJ entries.  A negative acc is
+// Cu = (Cu + acc * w) mod p for its 32 x 32*BJ entries, or Cu = acc * w mod
+// p for the first product of a sum (fresh: Cu is not read, so it needs no
+// clearing beforehand).  A negative acc is
 // first lifted by pm, the least multiple of p that is at least 2^31, so that
 // the multiplier sees a value in [0, 2^32).  The products replace the
 // accumulators in place; then every load of Cu is issued before the first
@@ -320,7 +322,7 @@ template <int BJ>
 __device__ __forceinline__ void split_rows(uint32_t* Cu, uint64_t ldc, uint64_t wgt, v16i* acc,
                                            uint32_t row0, uint32_t col0, uint32_t lane,
                                            uint32_t M, uint32_t N, uint64_t pm,
-                                           const FieldK& F) {
+                                           const FieldK& F, uint32_t fresh) {
 #pragma unroll
   for (int j = 0; j < BJ; ++j)
 #pragma unroll
@@ -328,17 +330,19 @@ __device__ __forceinline__ void split_rows(uint32_t* Cu, uint64_t ldc, uint64_t 
       const int64_t a = acc[j][r];
       acc[j][r] = (int32_t)mulmod_pre((uint32_t)(a < 0 ? a + (int64_t)pm : a), wgt, F);
     }
-  uint32_t old[BJ][16];
+  uint32_t old[BJ][16] = {};
+  if (!fresh) {
 #pragma unroll
-  for (int j = 0; j < BJ; ++j)
+    for (int j = 0; j < BJ; ++j)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const uint32_t gm = row0 + 8 * (r / 4) + 4 * (lane / 32) + r % 4;
-      const uint32_t gn = col0 + 32 * j + lane % 32;
-      // clamped (always valid) addresses keep the loads unconditional, so
-      // they are all in flight together; entries outside C are not stored
-      old[j][r] = Cu[(uint64_t)min(gm, M - 1) * ldc + min(gn, N - 1)];
-    }
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t gm = row0 + 8 * (r / 4) + 4 * (lane / 32) + r % 4;
+        const uint32_t gn = col0 + 32 * j + lane % 32;
+        // clamped (always valid) addresses keep the loads unconditional, so
+        // they are all in flight together; entries outside C are not stored
+        old[j][r] = Cu[(uint64_t)min(gm, M - 1) * ldc + min(gn, N - 1)];
+      }
+  }
 #pragma unroll
   for (int j = 0; j < BJ; ++j)
 #pragma unroll
@@ -357,7 +361,8 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(const FieldK F, uint32_t M
                                                       uint32_t K, const int8_t* A, uint64_t lda,
                                                       const int8_t* Bt, uint64_t ldbt, int8_t* C,
                                                       uint64_t ldc, uint32_t fold_steps,
-                                                      uint32_t* Cu = nullptr, uint64_t wgt = 0) {
+                                                      uint32_t* Cu = nullptr, uint64_t wgt = 0,
+                        uint32_t fresh = 0) {
   constexpr int TM = 64 * BI, TN = 64 * BJ;
   constexpr int NA = TM * IK / 16 / 256, NB = TN * IK / 16 / 256;  // 16-byte vectors per thread
   // Two LDS buffers where both fit in 64 KiB: the next K-tile is written to
@@ -465,7 +470,8 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(const FieldK F, uint32_t M
     const uint64_t pm = (0x80000000ull + F.p - 1) / F.p * F.p;
 #pragma unroll
     for (int i = 0; i < BI; ++i)
-      split_rows<BJ>(Cu, ldc, wgt, acc[i], m0 + wm + 32 * i, n0 + wn, lane, M, N, pm, F);
+      split_rows<BJ>(Cu, ldc, wgt, acc[i], m0 + wm + 32 * i, n0 + wn, lane, M, N, pm, F,
+                     fresh);
     return;
   }
 #pragma unroll
@@ -666,7 +672,8 @@ template <int BJ, int NS, int NW, bool SPLIT = false, int IKT = 64>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(BJ == 4 ? 1 : 2, BJ == 4 ? 1 : 2)))
 void gemm_i8_dma_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, const int8_t* A,
                         uint64_t lda, const int8_t* Bt, uint64_t ldbt, int8_t* C, uint64_t ldc,
-                        uint32_t* Cu = nullptr, uint64_t wgt = 0) {
+                        uint32_t* Cu = nullptr, uint64_t wgt = 0,
+                        uint32_t fresh = 0) {
   // NW = 4 wavefronts as 2 x 2, or 8 as 2 x 4 (the workgroup tile twice as
   // wide); each wavefront a 128 x (32 BJ) sub-tile.
   // IKT = 64: rows of 64 bytes, four 16-byte chunks; IKT = 128: rows of
@@ -764,7 +771,8 @@ void gemm_i8_dma_kernel(const FieldK F, uint32_t M, uint32_t N, uint32_t K, cons
     const uint64_t pm = (0x80000000ull + F.p - 1) / F.p * F.p;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      split_rows<BJ>(Cu, ldc, wgt, acc[i], m0 + wm + 32 * i, n0 + wn, lane, M, N, pm, F);
+      split_rows<BJ>(Cu, ldc, wgt, acc[i], m0 + wm + 32 * i, n0 + wn, lane, M, N, pm, F,
+                     fresh);
     return;
   }
 #pragma unroll
@@ -1027,15 +1035,6 @@ __global__ __launch_bounds__(256) void digits_cols_kernel(const E* B, uint64_t l
   }
 }
 
-// C (M x N residues, row stride ldc) = 0.
-__global__ __launch_bounds__(256) void zero_rows_kernel(uint32_t* C, uint64_t ldc, uint32_t M,
-                                                        uint32_t N) {
-  const uint64_t total = (uint64_t)M * N;
-  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (uint64_t)gridDim.x * blockDim.x)
-    C[(e / N) * ldc + e % N] = 0u;
-}
-
 // C (M x N discrete-log codes, row stride ldc) = codes of Cu (dense residues).
 __global__ __launch_bounds__(256) void residues_to_codes_kernel(const FieldK F, const uint32_t* Cu,
                                                                 uint32_t M, uint32_t N,
@@ -1083,8 +1082,7 @@ fdot_status_t gemm_split(const fdot_field_s* f, size_t M, size_t N, size_t K, co
   }
   const uint64_t cells = (uint64_t)M * N;
   const unsigned zg = (unsigned)std::min<uint64_t>((cells + 255) / 256, 65536);
-  hipLaunchKernelGGL(zero_rows_kernel, dim3(zg), dim3(256), 0, s, (uint32_t*)C, (uint64_t)ldc,
-                     (uint32_t)M, (uint32_t)N);
+  // C is not cleared: the first launch (weight 256^0) writes every entry
   const uint64_t ag = std::min<uint64_t>(((uint64_t)M * (ldk / 4) + 255) / 256, 65536);
   const dim3 cg((unsigned)((N + 63) / 64), (unsigned)(ldk / 64));
   if (f64) {
@@ -1130,16 +1128,18 @@ fdot_status_t gemm_split(const fdot_field_s* f, size_t M, size_t N, size_t K, co
       const int8_t* Ai = Ad + (size_t)c * ldk;                    // digits c .. c+cnt-1 of A
       const int8_t* Bj = Bd + (size_t)(nd - 1 - (e - c)) * ldk;   // digits e-c .. down of B
       const uint32_t Kx = (uint32_t)cnt * ldk;
+      const uint32_t fresh = e == 0 && c == i_lo ? 1u : 0u;  // the first launch
       if (big) {
         const uint64_t tiles = ((M + 255) / 256) * ((N + 255) / 256);
         hipLaunchKernelGGL((gemm_i8_dma_kernel<2, 2, 8, true, 128>), dim3((unsigned)tiles), dim3(512),
                            lds, s, f->k, (uint32_t)M, (uint32_t)N, Kx, Ai, ld_all, Bj, ld_all,
-                           (int8_t*)nullptr, (uint64_t)ldc, (uint32_t*)C, w);
+                           (int8_t*)nullptr, (uint64_t)ldc, (uint32_t*)C, w, fresh);
       } else {
         const uint64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
         hipLaunchKernelGGL((gemm_i8_kernel<2, 2, 64, true, true>), dim3((unsigned)tiles),
                            dim3(256), 0, s, f->k, (uint32_t)M, (uint32_t)N, Kx, Ai, ld_all, Bj,
-                           ld_all, (int8_t*)nullptr, (uint64_t)ldc, 0xFFFFFFFFu, (uint32_t*)C, w);
+                           ld_all, (int8_t*)nullptr, (uint64_t)ldc, 0xFFFFFFFFu, (uint32_t*)C, w,
+                           fresh);
       }
       if (hipGetLastError() != hipSuccess) return FDOT_E_DEVICE;
     }
