@@ -323,7 +323,7 @@ def test_gemm_fp64_wave_layouts(waves):
 @pytest.mark.parametrize("p,rep", [(2147483647, "zpz"), (2147483647, "mont"), (4278124237, "zpz"),
                                    (2654435761, "mont"), (67108859, "fp64"), (67108859, "zpz"),
                                    (67108859, "mont"), (1048573, "fp64"), (65521, "zpz"),
-                                   (32749, "mont"), (32749, "zpz"), (251, "zpz"),
+                                   (32749, "mont"), (32749, "zpz"), (251, "zpz"), (251, "fp64"),
                                    (32749, "zech"), (65521, "zech"), (3, "zech")])
 @pytest.mark.parametrize("M,N,K,tiles", [(300, 260, 700, "auto"), (1030, 1100, 1000, "auto"),
                                          (1030, 1100, 1000, "large"), (40, 36, 131008, "auto")])
